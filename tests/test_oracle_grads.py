@@ -1,0 +1,122 @@
+"""Gradient pins of the oracle: torch-CPU float64 autograd and central differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ntc_oracle as O
+from paper_2305_17105_amd import synth
+
+
+def _setup(act="relu", n=512, seed=0):
+    g = O.make_geometry(64, 64, 5, 3, 4, 4, 2, Hd=16, act=act)
+    P = O.mlp_param_count(g.K, g.Hd, g.C)
+    rng = np.random.default_rng(seed)
+    params = rng.standard_normal(P) * 0.3
+    lat = rng.uniform(-0.4, 0.5, g.latent_count)
+    q = synth.random_queries(seed, n, g.M)
+    _, tgt = synth.target_chain(seed, 0, 64, 64, 5, g.M)
+    return g, params, lat, q, tgt
+
+
+@pytest.mark.parametrize("act", ["relu", "hardgelu"])
+def test_backward_matches_torch_autograd(act):
+    """An independent float64 torch forward (same gather record) differentiated by
+    autograd agrees with the oracle's analytic backward."""
+    g, params, lat, q, tgt = _setup(act)
+    L, gp, gl, _ = O.loss_and_grads(g, lat, params, q, tgt)
+    _, rec = O.sample_inputs(g, lat, q)
+    K, Hd, C, C0, C1 = g.K, g.Hd, g.C, g.C0, g.C1
+    tl = torch.tensor(lat, dtype=torch.float64, requires_grad=True)
+    tp = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    i0 = torch.tensor(rec["g0_idx"])
+    i1 = torch.tensor(rec["g1_idx"])
+    w1 = torch.tensor(rec["g1_w"])
+    parts = [tl[i0[:, k:k + 1] + torch.arange(C0)] for k in range(4)]
+    parts.append(sum(w1[:, k:k + 1] * tl[i1[:, k:k + 1] + torch.arange(C1)] for k in range(4)))
+    parts.append(torch.tensor(O.pos_enc(rec["ix"], rec["iy"])))
+    x = torch.cat(parts, dim=1)
+    o = 0
+    mats = []
+    for shape in ((K, Hd), (Hd,), (Hd, Hd), (Hd,), (Hd, C), (C,)):
+        size = int(np.prod(shape))
+        mats.append(tp[o:o + size].reshape(shape))
+        o += size
+    W1, b1, W2, b2, W3, b3 = mats
+
+    def a(z):
+        if act == "relu":
+            return torch.relu(z)
+        return torch.where(z < -1.5, torch.zeros_like(z), torch.where(z > 1.5, z, z * (z + 1.5) / 3))
+
+    y = a(a(x @ W1 + b1) @ W2 + b2) @ W3 + b3
+    tt = []
+    for s in range(len(q)):
+        l = int(rec["lod"][s])
+        base = g.mip_off[l] + (rec["iy"][s] * g.mip_w[l] + rec["ix"][s]) * C
+        tt.append(tgt[base:base + C])
+    t = torch.tensor(np.array(tt), dtype=torch.float64)
+    loss = ((y - t) ** 2).mean()
+    loss.backward()
+    assert L == pytest.approx(loss.item(), rel=1e-13)
+    assert np.allclose(gp, tp.grad.numpy(), rtol=1e-10, atol=1e-14)
+    assert np.allclose(gl, tl.grad.numpy(), rtol=1e-10, atol=1e-14)
+
+
+def test_backward_central_differences():
+    """Central differences, h = 1e-4, on 64 seeded parameters (latents and weights).
+    Entries whose +-h perturbation flips any ReLU decision are skipped."""
+    g, params, lat, q, tgt = _setup("relu", n=256, seed=5)
+    L0, gp, gl, _ = O.loss_and_grads(g, lat, params, q, tgt)
+    P = len(params)
+    # latents that are actually read by this batch, plus weights
+    _, rec = O.sample_inputs(g, lat, q)
+    used = np.unique(np.concatenate([(rec["g0_idx"][:, :, None] + np.arange(g.C0)).ravel(),
+                                     (rec["g1_idx"][:, :, None] + np.arange(g.C1)).ravel()]))
+    rng = np.random.default_rng(11)
+    pick_w = rng.choice(P, 32, replace=False)
+    pick_l = rng.choice(used, 32, replace=False)
+    h = 1e-4
+
+    def masks(p, l):
+        x, _ = O.sample_inputs(g, l, q)
+        _, (z1, _, z2, _) = O.mlp_forward(p, x, g.K, g.Hd, g.C)
+        return np.concatenate([(z1 > 0).ravel(), (z2 > 0).ravel()])
+
+    base = masks(params, lat)
+    checked = 0
+    for kind, idx in [("w", i) for i in pick_w] + [("l", i) for i in pick_l]:
+        vals = []
+        ok = True
+        for s in (+1, -1):
+            p2, l2 = params.copy(), lat.copy()
+            if kind == "w":
+                p2[idx] += s * h
+            else:
+                l2[idx] += s * h
+            if not np.array_equal(masks(p2, l2), base):
+                ok = False
+                break
+            vals.append(O.loss_and_grads(g, l2, p2, q, tgt)[0])
+        if not ok:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = gp[idx] if kind == "w" else gl[idx]
+        assert abs(fd - an) <= 1e-6 + 1e-5 * abs(an), (kind, idx, fd, an)
+        checked += 1
+    assert checked >= 48
+
+
+def test_latent_gradient_conservation():
+    """Sum of all latent gradients equals the sum over samples of the G0 slots plus the
+    G1 slots (bilinear weights sum to one)."""
+    g, params, lat, q, tgt = _setup("relu", n=300, seed=2)
+    _, gp, gl, y = O.loss_and_grads(g, lat, params, q, tgt)
+    x, rec = O.sample_inputs(g, lat, q)
+    _, (z1, _, z2, _) = O.mlp_forward(params, x, g.K, g.Hd, g.C)
+    W1, b1, W2, b2, W3, b3 = O.mlp_split(params, g.K, g.Hd, g.C)
+    t = O._targets_at(g, tgt, rec)
+    dy = 2 * (y - t) / y.size
+    dz2 = (dy @ W3.T) * (z2 > 0)
+    dz1 = (dz2 @ W2.T) * (z1 > 0)
+    dx = dz1 @ W1.T
+    assert gl.sum() == pytest.approx(dx[:, :4 * g.C0 + g.C1].sum(), rel=1e-10)

@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark of the neural texture compression hot path on one MI355X.
+
+Step = one training step (forward, L2 loss, backward into MLP and latents, dense
+Adam, clamp, next-step noise) of the full-size FP32-configuration material:
+2048x2048x12 with its box-filtered mip chain (12 mips, 5 feature levels of 4-bit
+latent grid pairs, G0 512x512x12 at level 0), MLP 72->64->64->12, 262,144 uniform
+random (u, v, LOD) samples per step, quantization noise on, learning rates
+0.01 / 0.005 with cosine annealing over the run.  `value` is train samples/s of
+the FP16 matrix-core path; the FP32 path on the same GPU, the decode throughput
+(4096x4096x16, 2/4-bit, MLP 92->64->64->16, 16M random queries per launch and a
+coherent full mip-0 pass), the reconstruction PSNR (Eq. 1) after the timed run,
+the roofline of the fused training kernel and the FP64 CPU oracle's throughput
+are reported beside it.  All inputs are seeded synthetic data resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_F16_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
+PEAK_F32_TFLOPS = 157.3    # MI355X FP32 matrix / vector peak
+PEAK_HBM_GBS = 8000.0
+
+TRAIN = dict(W=2048, C=12, c0=12, c1=12, b0=4, b1=4, hidden=64, n=262144, lr_lat=0.01, lr_mlp=0.005)
+DECODE = dict(W=4096, C=16, c0=16, c1=16, b0=2, b1=4, hidden=64)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def train_flops_per_sample(K, Hd, C, Klat):
+    """Algorithmic FLOPs of one training sample: forward 2(K Hd + Hd^2 + Hd C), input
+    gradient through layers 3, 2 and the latent slots of layer 1, and the three weight
+    gradients."""
+    fwd = 2 * (K * Hd + Hd * Hd + Hd * C)
+    bwd_x = 2 * (Hd * C + Hd * Hd + Klat * Hd)
+    bwd_w = 2 * (K * Hd + Hd * Hd + Hd * C)
+    return fwd + bwd_x + bwd_w
+
+
+def decode_flops_per_query(K, Hd, C):
+    return 2 * (K * Hd + Hd * Hd + Hd * C)
+
+
+class TrainBench:
+    def __init__(self, ntc, synth, torch, seed=0):
+        t = TRAIN
+        self.ntc, self.torch = ntc, torch
+        self.m = ntc.material_init(t["W"], t["W"], t["C"], t["c0"], t["c1"], t["b0"], t["b1"], t["hidden"])
+        m = self.m
+        log(f"[bench] train material: {t['W']}^2 x {t['C']}, {m.num_mips} mips, {m.num_levels} levels, "
+            f"{m.latent_count} latents, K={m.input_width}")
+        t0 = time.time()
+        self.mips, tflat = synth.target_chain(seed, 0, t["W"], t["W"], t["C"], m.num_mips)
+        self.targets = torch.from_numpy(tflat).cuda()
+        log(f"[bench] targets generated in {time.time() - t0:.1f}s")
+        raw = torch.from_numpy(synth.uniform_latents(seed, int(m.latent_count))).cuda()
+        packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        ntc.quantize_latents(m, raw, packed)
+        self.lat0 = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+        ntc.dequantize_latents(m, packed, self.lat0)
+        self.mlp0 = torch.from_numpy(synth.xavier_mlp(seed, m.input_width, t["hidden"], t["C"])).cuda()
+        self.pool = [torch.from_numpy(synth.random_queries(seed + 17 * i, t["n"], m.num_mips).view(np.uint8).copy())
+                     .cuda() for i in range(8)]
+        self.n = t["n"]
+
+    def run(self, precision, steps, warmup):
+        ntc, torch = self.ntc, self.torch
+        m, n = self.m, self.n
+        st = ntc.TrainState(m, self.lat0, self.mlp0, precision)
+        ws = torch.zeros(ntc.train_workspace_bytes(m, n, precision), dtype=torch.uint8, device="cuda")
+        total = warmup + steps
+
+        def hp(step):
+            c = 0.5 * (1.0 + math.cos(math.pi * step / total))
+            return ntc.hparams(lr_latent=TRAIN["lr_lat"] * c, lr_mlp=TRAIN["lr_mlp"] * c, step=step,
+                               precision=precision, noise=True, seed=1)
+
+        ntc.train_prepare(m, st, hp(0))
+        for s in range(warmup):
+            h = hp(s)
+            ntc.train_step(m, st, self.pool[s % 8], n, self.targets, h, ws)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s = warmup + i
+            h = hp(s)
+            ev[i][0].record()
+            ntc.train_gradients(m, st, self.pool[s % 8], n, self.targets, h, ws)
+            ev[i][1].record()
+            ntc.train_update(m, st, n, h, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fused_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        loss = float(st.loss.cpu()[0])
+        return dict(seconds=dt, ms_per_step=dt / steps * 1e3, samples_per_s=n * steps / dt, fused_ms=fused_ms,
+                    loss=loss, state=st)
+
+    def psnr(self, st):
+        """Eq. 1 over the full mip chain, decoding the quantized latents in FP32."""
+        ntc, torch = self.ntc, self.torch
+        from paper_2305_17105_amd import synth
+        m = self.m
+        packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        ntc.quantize_latents(m, st.latents, packed)
+        wp = torch.zeros(ntc.mlp_packed_bytes(m, ntc.F32), dtype=torch.uint8, device="cuda")
+        ntc.pack_mlp(m, st.mlp, ntc.F32, wp)
+        se = 0.0
+        count = 0
+        for l in range(m.num_mips):
+            q = synth.tile_queries(m.width, m.height, l)
+            qd = torch.from_numpy(q.view(np.uint8).copy()).cuda()
+            out = torch.empty(len(q) * m.channels, dtype=torch.float32, device="cuda")
+            ntc.decode(m, packed, wp, ntc.F32, qd, len(q), out, ntc.F32)
+            off = int(m.mip_offset[l])
+            ref = self.targets[off:off + out.numel()]
+            se += float(((out.double() - ref.double()) ** 2).sum())
+            count += out.numel()
+        return -10.0 * math.log10(se / count)
+
+
+def _unit_mlp(synth, K, Hd, C, seed=0):
+    p = synth.xavier_mlp(seed, K, Hd, C).astype(np.float64)
+    w3 = K * Hd + Hd + Hd * Hd + Hd
+    p[w3:w3 + Hd * C] *= 0.25
+    p[w3 + Hd * C:] = 0.5
+    return p.astype(np.float32)
+
+
+def run_decode(ntc, synth, torch, nq, reps, seed=0):
+    d = DECODE
+    m = ntc.material_init(d["W"], d["W"], d["C"], d["c0"], d["c1"], d["b0"], d["b1"], d["hidden"])
+    raw = torch.from_numpy(synth.uniform_latents(seed, int(m.latent_count))).cuda()
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    ntc.quantize_latents(m, raw, packed)
+    mlp = torch.from_numpy(_unit_mlp(synth, m.input_width, d["hidden"], d["C"], seed)).cuda()
+    q_rand = torch.from_numpy(synth.random_queries(seed + 5, nq, m.num_mips).view(np.uint8).copy()).cuda()
+    q_tile = torch.from_numpy(synth.tile_queries(d["W"], d["W"], 0).view(np.uint8).copy()).cuda()
+    n_tile = d["W"] * d["W"]
+    out = torch.empty(max(nq, n_tile) * d["C"], dtype=torch.float16, device="cuda")
+    res = {}
+    for name, prec in (("f16", ntc.F16), ("f32", ntc.F32)):
+        wp = torch.zeros(ntc.mlp_packed_bytes(m, prec), dtype=torch.uint8, device="cuda")
+        ntc.pack_mlp(m, mlp, prec, wp)
+        for kind, qd, n in (("random", q_rand, nq), ("coherent", q_tile, n_tile)):
+            for _ in range(2):
+                ntc.decode(m, packed, wp, prec, qd, n, out, ntc.F16)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                ntc.decode(m, packed, wp, prec, qd, n, out, ntc.F16)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            fl = decode_flops_per_query(m.input_width, d["hidden"], d["C"]) * n
+            res[f"{kind}_{name}"] = dict(queries=n, ms=round(ms, 4), texels_per_s=n / (ms * 1e-3),
+                                         tflops=fl / (ms * 1e-3) / 1e12)
+            log(f"[bench] decode {kind} {name}: {ms:.3f} ms for {n} queries -> {n / (ms * 1e-3):.3e} texels/s")
+    return res
+
+
+def cpu_baseline():
+    """FP64 oracle on the host: one training step of the same material, gradient part
+    on 32,768 of the 262,144 samples, dense per-latent part (noise, Adam, clamp) on all
+    latents; per-step time extrapolated linearly in the sample count."""
+    from oracle import ntc_oracle as O
+    from paper_2305_17105_amd import synth
+    t = TRAIN
+    g = O.make_geometry(t["W"], t["W"], t["C"], t["c0"], t["c1"], t["b0"], t["b1"], Hd=t["hidden"])
+    _, tflat = synth.target_chain(0, 0, t["W"], t["W"], t["C"], g.M)
+    lat = O.dequantize_packed(g, O.quantize_latents(g, synth.uniform_latents(0, g.latent_count)))
+    mlp = synth.xavier_mlp(0, g.K, t["hidden"], t["C"]).astype(np.float64)
+    ns = 32768
+    q = synth.random_queries(1, ns, g.M)
+    t0 = time.perf_counter()
+    fwd = lat + O.noise_values(g, 1, 0)
+    t1 = time.perf_counter()
+    _, gp, gl, _ = O.loss_and_grads(g, fwd, mlp, q, tflat)
+    t2 = time.perf_counter()
+    O.adam_update(mlp, gp, np.zeros_like(mlp), np.zeros_like(mlp), 1, 0.005)
+    p, _, _ = O.adam_update(lat, gl, np.zeros_like(lat), np.zeros_like(lat), 1, 0.01)
+    O.clamp_latents(g, p)
+    t3 = time.perf_counter()
+    dense = (t1 - t0) + (t3 - t2)
+    per_step = (t2 - t1) * (t["n"] / ns) + dense
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = 1
+    return dict(value=t["n"] / per_step, unit="samples/s", cores=int(cores), kind="oracle",
+                sample=f"one FP64 oracle training step on the full-size material: gradients of {ns} of the "
+                       f"{t['n']} samples ({t2 - t1:.2f}s) extrapolated x{t['n'] // ns}, plus the dense noise/Adam/"
+                       f"clamp pass over all {g.latent_count} latents ({dense:.2f}s)", extrapolated=True,
+                cpu=_cpu_model())
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--decode-queries", type=int, default=16 * 2 ** 20)
+    ap.add_argument("--decode-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-decode", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the method trains and decodes one material per GPU and this "
+              "build has no multi-GPU path (materials or query batches would be sharded across GPUs with no "
+              "exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_17105_amd import ntc, synth
+    torch.cuda.set_device(0)
+
+    tb = TrainBench(ntc, synth, torch)
+    log("[bench] FP32 training run")
+    r32 = tb.run(ntc.F32, args.steps, args.warmup)
+    log(f"[bench] f32: {r32['ms_per_step']:.3f} ms/step, fused {r32['fused_ms']:.3f} ms, loss {r32['loss']:.5f}")
+    psnr32 = tb.psnr(r32.pop("state"))
+    log("[bench] FP16 training run")
+    r16 = tb.run(ntc.F16, args.steps, args.warmup)
+    log(f"[bench] f16: {r16['ms_per_step']:.3f} ms/step, fused {r16['fused_ms']:.3f} ms, loss {r16['loss']:.5f}")
+    psnr16 = tb.psnr(r16.pop("state"))
+    log(f"[bench] PSNR after {args.warmup + args.steps} steps: f16 {psnr16:.2f} dB, f32 {psnr32:.2f} dB")
+
+    m = tb.m
+    fps = train_flops_per_sample(m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1)
+    ach = fps * tb.n / (r16["fused_ms"] * 1e-3) / 1e12
+    roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
+                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4), traffic=None,
+                flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4))
+    ach32 = fps * tb.n / (r32["fused_ms"] * 1e-3) / 1e12
+
+    decode = None
+    if not args.no_decode:
+        decode = run_decode(ntc, synth, torch, args.decode_queries, args.decode_reps)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host")
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": "decoded texels/s + train samples/s (fwd+bwd), FP16 MFMA vs FP32 at stated PSNR",
+        "value": round(r16["samples_per_s"], 1),
+        "unit": "train samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r16["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "train step, 2048x2048x12 + 12-mip chain, 5 levels of 4-bit 512^2/256^2 (level 0) "
+                               "latent grids, MLP 72-64-64-12, 262144 random (u,v,LOD) samples, noise on",
+                   "global_batch": tb.n, "parallelism": "single GPU"},
+        "psnr_db": {"f16": round(psnr16, 3), "f32": round(psnr32, 3), "steps_trained": args.warmup + args.steps},
+        "fp32": {"value": round(r32["samples_per_s"], 1), "unit": "train samples/s",
+                 "ms_per_step": round(r32["ms_per_step"], 4), "fused_ms": round(r32["fused_ms"], 4),
+                 "fused_tflops": round(ach32, 2), "fused_frac_of_fp32_peak": round(ach32 / PEAK_F32_TFLOPS, 4)},
+        "fused_ms_f16": round(r16["fused_ms"], 4),
+        "decode": decode,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * ntc.h — C ABI of the MI355X (gfx950) neural texture compression hot path.
+ *
+ * Method: Vaidyanathan et al., "Random-Access Neural Compression of Material
+ * Textures" (arXiv 2305.17105).  A texture set of W x H x C texels with its mip
+ * chain is represented by a pyramid of quantized latent grid pairs (section 4.1)
+ * and one small per-material MLP (section 4.4).  Decoding a texel samples the
+ * grids of the level that serves its mip (four G0 neighbours concatenated, G1
+ * bilinear; section 4.3.1), appends a tiled positional encoding (section 4.3.2)
+ * and runs the MLP, which outputs all C channels.  Training optimises latents and
+ * MLP jointly with L2 loss and Adam (section 4.5), with simulated quantization
+ * noise and a post-update clamp (section 4.2).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless marked (host).  All memory is owned and
+ *    allocated by the caller; no entry point allocates device memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously; nothing synchronises the host.
+ *  - Every argument is validated before anything is enqueued, so a call that
+ *    returns an error has no side effect.  Errors never abort the process;
+ *    ntc_last_error() gives a message for the calling thread.
+ *  - Per-element device data (query coordinates) is never an error: u, v are
+ *    clamped to the texture (NaN -> 0), lod is clamped to [0, num_mips-1].
+ *  - Calls on the same buffers from different streams are not synchronised
+ *    against each other; the caller orders them.
+ */
+#ifndef NTC_H
+#define NTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NTC_OK = 0,
+  NTC_E_INVALID = 1,      /* bad argument or descriptor */
+  NTC_E_UNSUPPORTED = 2,  /* valid, but no kernel is built for this shape */
+  NTC_E_WORKSPACE = 3,    /* workspace missing or too small */
+  NTC_E_HIP = 4           /* HIP runtime error (also asynchronous errors of earlier work) */
+} ntc_status;
+
+typedef enum { NTC_F32 = 0, NTC_F16 = 1, NTC_FP8_E4M3 = 2 } ntc_dtype;
+
+typedef enum { NTC_ACT_RELU = 0, NTC_ACT_HARDGELU = 1 } ntc_activation;
+
+/* One texel query: u, v in [0, 1) over the whole texture, integer mip level. 12 bytes. */
+typedef struct {
+  float u, v;
+  int32_t lod;
+} ntc_query;
+
+#define NTC_MAX_LEVELS 8
+#define NTC_MAX_MIPS 16
+
+/*
+ * Material descriptor (host struct, passed by pointer and copied by the callee).
+ * The caller sets the first block, then ntc_material_init() validates it and
+ * fills the derived geometry (section 4.1, Table 1):
+ *   level j: G0 = (W, H) >> (grid_shift + 2 j), G1 = G0 / 2; levels are added
+ *   while G1 has at least one cell and the mip chain still reaches them;
+ *   mip l is served by level clamp(floor((l - grid_shift) / 2), 0, J - 1).
+ * Buffer layouts fixed by the descriptor:
+ *   latents (FP32): for each level j ascending, G0^j then G1^j, each [h][w][c].
+ *   packed latents: same grid order, each grid a dense LSB-first bitstream of
+ *     B-bit codes in cell-major, channel-minor order, padded to 16 bytes; the
+ *     unpadded size is the paper's w*h*C*B/8 (Appendix 'Storage Cost').
+ *   MLP (FP32, canonical): W1[K][Hd], b1[Hd], W2[Hd][Hd], b2[Hd], W3[Hd][C], b3[C],
+ *     K = 4 c0 + c1 + 12 (section 4.4; the LOD input is not used).  Input order:
+ *     G0 neighbours (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1) each c0 wide, G1
+ *     bilinear (c1), positional encoding (x: sin/cos at 1, 2, 4 cycles per 8
+ *     texels, then y).
+ *   targets (FP32): mips 0..M-1 concatenated, each [H_l][W_l][C].
+ */
+typedef struct {
+  /* set by the caller */
+  int32_t width, height;   /* powers of two */
+  int32_t channels;        /* C, 1..16 */
+  int32_t num_mips;        /* M; 0 selects the full chain down to 1x1 */
+  int32_t c0, c1;          /* latent channels of G0 and G1 */
+  int32_t b0, b1;          /* bits per latent: 1, 2, 4 or 8 */
+  int32_t grid_shift;      /* G0 at level 0 is the texture size >> grid_shift (2: W/4) */
+  int32_t hidden;          /* Hd: 32 or 64 */
+  int32_t activation;      /* ntc_activation */
+  /* filled by ntc_material_init */
+  int32_t num_levels;
+  int32_t input_width;
+  int32_t mip_w[NTC_MAX_MIPS], mip_h[NTC_MAX_MIPS], level_of_mip[NTC_MAX_MIPS];
+  int32_t g0_w[NTC_MAX_LEVELS], g0_h[NTC_MAX_LEVELS];
+  int32_t g1_w[NTC_MAX_LEVELS], g1_h[NTC_MAX_LEVELS];
+  int64_t g0_offset[NTC_MAX_LEVELS], g1_offset[NTC_MAX_LEVELS]; /* floats, latent buffer */
+  int64_t g0_packed[NTC_MAX_LEVELS], g1_packed[NTC_MAX_LEVELS]; /* bytes, packed buffer */
+  int64_t mip_offset[NTC_MAX_MIPS];                             /* floats, target chain */
+  int64_t latent_count, packed_bytes, target_count, mlp_params;
+} ntc_material;
+
+const char* ntc_status_string(ntc_status s);
+/* Message describing the last failing call made by this thread ("" if none). */
+const char* ntc_last_error(void);
+
+/* Validate the caller fields of *m and fill the derived ones (host only, no GPU). */
+ntc_status ntc_material_init(ntc_material* m);
+
+/* Whether kernels are built for this material's (c0, c1, channels, hidden) and,
+ * for decode, its bit depths.  Host only. */
+int ntc_shape_supported(const ntc_material* m, int for_decode);
+
+/*
+ * Fixed-rate quantization of all latents (section 4.2): with N = 2^B levels and
+ * Q = 1/N, the value x becomes k = clamp(rint(x N), -N/2 + 1, N/2) (ties to
+ * even; x N is exact) and is stored as the code k + N/2 - 1 in B bits.  Zero is
+ * exact.  Non-finite inputs store the code of zero.  Bit-exact.
+ *   latents: m->latent_count floats.  packed: m->packed_bytes bytes (fully written,
+ *   padding zeroed).
+ */
+ntc_status ntc_quantize_latents(const ntc_material* m, const float* latents, uint8_t* packed,
+                                void* stream);
+
+/* Inverse of ntc_quantize_latents for the codes: code k -> (k - (N/2 - 1)) / N. */
+ntc_status ntc_dequantize_latents(const ntc_material* m, const uint8_t* packed, float* latents,
+                                  void* stream);
+
+/*
+ * Network weights for decoding.  ntc_pack_mlp converts the canonical FP32 MLP
+ * (m->mlp_params floats) into the library's matrix-core operand layout in the
+ * given compute precision (NTC_F32 or NTC_F16).  `packed` must hold
+ * ntc_mlp_packed_bytes(m, precision) bytes; its content is private to the
+ * library and valid only for the same material shape and precision.
+ */
+size_t ntc_mlp_packed_bytes(const ntc_material* m, ntc_dtype precision);
+ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype precision,
+                        void* packed, void* stream);
+
+/*
+ * Decode all C channels of n texels (sections 4.3-4.4) from the packed latents.
+ *   q: n queries.  out: n x C values, row-major, of out_dtype (NTC_F32 or NTC_F16).
+ *   precision: arithmetic of the MLP (NTC_F32: FP32 matrix cores; NTC_F16: FP16
+ *   inputs with FP32 accumulation); `mlp_packed` must come from ntc_pack_mlp with
+ *   the same precision.  n == 0 is a no-op.
+ */
+ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                      ntc_dtype precision, const ntc_query* q, int64_t n, void* out,
+                      ntc_dtype out_dtype, void* stream);
+
+/*
+ * Training (autodecoder, section 4; optimiser section 4.5 and section 5.1).
+ * State buffers (all caller-owned device memory):
+ *   latents      latent_count  FP32 masters
+ *   latents_fwd  latent_count  latents the next forward reads (masters + noise)
+ *   lat_m, lat_v latent_count  Adam moments
+ *   lat_grad     latent_count  gradient accumulator, zero between steps
+ *   mlp, mlp_m, mlp_v  mlp_params  canonical FP32 weights and Adam moments
+ *   mlp_packed   ntc_train_packed_bytes(m, precision) bytes, private layout
+ *   loss         1 float: mean squared error of the last step
+ *   loss_scale   1 float: dynamic loss scale (used by NTC_F16; set it once, e.g. 65536)
+ *   scale_state  2 int32: [0] consecutive good steps, [1] 1 if the last step was skipped
+ */
+typedef struct {
+  float* latents;
+  float* latents_fwd;
+  float* lat_m;
+  float* lat_v;
+  float* lat_grad;
+  float* mlp;
+  float* mlp_m;
+  float* mlp_v;
+  void* mlp_packed;
+  float* loss;
+  float* loss_scale;
+  int32_t* scale_state;
+} ntc_train_state;
+
+/* Host struct.  beta1/beta2/eps: Adam (0.9, 0.999, 1e-8).  step: 0-based index of
+ * this step (Adam uses t = step + 1; the noise of step s is a stateless hash of
+ * (noise_seed, s, latent index)).  precision: NTC_F32 or NTC_F16.  noise: add
+ * U(-Q/2, Q/2) to the forward latents.  freeze_latents: the quantize-and-freeze
+ * phase (latents neither noised nor updated).  scale_growth_interval: NTC_F16
+ * doubles the loss scale after this many good steps (halves it on overflow). */
+typedef struct {
+  float lr_latent, lr_mlp, beta1, beta2, eps;
+  uint64_t noise_seed;
+  int32_t step;
+  int32_t precision;
+  int32_t noise;
+  int32_t freeze_latents;
+  int32_t scale_growth_interval;
+} ntc_hparams;
+
+size_t ntc_train_packed_bytes(const ntc_material* m, ntc_dtype precision);
+/* Workspace for a training step of n samples on the current device. */
+size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision);
+
+/*
+ * Make the state consistent for step hp->step: latents_fwd = latents (+ that
+ * step's noise when hp->noise and not frozen), lat_grad = 0, mlp_packed from mlp.
+ * Call once before the first step and after changing latents or mlp directly.
+ */
+ntc_status ntc_train_prepare(const ntc_material* m, const ntc_train_state* s,
+                             const ntc_hparams* hp, void* stream);
+
+/*
+ * One training step on n samples: forward with latents_fwd, L2 loss against the
+ * targets at each query's texel, backward into the MLP and the latents,
+ * bias-corrected Adam on every parameter (dense), clamp of the latents to
+ * [-(N-1)/(2N), 1/2], then latents_fwd for step hp->step + 1.  If any gradient
+ * is not finite the update is skipped (scale_state[1] = 1; NTC_F16 halves the
+ * loss scale).  Leaves lat_grad zeroed.  workspace: ws_bytes >=
+ * ntc_train_workspace_bytes(m, n, precision).
+ */
+ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const ntc_query* q,
+                          int64_t n, const float* targets, const ntc_hparams* hp,
+                          void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * The two halves of ntc_train_step, for callers that time or overlap them, or
+ * accumulate gradients of several batches before one update:
+ *  ntc_train_gradients: forward, loss and backward of n samples (one fused kernel).
+ *    Latent gradients are added into s->lat_grad; per-block weight-gradient and
+ *    loss partials go to the workspace.
+ *  ntc_train_update: reduces the partials of the preceding ntc_train_gradients
+ *    call with the same (n, workspace), then Adam, clamp and the next forward
+ *    latents exactly as ntc_train_step.  n must equal the gradient call's n.
+ * ntc_train_step(...) == ntc_train_gradients(...) followed by ntc_train_update(...).
+ */
+ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, const ntc_query* q,
+                               int64_t n, const float* targets, const ntc_hparams* hp,
+                               void* workspace, size_t ws_bytes, void* stream);
+ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int64_t n,
+                            const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTC_H */

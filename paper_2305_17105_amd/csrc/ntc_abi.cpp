@@ -1,0 +1,404 @@
+// C ABI of the library: argument validation, geometry, workspace layout and the
+// launch sequence of each entry point.  No entry point allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "ntc_internal.h"
+
+namespace ntc {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+DevMat dev_mat(const ntc_material& m) {
+  DevMat d;
+  std::memset(&d, 0, sizeof d);
+  d.W = m.width; d.H = m.height; d.C = m.channels; d.M = m.num_mips;
+  d.C0 = m.c0; d.C1 = m.c1; d.B0 = m.b0; d.B1 = m.b1; d.shift = m.grid_shift;
+  d.Hd = m.hidden; d.act = m.activation; d.J = m.num_levels; d.K = m.input_width;
+  for (int l = 0; l < kMaxMips; ++l) {
+    d.mip_w[l] = m.mip_w[l]; d.mip_h[l] = m.mip_h[l]; d.level_of_mip[l] = m.level_of_mip[l];
+    d.mip_off[l] = m.mip_offset[l];
+  }
+  for (int j = 0; j < kMaxLevels; ++j) {
+    d.g0_w[j] = m.g0_w[j]; d.g0_h[j] = m.g0_h[j]; d.g1_w[j] = m.g1_w[j]; d.g1_h[j] = m.g1_h[j];
+    d.g0_off[j] = m.g0_offset[j]; d.g1_off[j] = m.g1_offset[j];
+    d.g0_pk[j] = m.g0_packed[j]; d.g1_pk[j] = m.g1_packed[j];
+    if (j < m.num_levels) {
+      d.g0_pk_end[j] = (m.g1_packed[j]) / 4 - 1;
+      const long long next = (j + 1 < m.num_levels) ? m.g0_packed[j + 1] : m.packed_bytes;
+      d.g1_pk_end[j] = next / 4 - 1;
+    }
+  }
+  d.latent_count = m.latent_count;
+  return d;
+}
+
+PeTable pe_table() {
+  PeTable p;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int i = 0; i < 8; ++i) {
+    const double t = (i + 0.5) / 8.0;
+    for (int f = 0; f < 3; ++f) {
+      const double a = two_pi * (double)(1 << f) * t;
+      p.v[i][2 * f] = (float)std::sin(a);
+      p.v[i][2 * f + 1] = (float)std::cos(a);
+    }
+  }
+  return p;
+}
+
+bool decode_shape_supported(int c0, int c1, int c, int hd, int b0, int b1);
+bool train_shape_supported(int c0, int c1, int c, int hd);
+
+}  // namespace ntc
+
+using namespace ntc;
+
+static long long grid_bytes(long long cells, int ch, int bits) {
+  const long long raw = (cells * ch * bits + 7) / 8;
+  return (raw + 15) / 16 * 16;
+}
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static ntc_status fail(ntc_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+static ntc_status hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return NTC_OK;
+  return fail(NTC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Re-check a descriptor the caller passes back (it must come from ntc_material_init).
+static ntc_status check_material(const ntc_material* m) {
+  if (!m) return fail(NTC_E_INVALID, "material is NULL");
+  ntc_material copy = *m;
+  if (ntc_material_init(&copy) != NTC_OK) return NTC_E_INVALID;
+  if (std::memcmp(&copy, m, sizeof copy) != 0)
+    return fail(NTC_E_INVALID, "material descriptor was modified after ntc_material_init");
+  return NTC_OK;
+}
+
+static long long mlp_params(int K, int Hd, int C) {
+  return (long long)K * Hd + Hd + (long long)Hd * Hd + Hd + (long long)Hd * C + C;
+}
+
+extern "C" {
+
+const char* ntc_status_string(ntc_status s) {
+  switch (s) {
+    case NTC_OK: return "ok";
+    case NTC_E_INVALID: return "invalid argument";
+    case NTC_E_UNSUPPORTED: return "unsupported shape";
+    case NTC_E_WORKSPACE: return "workspace too small";
+    case NTC_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* ntc_last_error(void) { return g_err.c_str(); }
+
+ntc_status ntc_material_init(ntc_material* m) {
+  if (!m) return fail(NTC_E_INVALID, "material is NULL");
+  if (!pow2(m->width) || !pow2(m->height) || m->width > 32768 || m->height > 32768)
+    return fail(NTC_E_INVALID, "width and height must be powers of two <= 32768");
+  if (m->channels < 1 || m->channels > 16) return fail(NTC_E_INVALID, "channels must be in 1..16");
+  if (m->c0 < 1 || m->c0 > 16 || m->c1 < 1 || m->c1 > 16) return fail(NTC_E_INVALID, "c0, c1 must be in 1..16");
+  auto okbits = [](int b) { return b == 1 || b == 2 || b == 4 || b == 8; };
+  if (!okbits(m->b0) || !okbits(m->b1)) return fail(NTC_E_INVALID, "b0, b1 must be 1, 2, 4 or 8");
+  if (m->grid_shift < 0 || m->grid_shift > 8) return fail(NTC_E_INVALID, "grid_shift must be in 0..8");
+  if (m->hidden != 16 && m->hidden != 32 && m->hidden != 48 && m->hidden != 64)
+    return fail(NTC_E_INVALID, "hidden must be 16, 32, 48 or 64");
+  if (m->activation != NTC_ACT_RELU && m->activation != NTC_ACT_HARDGELU)
+    return fail(NTC_E_INVALID, "unknown activation");
+  const int W = m->width, H = m->height, sh = m->grid_shift;
+  int full = 1;
+  while ((std::max(W, H) >> (full - 1)) > 1) ++full;
+  const int M = m->num_mips == 0 ? full : m->num_mips;
+  if (M < 1 || M > full || M > NTC_MAX_MIPS) return fail(NTC_E_INVALID, "num_mips out of range");
+  int jmax = 0;
+  while (jmax < 30 && (W >> (sh + 2 * jmax + 1)) >= 1 && (H >> (sh + 2 * jmax + 1)) >= 1) ++jmax;
+  if (jmax == 0) return fail(NTC_E_INVALID, "texture too small for grid_shift (G1 would be empty)");
+  const int raw_last = std::max(0, (M - 1 - sh) >= 0 ? (M - 1 - sh) / 2 : 0);
+  const int J = std::min(jmax, raw_last + 1);
+  if (J > NTC_MAX_LEVELS) return fail(NTC_E_INVALID, "too many feature levels");
+  m->num_mips = M;
+  m->num_levels = J;
+  m->input_width = 4 * m->c0 + m->c1 + 12;
+  std::memset(m->mip_w, 0, sizeof m->mip_w);
+  std::memset(m->mip_h, 0, sizeof m->mip_h);
+  std::memset(m->level_of_mip, 0, sizeof m->level_of_mip);
+  std::memset(m->mip_offset, 0, sizeof m->mip_offset);
+  long long toff = 0;
+  for (int l = 0; l < M; ++l) {
+    m->mip_w[l] = std::max(1, W >> l);
+    m->mip_h[l] = std::max(1, H >> l);
+    const int d = l - sh;
+    const int lv = d < 0 ? 0 : d / 2;
+    m->level_of_mip[l] = std::min(lv, J - 1);
+    m->mip_offset[l] = toff;
+    toff += (long long)m->mip_w[l] * m->mip_h[l] * m->channels;
+  }
+  m->target_count = toff;
+  std::memset(m->g0_w, 0, sizeof m->g0_w);
+  std::memset(m->g0_h, 0, sizeof m->g0_h);
+  std::memset(m->g1_w, 0, sizeof m->g1_w);
+  std::memset(m->g1_h, 0, sizeof m->g1_h);
+  std::memset(m->g0_offset, 0, sizeof m->g0_offset);
+  std::memset(m->g1_offset, 0, sizeof m->g1_offset);
+  std::memset(m->g0_packed, 0, sizeof m->g0_packed);
+  std::memset(m->g1_packed, 0, sizeof m->g1_packed);
+  long long off = 0, pk = 0;
+  for (int j = 0; j < J; ++j) {
+    const int w0 = W >> (sh + 2 * j), h0 = H >> (sh + 2 * j);
+    m->g0_w[j] = w0; m->g0_h[j] = h0; m->g1_w[j] = w0 / 2; m->g1_h[j] = h0 / 2;
+    m->g0_offset[j] = off;
+    m->g0_packed[j] = pk;
+    off += (long long)w0 * h0 * m->c0;
+    pk += grid_bytes((long long)w0 * h0, m->c0, m->b0);
+    m->g1_offset[j] = off;
+    m->g1_packed[j] = pk;
+    off += (long long)(w0 / 2) * (h0 / 2) * m->c1;
+    pk += grid_bytes((long long)(w0 / 2) * (h0 / 2), m->c1, m->b1);
+  }
+  if (off >= (1ll << 31)) return fail(NTC_E_INVALID, "latent count exceeds 2^31");
+  m->latent_count = off;
+  m->packed_bytes = pk;
+  m->mlp_params = mlp_params(m->input_width, m->hidden, m->channels);
+  return NTC_OK;
+}
+
+int ntc_shape_supported(const ntc_material* m, int for_decode) {
+  if (!m) return 0;
+  if (for_decode) return decode_shape_supported(m->c0, m->c1, m->channels, m->hidden, m->b0, m->b1) ? 1 : 0;
+  return train_shape_supported(m->c0, m->c1, m->channels, m->hidden) ? 1 : 0;
+}
+
+ntc_status ntc_quantize_latents(const ntc_material* m, const float* latents, uint8_t* packed, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (!latents || !packed) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_quantize(*m, latents, packed, (hipStream_t)stream), "ntc_quantize_latents");
+}
+
+ntc_status ntc_dequantize_latents(const ntc_material* m, const uint8_t* packed, float* latents, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (!latents || !packed) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_dequantize(*m, packed, latents, (hipStream_t)stream), "ntc_dequantize_latents");
+}
+
+static size_t round16(size_t b) { return (b + 15) / 16 * 16; }
+
+size_t ntc_mlp_packed_bytes(const ntc_material* m, ntc_dtype precision) {
+  if (!m || (precision != NTC_F32 && precision != NTC_F16)) return 0;
+  const bool f16 = precision == NTC_F16;
+  const PackGeom pg = pack_geom(m->c0, m->c1, m->hidden, f16);
+  const size_t w = round16((size_t)pg.fwd_end * (f16 ? 2 : 4));
+  return w + round16((size_t)(2 * m->hidden + m->channels) * 4);
+}
+
+size_t ntc_train_packed_bytes(const ntc_material* m, ntc_dtype precision) {
+  if (!m || (precision != NTC_F32 && precision != NTC_F16)) return 0;
+  const bool f16 = precision == NTC_F16;
+  const PackGeom pg = pack_geom(m->c0, m->c1, m->hidden, f16);
+  return round16((size_t)pg.train_end * (f16 ? 2 : 4));
+}
+
+ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype precision, void* packed, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "pack precision must be F32 or F16");
+  if (!mlp || !packed) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_pack_mlp(*m, mlp, precision == NTC_F16, false, packed, (hipStream_t)stream), "ntc_pack_mlp");
+}
+
+ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                      ntc_dtype precision, const ntc_query* q, int64_t n, void* out, ntc_dtype out_dtype,
+                      void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "decode precision must be F32 or F16");
+  if (out_dtype != NTC_F32 && out_dtype != NTC_F16) return fail(NTC_E_UNSUPPORTED, "output dtype must be F32 or F16");
+  if (n < 0) return fail(NTC_E_INVALID, "n < 0");
+  if (!decode_shape_supported(m->c0, m->c1, m->channels, m->hidden, m->b0, m->b1))
+    return fail(NTC_E_UNSUPPORTED, "no decode kernel for this (c0, c1, channels, hidden, b0, b1)");
+  if (n == 0) return NTC_OK;
+  if (!packed_latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_decode(*m, packed_latents, mlp_packed, precision == NTC_F16, q, n, out,
+                                  out_dtype == NTC_F16, (hipStream_t)stream), "ntc_decode");
+}
+
+// Workspace of a training step: per-block weight-gradient partials, per-block loss
+// partials, the reduced weight gradient.
+struct WsLayout {
+  size_t part_dw, part_loss, grad, total;
+};
+static WsLayout ws_layout(const ntc_material* m, int grid) {
+  WsLayout w;
+  const size_t P = (size_t)m->mlp_params;
+  w.part_dw = 0;
+  w.part_loss = round16((size_t)grid * P * 4);
+  w.grad = w.part_loss + round16((size_t)grid * 4);
+  w.total = w.grad + round16(P * 4);
+  return w;
+}
+
+size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
+  if (!m || n <= 0 || (precision != NTC_F32 && precision != NTC_F16)) return 0;
+  return ws_layout(m, train_grid(*m, precision == NTC_F16, n)).total;
+}
+
+static ntc_status check_state(const ntc_train_state* s, bool f16) {
+  if (!s) return fail(NTC_E_INVALID, "state is NULL");
+  if (!s->latents || !s->latents_fwd || !s->lat_m || !s->lat_v || !s->lat_grad || !s->mlp || !s->mlp_m ||
+      !s->mlp_v || !s->mlp_packed || !s->loss || !s->scale_state)
+    return fail(NTC_E_INVALID, "NULL state buffer");
+  if (f16 && !s->loss_scale) return fail(NTC_E_INVALID, "loss_scale is required for F16 training");
+  return NTC_OK;
+}
+
+static ntc_status check_hparams(const ntc_hparams* hp) {
+  if (!hp) return fail(NTC_E_INVALID, "hparams is NULL");
+  if (hp->precision != NTC_F32 && hp->precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  if (hp->step < 0) return fail(NTC_E_INVALID, "step < 0");
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f && hp->eps > 0.f))
+    return fail(NTC_E_INVALID, "bad Adam constants");
+  if (!std::isfinite(hp->lr_latent) || !std::isfinite(hp->lr_mlp)) return fail(NTC_E_INVALID, "bad learning rate");
+  return NTC_OK;
+}
+
+ntc_status ntc_train_prepare(const ntc_material* m, const ntc_train_state* s, const ntc_hparams* hp, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if ((st = check_hparams(hp)) != NTC_OK) return st;
+  const bool f16 = hp->precision == NTC_F16;
+  if ((st = check_state(s, f16)) != NTC_OK) return st;
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no training kernel for this (c0, c1, channels, hidden)");
+  hipStream_t hs = (hipStream_t)stream;
+  const bool noise = hp->noise && !hp->freeze_latents;
+  hipError_t e = launch_prepare(*m, s->latents, s->latents_fwd, s->lat_grad, noise_key(hp->noise_seed, hp->step),
+                                noise ? 1 : 0, hs);
+  if (e == hipSuccess) e = launch_pack_mlp(*m, s->mlp, f16, true, s->mlp_packed, hs);
+  return hip_status(e, "ntc_train_prepare");
+}
+
+static ntc_status check_train(const ntc_material* m, const ntc_train_state* s, const ntc_hparams* hp, int64_t n) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if ((st = check_hparams(hp)) != NTC_OK) return st;
+  if ((st = check_state(s, hp->precision == NTC_F16)) != NTC_OK) return st;
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no training kernel for this (c0, c1, channels, hidden)");
+  if (n <= 0) return fail(NTC_E_INVALID, "n must be positive");
+  return NTC_OK;
+}
+
+ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
+                               const float* targets, const ntc_hparams* hp, void* workspace, size_t ws_bytes,
+                               void* stream) {
+  ntc_status st = check_train(m, s, hp, n);
+  if (st != NTC_OK) return st;
+  if (!q || !targets) return fail(NTC_E_INVALID, "NULL queries or targets");
+  const bool f16 = hp->precision == NTC_F16;
+  const int grid = train_grid(*m, f16, n);
+  const WsLayout wl = ws_layout(m, grid);
+  if (!workspace || ws_bytes < wl.total) return fail(NTC_E_WORKSPACE, "workspace too small");
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_status(e, "ntc_train_gradients (earlier asynchronous error)");
+  char* ws = (char*)workspace;
+  TrainLaunch a;
+  a.lat_fwd = s->latents_fwd;
+  a.wpack = s->mlp_packed;
+  a.mlp = s->mlp;
+  a.q = q;
+  a.n = n;
+  a.targets = targets;
+  a.lat_grad = s->lat_grad;
+  a.part_dw = (float*)(ws + wl.part_dw);
+  a.part_loss = (float*)(ws + wl.part_loss);
+  a.loss_scale = f16 ? s->loss_scale : nullptr;
+  a.scale_slot = hp->step & 1;
+  a.overflow_flag = s->scale_state + 1;
+  a.scatter_latents = !hp->freeze_latents;
+  a.grid = grid;
+  return hip_status(launch_train_fused(*m, f16, a, (hipStream_t)stream), "ntc_train_gradients");
+}
+
+ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int64_t n, const ntc_hparams* hp,
+                            void* workspace, size_t ws_bytes, void* stream) {
+  ntc_status st = check_train(m, s, hp, n);
+  if (st != NTC_OK) return st;
+  const bool f16 = hp->precision == NTC_F16;
+  const int grid = train_grid(*m, f16, n);
+  const WsLayout wl = ws_layout(m, grid);
+  if (!workspace || ws_bytes < wl.total) return fail(NTC_E_WORKSPACE, "workspace too small");
+  hipStream_t hs = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  hipError_t e = launch_reduce(*m, grid, (const float*)(ws + wl.part_dw), (const float*)(ws + wl.part_loss),
+                               (float*)(ws + wl.grad), s->loss, 1.0f / (float)((double)n * m->channels),
+                               s->scale_state + 1, hs);
+  if (e == hipSuccess) {
+    AdamLaunch ad;
+    ad.latents = s->latents;
+    ad.latents_fwd = s->latents_fwd;
+    ad.lat_m = s->lat_m;
+    ad.lat_v = s->lat_v;
+    ad.lat_grad = s->lat_grad;
+    ad.mlp = s->mlp;
+    ad.mlp_m = s->mlp_m;
+    ad.mlp_v = s->mlp_v;
+    ad.mlp_grad = (const float*)(ws + wl.grad);
+    ad.wpack = s->mlp_packed;
+    ad.loss_scale = f16 ? s->loss_scale : nullptr;
+    ad.scale_state = s->scale_state;
+    ad.lr_lat = hp->lr_latent;
+    ad.lr_mlp = hp->lr_mlp;
+    ad.beta1 = hp->beta1;
+    ad.beta2 = hp->beta2;
+    ad.eps = hp->eps;
+    const double t = (double)hp->step + 1.0;
+    ad.bc1 = (float)(1.0 - std::pow((double)hp->beta1, t));
+    ad.bc2 = (float)(1.0 - std::pow((double)hp->beta2, t));
+    ad.next_key = noise_key(hp->noise_seed, hp->step + 1);
+    ad.step = hp->step;
+    ad.noise = hp->noise ? 1 : 0;
+    ad.freeze = hp->freeze_latents ? 1 : 0;
+    ad.growth = hp->scale_growth_interval > 0 ? hp->scale_growth_interval : 2000;
+    ad.f16 = f16 ? 1 : 0;
+    e = launch_adam(*m, ad, hs);
+  }
+  return hip_status(e, "ntc_train_update");
+}
+
+ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
+                          const float* targets, const ntc_hparams* hp, void* workspace, size_t ws_bytes,
+                          void* stream) {
+  ntc_status st = ntc_train_gradients(m, s, q, n, targets, hp, workspace, ws_bytes, stream);
+  if (st != NTC_OK) return st;
+  return ntc_train_update(m, s, n, hp, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Device-side building blocks shared by the decode and training kernels (gfx950).
+//
+// Matrix-core convention used throughout (verified lane layouts of gfx950 MFMA):
+//   v_mfma_f32_16x16x{4f32,16f16,32_f16}: lane l = 16*g + r (g = l/16, r = l%16)
+//   A operand: A[r][KW*g + j], B operand: B[KW*g + j][r], D: D[4*g + i][r], i = 0..3,
+//   with KW = 1, 4, 8 values per lane respectively.
+// Layers are evaluated as Z^T (features x texels) = W^T (features x inputs) * X^T:
+// the 16 texels of a tile sit on r, so each lane group g carries a quarter of one
+// texel's features ("slots").  A layer's D fragment (rows 16m + 4g + i) becomes
+// the next layer's B fragment without any data movement: slot t of group g holds
+// feature phi(g, t) = 16*(t/4) + 4*g + t%4, and the weight rows are permuted to
+// match when the weights are packed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ntc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxMips = 16;
+
+// Geometry as the kernels see it (filled on the host from ntc_material).
+struct DevMat {
+  int W, H, C, M, C0, C1, B0, B1, shift, Hd, act, J, K;
+  int mip_w[kMaxMips], mip_h[kMaxMips], level_of_mip[kMaxMips];
+  int g0_w[kMaxLevels], g0_h[kMaxLevels], g1_w[kMaxLevels], g1_h[kMaxLevels];
+  long long g0_off[kMaxLevels], g1_off[kMaxLevels];
+  long long g0_pk[kMaxLevels], g1_pk[kMaxLevels];
+  long long g0_pk_end[kMaxLevels], g1_pk_end[kMaxLevels];
+  long long mip_off[kMaxMips];
+  long long latent_count;
+};
+
+// Positional-encoding table: pe[m][q] for texel position m = i mod 8 inside the
+// 8-texel tile and value q = (sin, cos) x (1, 2, 4 cycles per tile) (section 4.3.2).
+struct PeTable {
+  float v[8][6];
+};
+
+// ------------------------------------------------------------------ slot maps
+__host__ __device__ constexpr int hid_feature(int g, int t) { return 16 * (t / 4) + 4 * g + (t % 4); }
+
+// Input slots of a lane group g for latent widths C0, C1 (same positions in
+// every group, so slot indices are compile-time constants):
+//   t <  C0                 : G0 neighbour g, channel t
+//   C0 <= t < T_lat         : G1 channel g + 4 (t - C0) (padding if >= C1)
+//   T_lat <= t < T_lat + 3  : positional-encoding values 3g .. 3g+2
+//   beyond                  : zero padding
+template <int C0, int C1>
+struct InSlots {
+  static constexpr int n1max = (C1 + 3) / 4;
+  static constexpr int T_lat = C0 + n1max;
+  static constexpr int T_used = T_lat + 3;
+  static constexpr int K = 4 * C0 + C1 + 12;
+  // canonical input feature of slot (g, t); -1 for padding
+  static constexpr int psi(int g, int t) {
+    return t < C0 ? g * C0 + t
+         : t < T_lat ? (g + 4 * (t - C0) < C1 ? 4 * C0 + g + 4 * (t - C0) : -1)
+         : t < T_used ? 4 * C0 + C1 + 3 * g + (t - T_lat)
+         : -1;
+  }
+};
+
+// Sizes of the operand packs of one material (elements of the compute type).
+struct PackGeom {
+  int S1, SH, MT, ML, T_lat, T_used;
+  long long L1, L2, L3, B3, B2, B1;  // element offsets
+  long long fwd_end, train_end;      // end of forward packs, end of all packs
+};
+__host__ __device__ constexpr PackGeom pack_geom(int c0, int c1, int hd, bool f16) {
+  PackGeom p{};
+  p.T_lat = c0 + (c1 + 3) / 4;
+  p.T_used = p.T_lat + 3;
+  p.S1 = f16 ? (p.T_used + 3) / 4 * 4 : p.T_used;
+  p.SH = hd / 4;
+  p.MT = hd / 16;
+  p.ML = (p.T_lat + 3) / 4;
+  p.L1 = 0;
+  p.L2 = p.L1 + (long long)p.MT * p.S1 * 64;
+  p.L3 = p.L2 + (long long)p.MT * p.SH * 64;
+  p.B3 = p.L3 + (long long)p.SH * 64;
+  p.fwd_end = p.B3;
+  p.B2 = p.B3 + (long long)p.MT * 4 * 64;
+  p.B1 = p.B2 + (long long)p.MT * p.SH * 64;
+  p.train_end = p.B1 + (long long)p.ML * p.SH * 64;
+  return p;
+}
+
+// Runtime inverse slot maps (used where canonical weights are scattered into packs).
+__host__ __device__ inline void in_slot_of(int k, int c0, int c1, int& g, int& t) {
+  const int tl = c0 + (c1 + 3) / 4;
+  if (k < 4 * c0) { g = k / c0; t = k % c0; }
+  else if (k < 4 * c0 + c1) { const int ch = k - 4 * c0; g = ch % 4; t = c0 + ch / 4; }
+  else { const int p = k - 4 * c0 - c1; g = p / 3; t = tl + p % 3; }
+}
+__host__ __device__ inline void hid_slot_of(int h, int& g, int& t) { g = (h / 4) % 4; t = 4 * (h / 16) + h % 4; }
+
+// ------------------------------------------------------------------ operand packs
+// A pack holds, for every M-tile mo and every slot t of the K dimension, the 64
+// lane values of the A operand.  Values of one lane that feed one MFMA are
+// contiguous: FP32 -> 1 value per MFMA (16x16x4); FP16 -> groups of 8 slots
+// (16x16x32) and a trailing group of 4 (16x16x16).
+template <typename T>
+__host__ __device__ inline int pack_index(int S, int mo, int t, int lane);
+
+template <>
+__host__ __device__ inline int pack_index<float>(int S, int mo, int t, int lane) {
+  return (mo * S + t) * 64 + lane;
+}
+template <>
+__host__ __device__ inline int pack_index<_Float16>(int S, int mo, int t, int lane) {
+  const int s8 = S / 8 * 8;
+  const int base = mo * S * 64;
+  if (t < s8) return base + (t / 8) * 512 + lane * 8 + (t % 8);
+  return base + s8 * 64 + lane * 4 + (t - s8);
+}
+
+// acc += A(tile) * B over S slots; `a` points at the tile's pack (mo already applied).
+template <int S>
+__device__ inline f32x4 mma_slots(f32x4 acc, const float* __restrict__ a, const float (&b)[S], int lane) {
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t * 64 + lane], b[t], acc, 0, 0, 0);
+  return acc;
+}
+template <int S>
+__device__ inline f32x4 mma_slots(f32x4 acc, const _Float16* __restrict__ a, const _Float16 (&b)[S], int lane) {
+  static_assert(S % 4 == 0, "fp16 slot counts are multiples of 4");
+  constexpr int S8 = S / 8 * 8;
+#pragma unroll
+  for (int t = 0; t < S8; t += 8) {
+    const f16x8 av = *reinterpret_cast<const f16x8*>(a + t * 64 + lane * 8);
+    f16x8 bv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = b[t + j];
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
+  }
+  if constexpr (S8 < S) {
+    // The 16x16x16 tail gets its own zero accumulator and is added on the VALU:
+    // chaining a 16x16x32 and a 16x16x16 MFMA back-to-back through the
+    // accumulator operand returns wrong sums on gfx950 with ROCm 7.2 (the
+    // compiler inserts no wait states between the two shapes).
+    const f16x4 av = *reinterpret_cast<const f16x4*>(a + S8 * 64 + lane * 4);
+    f16x4 bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = b[S8 + j];
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 tail = __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, zero, 0, 0, 0);
+    acc += tail;
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------ activations (section 4.4)
+__device__ inline float act_fn(float z, int act) {
+  if (act == 0) return fmaxf(z, 0.f);
+  return z < -1.5f ? 0.f : (z > 1.5f ? z : z * (z + 1.5f) * (1.f / 3.f));
+}
+__device__ inline float act_grad(float z, int act) {
+  if (act == 0) return z > 0.f ? 1.f : 0.f;
+  return z < -1.5f ? 0.f : (z > 1.5f ? 1.f : (2.f * z + 1.5f) * (1.f / 3.f));
+}
+
+// ------------------------------------------------------------------ sampling (section 4.3)
+__device__ inline int snap_texel(float u, int size) {
+  float p = u * (float)size;
+  p = (p == p) ? p : 0.f;  // NaN -> 0
+  p = fminf(fmaxf(p, 0.f), (float)(size - 1));
+  return (int)floorf(p);
+}
+
+// Everything one lane needs to fetch its share of a texel's inputs.
+struct Footprint {
+  int l, j, ix, iy;
+  int g0_cell;      // G0 cell index (within the level's grid) of this lane group's neighbour
+  int g1_cell[4];   // G1 tap cells, order (x,y), (x+1,y), (x,y+1), (x+1,y+1)
+  float g1_w[4];    // bilinear weights of the taps
+};
+
+__device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, int g) {
+  Footprint f;
+  const int l = min(max(lod, 0), m.M - 1);
+  const int Wl = max(1, m.W >> l), Hl = max(1, m.H >> l);
+  const int j = min(max((l - m.shift) >> 1, 0), m.J - 1);
+  const int w0 = m.W >> (m.shift + 2 * j), h0 = m.H >> (m.shift + 2 * j);
+  const int w1 = w0 >> 1, h1 = h0 >> 1;
+  f.l = l;
+  f.j = j;
+  f.ix = snap_texel(u, Wl);
+  f.iy = snap_texel(v, Hl);
+  // texel centre in grid units; every factor is a power of two, so this is exact
+  const float cx = (float)f.ix + 0.5f, cy = (float)f.iy + 0.5f;
+  {
+    const float gx = cx * ((float)w0 / (float)Wl) - 0.5f;
+    const float gy = cy * ((float)h0 / (float)Hl) - 0.5f;
+    const int x0 = (int)floorf(gx), y0 = (int)floorf(gy);
+    const int xx = min(max(x0 + (g & 1), 0), w0 - 1);
+    const int yy = min(max(y0 + (g >> 1), 0), h0 - 1);
+    f.g0_cell = yy * w0 + xx;
+  }
+  {
+    const float gx = cx * ((float)w1 / (float)Wl) - 0.5f;
+    const float gy = cy * ((float)h1 / (float)Hl) - 0.5f;
+    const float fx0 = floorf(gx), fy0 = floorf(gy);
+    const float fx = gx - fx0, fy = gy - fy0;
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const int xa = min(max(x0, 0), w1 - 1), xb = min(max(x0 + 1, 0), w1 - 1);
+    const int ya = min(max(y0, 0), h1 - 1), yb = min(max(y0 + 1, 0), h1 - 1);
+    f.g1_cell[0] = ya * w1 + xa;
+    f.g1_cell[1] = ya * w1 + xb;
+    f.g1_cell[2] = yb * w1 + xa;
+    f.g1_cell[3] = yb * w1 + xb;
+    f.g1_w[0] = (1.f - fx) * (1.f - fy);
+    f.g1_w[1] = fx * (1.f - fy);
+    f.g1_w[2] = (1.f - fx) * fy;
+    f.g1_w[3] = fx * fy;
+  }
+  return f;
+}
+
+// The three positional-encoding values of lane group g (slots 3g..3g+2 of the 12).
+__device__ inline void pe_values(const float* pe_lds, int ix, int iy, int g, float out[3]) {
+  const int mpos = (g >> 1) ? (iy & 7) : (ix & 7);
+  const int q0 = 3 * (g & 1);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) out[s] = pe_lds[mpos * 6 + q0 + s];
+}
+
+// ------------------------------------------------------------------ bit-packed codes (section 4.2)
+// Window of NW+1 dwords covering `nbits` bits starting at absolute bit `bit0` of a
+// packed grid, realigned so that result bit 0 is `bit0`.  Dword reads are clamped to
+// the grid's last dword so they never leave the grid.
+template <int NW, bool ALIGNED>
+__device__ inline void load_bits(const uint32_t* __restrict__ base, long long bit0, long long last_dword,
+                                 uint32_t (&out)[NW]) {
+  const long long d0 = bit0 >> 5;
+  if constexpr (ALIGNED) {  // bit0 is a multiple of 32 and the window ends inside the grid
+#pragma unroll
+    for (int k = 0; k < NW; ++k) out[k] = base[d0 + k];
+  } else {
+    const int s = (int)(bit0 & 31);
+    uint32_t w[NW + 1];
+#pragma unroll
+    for (int k = 0; k <= NW; ++k) w[k] = base[min(d0 + k, last_dword)];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) out[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
+  }
+}
+
+template <int B, int NW>
+__device__ inline int code_at(const uint32_t (&win)[NW], int c) {
+  constexpr uint32_t mask = (1u << B) - 1u;
+  const int p = c * B;
+  return (int)((win[p >> 5] >> (p & 31)) & mask);
+}
+
+// Same with a run-time channel index (selects the window word without dynamic indexing).
+template <int B, int NW>
+__device__ inline int code_at_dyn(const uint32_t (&win)[NW], int c) {
+  constexpr uint32_t mask = (1u << B) - 1u;
+  const int p = c * B;
+  const int k = p >> 5;
+  uint32_t w = win[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) w = (k == i) ? win[i] : w;
+  return (int)((w >> (p & 31)) & mask);
+}
+
+template <int B>
+__device__ inline float dequant(int code) {
+  constexpr int N = 1 << B;
+  return (float)(code - (N / 2 - 1)) * (1.f / (float)N);
+}
+
+// ------------------------------------------------------------------ counter noise (section 4.2)
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+__host__ __device__ inline uint64_t noise_key(uint64_t seed, int step) {
+  return mix64(seed + kGamma * (uint64_t)(step + 1));
+}
+// U[-Q/2, Q/2) with Q = 2^-bits, 24-bit resolution; exact in FP32.
+__device__ inline float noise_at(uint64_t key, long long i, int bits) {
+  const uint64_t r = mix64(key + kGamma * (uint64_t)(i + 1));
+  const int r24 = (int)(r >> 40);
+  return (float)(r24 - (1 << 23)) * ldexpf(1.f, -24 - bits);
+}
+
+// ------------------------------------------------------------------ weight scatter into packs
+// Canonical FP32 parameter p (layout W1[K][Hd], b1, W2[Hd][Hd], b2, W3[Hd][C], b3)
+// is written to its place in the forward packs and, when `bwd`, in the backward
+// packs (weights only; biases are read from the canonical buffer).
+template <typename T>
+__device__ inline void scatter_param(T* __restrict__ pack, const PackGeom& pg, int c0, int c1, int C, int Hd,
+                                     long long p, float value, bool bwd) {
+  const long long K = 4 * c0 + c1 + 12;
+  const long long nW1 = K * Hd, nW2 = (long long)Hd * Hd, nW3 = (long long)Hd * C;
+  const T v = (T)value;
+  if (p < nW1) {
+    const int k = (int)(p / Hd), h = (int)(p % Hd);
+    int g, t;
+    in_slot_of(k, c0, c1, g, t);
+    pack[pg.L1 + pack_index<T>(pg.S1, h / 16, t, 16 * g + h % 16)] = v;
+    if (bwd && t < pg.T_lat) {
+      int g2, t2;
+      hid_slot_of(h, g2, t2);
+      pack[pg.B1 + pack_index<T>(pg.SH, t / 4, t2, 16 * g2 + 4 * g + t % 4)] = v;
+    }
+    return;
+  }
+  p -= nW1 + Hd;
+  if (p >= 0 && p < nW2) {
+    const int h1 = (int)(p / Hd), h2 = (int)(p % Hd);
+    int g, t;
+    hid_slot_of(h1, g, t);
+    pack[pg.L2 + pack_index<T>(pg.SH, h2 / 16, t, 16 * g + h2 % 16)] = v;
+    if (bwd) {
+      int g2, t2;
+      hid_slot_of(h2, g2, t2);
+      pack[pg.B2 + pack_index<T>(pg.SH, h1 / 16, t2, 16 * g2 + h1 % 16)] = v;
+    }
+    return;
+  }
+  p -= nW2 + Hd;
+  if (p >= 0 && p < nW3) {
+    const int h = (int)(p / C), c = (int)(p % C);
+    int g, t;
+    hid_slot_of(h, g, t);
+    pack[pg.L3 + pack_index<T>(pg.SH, 0, t, 16 * g + c)] = v;
+    if (bwd) pack[pg.B3 + pack_index<T>(4, h / 16, c % 4, 16 * (c / 4) + h % 16)] = v;
+  }
+}
+
+}  // namespace ntc

@@ -1,0 +1,73 @@
+// Host-side internals shared by the C ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/ntc.h"
+#include "ntc_device.h"
+
+namespace ntc {
+
+// Thread-local error message for ntc_last_error().
+void set_error(const std::string& msg);
+
+// ntc_material (validated) -> kernel view.
+DevMat dev_mat(const ntc_material& m);
+PeTable pe_table();
+
+// Number of CUs of the current device (cached per device).
+int device_cus();
+
+// Launchers: return hipSuccess or the launch error.  Shapes are validated by the caller.
+hipError_t launch_quantize(const ntc_material& m, const float* lat, uint8_t* packed, hipStream_t s);
+hipError_t launch_dequantize(const ntc_material& m, const uint8_t* packed, float* lat, hipStream_t s);
+// Scatter canonical FP32 weights into operand packs (forward only, or forward + backward).
+hipError_t launch_pack_mlp(const ntc_material& m, const float* mlp, bool f16, bool with_backward,
+                           void* packed, hipStream_t s);
+hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const void* wpack, bool f16,
+                         const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s);
+
+struct TrainLaunch {
+  const float* lat_fwd;
+  const void* wpack;
+  const float* mlp;
+  const ntc_query* q;
+  long long n;
+  const float* targets;
+  float* lat_grad;
+  float* part_dw;     // [grid][P]
+  float* part_loss;   // [grid]
+  const float* loss_scale;  // device, 2 entries, or nullptr (scale 1)
+  int scale_slot;
+  int32_t* overflow_flag;   // reset by block 0
+  bool scatter_latents;
+  int grid;
+};
+hipError_t launch_train_fused(const ntc_material& m, bool f16, const TrainLaunch& a, hipStream_t s);
+int train_grid(const ntc_material& m, bool f16, long long n);
+hipError_t launch_reduce(const ntc_material& m, int grid, const float* part_dw, const float* part_loss,
+                         float* grad, float* loss_out, float loss_norm, int32_t* overflow_flag, hipStream_t s);
+
+struct AdamLaunch {
+  float* latents;
+  float* latents_fwd;
+  float* lat_m;
+  float* lat_v;
+  float* lat_grad;
+  float* mlp;
+  float* mlp_m;
+  float* mlp_v;
+  const float* mlp_grad;
+  void* wpack;
+  float* loss_scale;   // 2 entries or nullptr
+  int32_t* scale_state;
+  float lr_lat, lr_mlp, beta1, beta2, eps, bc1, bc2;
+  uint64_t next_key;   // noise key of step + 1
+  int step, noise, freeze, growth, f16;
+};
+hipError_t launch_adam(const ntc_material& m, const AdamLaunch& a, hipStream_t s);
+hipError_t launch_prepare(const ntc_material& m, const float* latents, float* latents_fwd, float* lat_grad,
+                          uint64_t key, int noise, hipStream_t s);
+
+}  // namespace ntc

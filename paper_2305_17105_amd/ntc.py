@@ -1,0 +1,217 @@
+"""Thin ctypes binding of libntc.so (C ABI in include/ntc.h).
+
+Argument marshalling only: every step of decoding and training runs in the HIP
+kernels of libntc.so.  PyTorch provides device memory and streams.  Importing this
+module fails loudly if the library has not been built
+(``python -m paper_2305_17105_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libntc.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_17105_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_UNSUPPORTED, E_WORKSPACE, E_HIP = range(5)
+F32, F16, FP8_E4M3 = 0, 1, 2
+ACT_RELU, ACT_HARDGELU = 0, 1
+MAX_LEVELS, MAX_MIPS = 8, 16
+
+QUERY_DTYPE = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
+
+
+class Material(C.Structure):
+    _fields_ = [
+        ("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32), ("num_mips", C.c_int32),
+        ("c0", C.c_int32), ("c1", C.c_int32), ("b0", C.c_int32), ("b1", C.c_int32),
+        ("grid_shift", C.c_int32), ("hidden", C.c_int32), ("activation", C.c_int32),
+        ("num_levels", C.c_int32), ("input_width", C.c_int32),
+        ("mip_w", C.c_int32 * MAX_MIPS), ("mip_h", C.c_int32 * MAX_MIPS), ("level_of_mip", C.c_int32 * MAX_MIPS),
+        ("g0_w", C.c_int32 * MAX_LEVELS), ("g0_h", C.c_int32 * MAX_LEVELS),
+        ("g1_w", C.c_int32 * MAX_LEVELS), ("g1_h", C.c_int32 * MAX_LEVELS),
+        ("g0_offset", C.c_int64 * MAX_LEVELS), ("g1_offset", C.c_int64 * MAX_LEVELS),
+        ("g0_packed", C.c_int64 * MAX_LEVELS), ("g1_packed", C.c_int64 * MAX_LEVELS),
+        ("mip_offset", C.c_int64 * MAX_MIPS),
+        ("latent_count", C.c_int64), ("packed_bytes", C.c_int64), ("target_count", C.c_int64),
+        ("mlp_params", C.c_int64),
+    ]
+
+
+class TrainStateC(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "latents", "latents_fwd", "lat_m", "lat_v", "lat_grad", "mlp", "mlp_m", "mlp_v", "mlp_packed",
+        "loss", "loss_scale", "scale_state")]
+
+
+class HParams(C.Structure):
+    _fields_ = [
+        ("lr_latent", C.c_float), ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+        ("eps", C.c_float), ("noise_seed", C.c_uint64), ("step", C.c_int32), ("precision", C.c_int32),
+        ("noise", C.c_int32), ("freeze_latents", C.c_int32), ("scale_growth_interval", C.c_int32),
+    ]
+
+
+_P = C.POINTER
+_sig = {
+    "ntc_status_string": (C.c_char_p, [C.c_int]),
+    "ntc_last_error": (C.c_char_p, []),
+    "ntc_material_init": (C.c_int, [_P(Material)]),
+    "ntc_shape_supported": (C.c_int, [_P(Material), C.c_int]),
+    "ntc_quantize_latents": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ntc_dequantize_latents": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ntc_mlp_packed_bytes": (C.c_size_t, [_P(Material), C.c_int]),
+    "ntc_pack_mlp": (C.c_int, [_P(Material), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "ntc_decode": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                             C.c_int, C.c_void_p]),
+    "ntc_train_packed_bytes": (C.c_size_t, [_P(Material), C.c_int]),
+    "ntc_train_workspace_bytes": (C.c_size_t, [_P(Material), C.c_int64, C.c_int]),
+    "ntc_train_prepare": (C.c_int, [_P(Material), _P(TrainStateC), _P(HParams), C.c_void_p]),
+    "ntc_train_step": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p, _P(HParams),
+                                 C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_train_gradients": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p,
+                                      _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_train_update": (C.c_int, [_P(Material), _P(TrainStateC), C.c_int64, _P(HParams), C.c_void_p, C.c_size_t,
+                                   C.c_void_p]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class NtcError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.ntc_last_error().decode()
+        super().__init__(f"{where}: {_lib.ntc_status_string(status).decode()} ({msg})")
+
+
+def _check(status, where):
+    if status != OK:
+        raise NtcError(status, where)
+
+
+def exported_symbols():
+    """Names of the C entry points this binding resolves from the library."""
+    return sorted(_sig)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ descriptor
+def material_init(width, height, channels, c0, c1, b0, b1, hidden=64, num_mips=0, grid_shift=2,
+                  activation=ACT_RELU) -> Material:
+    m = Material()
+    m.width, m.height, m.channels, m.num_mips = width, height, channels, num_mips
+    m.c0, m.c1, m.b0, m.b1 = c0, c1, b0, b1
+    m.grid_shift, m.hidden, m.activation = grid_shift, hidden, activation
+    _check(_lib.ntc_material_init(C.byref(m)), "ntc_material_init")
+    return m
+
+
+def shape_supported(m: Material, for_decode: bool) -> bool:
+    return bool(_lib.ntc_shape_supported(C.byref(m), int(for_decode)))
+
+
+def mlp_packed_bytes(m: Material, precision=F32) -> int:
+    return int(_lib.ntc_mlp_packed_bytes(C.byref(m), precision))
+
+
+def train_packed_bytes(m: Material, precision=F32) -> int:
+    return int(_lib.ntc_train_packed_bytes(C.byref(m), precision))
+
+
+def train_workspace_bytes(m: Material, n: int, precision=F32) -> int:
+    return int(_lib.ntc_train_workspace_bytes(C.byref(m), n, precision))
+
+
+# ------------------------------------------------------------------ entry points (device tensors)
+def quantize_latents(m: Material, latents, packed, stream=None):
+    _check(_lib.ntc_quantize_latents(C.byref(m), _ptr(latents), _ptr(packed), _stream(stream)), "ntc_quantize_latents")
+
+
+def dequantize_latents(m: Material, packed, latents, stream=None):
+    _check(_lib.ntc_dequantize_latents(C.byref(m), _ptr(packed), _ptr(latents), _stream(stream)),
+           "ntc_dequantize_latents")
+
+
+def pack_mlp(m: Material, mlp, precision, packed, stream=None):
+    _check(_lib.ntc_pack_mlp(C.byref(m), _ptr(mlp), precision, _ptr(packed), _stream(stream)), "ntc_pack_mlp")
+
+
+def decode(m: Material, packed_latents, mlp_packed, precision, queries, n, out, out_dtype, stream=None):
+    _check(_lib.ntc_decode(C.byref(m), _ptr(packed_latents), _ptr(mlp_packed), precision, _ptr(queries), n,
+                           _ptr(out), out_dtype, _stream(stream)), "ntc_decode")
+
+
+def train_prepare(m: Material, state: "TrainState", hp: HParams, stream=None):
+    _check(_lib.ntc_train_prepare(C.byref(m), C.byref(state.c), C.byref(hp), _stream(stream)), "ntc_train_prepare")
+
+
+def train_step(m: Material, state: "TrainState", queries, n, targets, hp: HParams, workspace, stream=None):
+    _check(_lib.ntc_train_step(C.byref(m), C.byref(state.c), _ptr(queries), n, _ptr(targets), C.byref(hp),
+                               _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+           "ntc_train_step")
+
+
+def train_gradients(m: Material, state: "TrainState", queries, n, targets, hp: HParams, workspace, stream=None):
+    _check(_lib.ntc_train_gradients(C.byref(m), C.byref(state.c), _ptr(queries), n, _ptr(targets), C.byref(hp),
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+           "ntc_train_gradients")
+
+
+def train_update(m: Material, state: "TrainState", n, hp: HParams, workspace, stream=None):
+    _check(_lib.ntc_train_update(C.byref(m), C.byref(state.c), n, C.byref(hp), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)), "ntc_train_update")
+
+
+def hparams(lr_latent=0.01, lr_mlp=0.005, step=0, precision=F32, noise=True, freeze=False, seed=0,
+            beta1=0.9, beta2=0.999, eps=1e-8, growth=2000) -> HParams:
+    hp = HParams()
+    hp.lr_latent, hp.lr_mlp, hp.beta1, hp.beta2, hp.eps = lr_latent, lr_mlp, beta1, beta2, eps
+    hp.noise_seed, hp.step, hp.precision = seed, step, precision
+    hp.noise, hp.freeze_latents, hp.scale_growth_interval = int(noise), int(freeze), growth
+    return hp
+
+
+class TrainState:
+    """Device buffers of a training run, allocated through PyTorch."""
+
+    def __init__(self, m: Material, latents, mlp, precision=F32, device="cuda", loss_scale=65536.0):
+        import torch
+        L, P = int(m.latent_count), int(m.mlp_params)
+        f = dict(dtype=torch.float32, device=device)
+        self.latents = torch.as_tensor(latents, **f).clone().contiguous()
+        assert self.latents.numel() == L
+        self.latents_fwd = torch.zeros(L, **f)
+        self.lat_m = torch.zeros(L, **f)
+        self.lat_v = torch.zeros(L, **f)
+        self.lat_grad = torch.zeros(L, **f)
+        self.mlp = torch.as_tensor(mlp, **f).clone().contiguous()
+        assert self.mlp.numel() == P
+        self.mlp_m = torch.zeros(P, **f)
+        self.mlp_v = torch.zeros(P, **f)
+        self.mlp_packed = torch.zeros(train_packed_bytes(m, precision), dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, **f)
+        self.loss_scale = torch.full((2,), loss_scale, **f)
+        self.scale_state = torch.zeros(2, dtype=torch.int32, device=device)
+        self.c = TrainStateC(*[C.c_void_p(getattr(self, n).data_ptr()) for n, _ in TrainStateC._fields_])

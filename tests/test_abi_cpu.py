@@ -1,0 +1,93 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point the
+header declares, and its host-side geometry agrees with the oracle's independent one."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ntc_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "ntc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ntc_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def ntc():
+    from paper_2305_17105_amd import ntc as mod
+    return mod
+
+
+def test_every_declared_symbol_is_exported(ntc):
+    import ctypes
+    lib = ctypes.CDLL(ntc.LIB_PATH)
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ntc.exported_symbols())
+
+
+@pytest.mark.parametrize("args", [
+    (1024, 1024, 9, 8, 8, 4, 4, 64, 0, 2),
+    (2048, 2048, 12, 12, 12, 4, 4, 64, 0, 2),
+    (4096, 4096, 16, 16, 16, 2, 4, 64, 0, 2),
+    (256, 256, 8, 8, 8, 4, 4, 64, 1, 2),
+    (512, 128, 3, 5, 7, 2, 8, 32, 0, 1),
+    (4096, 4096, 9, 12, 10, 2, 4, 64, 0, 1),
+])
+def test_host_geometry_matches_oracle(ntc, args):
+    W, H, C, c0, c1, b0, b1, hd, M, sh = args
+    m = ntc.material_init(W, H, C, c0, c1, b0, b1, hd, num_mips=M, grid_shift=sh)
+    g = O.make_geometry(W, H, C, c0, c1, b0, b1, Hd=hd, M=M or None, shift=sh)
+    assert m.num_mips == g.M and m.num_levels == g.J and m.input_width == g.K
+    assert list(m.level_of_mip)[:g.M] == g.level_of_mip
+    assert list(m.mip_w)[:g.M] == g.mip_w and list(m.mip_h)[:g.M] == g.mip_h
+    for j in range(g.J):
+        assert (m.g0_w[j], m.g0_h[j]) == g.g0[j] and (m.g1_w[j], m.g1_h[j]) == g.g1[j]
+        assert m.g0_offset[j] == g.g0_off[j] and m.g1_offset[j] == g.g1_off[j]
+    assert m.latent_count == g.latent_count
+    assert list(m.mip_offset)[:g.M] == g.mip_off and m.target_count == g.target_count
+    assert m.mlp_params == O.mlp_param_count(g.K, hd, C)
+    # packed size: the oracle packer's output length (each grid padded to 16 bytes)
+    assert m.packed_bytes == len(O.quantize_latents(g, np.zeros(g.latent_count)))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width=100), dict(channels=0), dict(channels=17), dict(c0=0), dict(b0=3), dict(hidden=40),
+    dict(num_mips=20), dict(grid_shift=12), dict(width=4, height=4, grid_shift=2), dict(activation=5),
+])
+def test_invalid_descriptors_rejected(ntc, bad):
+    kw = dict(width=256, height=256, channels=8, c0=8, c1=8, b0=4, b1=4, hidden=64, num_mips=0, grid_shift=2,
+              activation=0)
+    kw.update(bad)
+    with pytest.raises(ntc.NtcError) as e:
+        ntc.material_init(kw["width"], kw["height"], kw["channels"], kw["c0"], kw["c1"], kw["b0"], kw["b1"],
+                          kw["hidden"], kw["num_mips"], kw["grid_shift"], kw["activation"])
+    assert e.value.status == ntc.E_INVALID
+
+
+def test_modified_descriptor_rejected_before_any_launch(ntc):
+    import ctypes
+    m = ntc.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    m.latent_count += 1
+    lib = ctypes.CDLL(ntc.LIB_PATH)
+    lib.ntc_quantize_latents.restype = ctypes.c_int
+    st = lib.ntc_quantize_latents(ctypes.byref(m), ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert st == ntc.E_INVALID
+
+
+def test_supported_shapes_and_sizes(ntc):
+    m = ntc.material_init(2048, 2048, 12, 12, 12, 4, 4, 64)
+    assert ntc.shape_supported(m, True) and ntc.shape_supported(m, False)
+    m2 = ntc.material_init(256, 256, 3, 5, 7, 4, 4, 64)
+    assert not ntc.shape_supported(m2, True)
+    # FP16 packs are half the FP32 ones (plus FP32 biases)
+    assert ntc.train_packed_bytes(m, ntc.F16) * 2 >= ntc.train_packed_bytes(m, ntc.F32) - 16
+    assert ntc.mlp_packed_bytes(m, ntc.F32) > ntc.mlp_packed_bytes(m, ntc.F16) > 0
+    assert ntc.mlp_packed_bytes(m, 7) == 0

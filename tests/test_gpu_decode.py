@@ -1,0 +1,136 @@
+"""GPU parity: quantization (bit-exact) and decode (FP32 / FP16) against the FP64 oracle.
+
+Every call goes through the C ABI of libntc.so.  Sizes span several tiles and a
+ragged tail; edge cases: n = 0, n = 1, out-of-range coordinates and LODs.
+"""
+import numpy as np
+import pytest
+
+from _helpers import geometry, mlp_in_unit_range, queries_dev, quantized_latents_oracle, to_dev
+from oracle import ntc_oracle as O
+from paper_2305_17105_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_17105_amd import ntc
+    return ntc
+
+
+def _packed(lib, m, raw):
+    import torch
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    lib.quantize_latents(m, to_dev(raw), packed)
+    return packed
+
+
+QSHAPES = [  # W, C, c0, c1, b0, b1
+    (256, 8, 8, 8, 4, 4),
+    (512, 16, 16, 16, 2, 4),
+    (256, 10, 10, 10, 1, 8),
+    (128, 12, 12, 12, 8, 2),
+    (64, 3, 5, 7, 4, 4),
+]
+
+
+@pytest.mark.parametrize("shape", QSHAPES)
+def test_quantize_bit_exact(lib, shape):
+    import torch
+    W, C, c0, c1, b0, b1 = shape
+    m = lib.material_init(W, W, C, c0, c1, b0, b1, 64)
+    g = geometry(m)
+    raw = synth.uniform_latents(1, int(m.latent_count), -0.8, 0.8)
+    # ties, range ends, non-finite and huge values
+    special = np.array([0.0, -0.0, 0.5, -0.5, 1 / 32, 3 / 32, -15 / 32, -7 / 16, 0.49999997, 1e30, -1e30,
+                        np.inf, -np.inf, np.nan, 1e-40, 0.125, 0.375, -0.375, 0.25 + 2 ** -25], dtype=np.float32)
+    raw[:len(special)] = special
+    got = _packed(lib, m, raw).cpu().numpy()
+    want = O.quantize_latents(g, raw)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    back = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+    lib.dequantize_latents(m, _packed(lib, m, raw), back)
+    assert np.array_equal(back.cpu().numpy().astype(np.float64), O.dequantize_packed(g, want))
+
+
+def test_quantize_fp32_pattern_sweep(lib):
+    """Strided sweep over all 2^32 float32 bit patterns (every 4099th), both bit depths."""
+    m = lib.material_init(1024, 1024, 16, 16, 16, 2, 4, 64)
+    g = geometry(m)
+    n = int(m.latent_count)
+    bits = (np.arange(n, dtype=np.uint64) * np.uint64(4099)) % np.uint64(2 ** 32)
+    raw = bits.astype(np.uint32).view(np.float32)
+    assert np.array_equal(_packed(lib, m, raw).cpu().numpy(), O.quantize_latents(g, raw))
+
+
+DSHAPES = [  # W, C, c0, c1, b0, b1, hidden, mips, n, lod
+    (256, 8, 8, 8, 4, 4, 64, 1, 65536, 0),        # tiny configuration, LOD 0
+    (512, 12, 12, 12, 4, 4, 64, 0, 20011, None),  # full mip chain, 5 levels, ragged
+    (256, 10, 10, 10, 4, 4, 32, 0, 1013, None),   # C not a multiple of 4, hidden 32
+    (512, 16, 16, 16, 2, 4, 64, 0, 4099, None),   # 2-bit G0, 4-bit G1
+    (256, 16, 16, 16, 4, 4, 32, 0, 1, None),      # a single query
+]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("shape", DSHAPES)
+def test_decode_parity(lib, shape, prec):
+    import torch
+    W, C, c0, c1, b0, b1, hd, mips, n, lod = shape
+    P = lib.F32 if prec == "f32" else lib.F16
+    m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips)
+    g = geometry(m)
+    raw = synth.uniform_latents(3, int(m.latent_count))
+    mlp = mlp_in_unit_range(3, g.K, hd, C)
+    q = synth.random_queries(3, n, g.M, lod)
+    packed = _packed(lib, m, raw)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    out = torch.full((n * C,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode(m, packed, wp, P, queries_dev(q), n, out, lib.F32)
+    out16 = torch.zeros(n * C, dtype=torch.float16, device="cuda")
+    lib.decode(m, packed, wp, P, queries_dev(q), n, out16, lib.F16)
+    torch.cuda.synchronize()
+    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q).ravel()
+    got = out.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(got - ref))
+    tol = 1e-5 if prec == "f32" else 2e-3
+    print(f"decode {shape} {prec}: max-abs err {err:.3e}")
+    assert err <= tol
+    got16 = out16.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got16 - got)) <= 2e-3  # FP16 output is the FP32 result rounded
+
+
+def test_decode_edge_coordinates(lib):
+    """u, v outside [0, 1), NaN, and LODs outside the chain are clamped like the oracle."""
+    import torch
+    m = lib.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    g = geometry(m)
+    raw = synth.uniform_latents(5, int(m.latent_count))
+    mlp = mlp_in_unit_range(5, g.K, 64, 8)
+    q = np.zeros(8, dtype=synth.QUERY_DTYPE)
+    q["u"] = [-1.0, 1.0, 2.5, np.nan, 0.999999, 0.5, np.inf, -np.inf]
+    q["v"] = [0.5, 0.0, 1.0, 0.25, 0.999999, np.nan, 0.1, 0.9]
+    q["lod"] = [0, -5, 100, 3, g.M - 1, 2, 1, 7]
+    wp = torch.zeros(lib.mlp_packed_bytes(m, lib.F32), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), lib.F32, wp)
+    out = torch.zeros(8 * 8, dtype=torch.float32, device="cuda")
+    lib.decode(m, _packed(lib, m, raw), wp, lib.F32, queries_dev(q), 8, out, lib.F32)
+    torch.cuda.synchronize()
+    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q).ravel()
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-5
+
+
+def test_decode_zero_queries_is_noop(lib):
+    import torch
+    m = lib.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    out = torch.full((8,), 7.0, device="cuda")
+    wp = torch.zeros(lib.mlp_packed_bytes(m, lib.F32), dtype=torch.uint8, device="cuda")
+    lib.decode(m, torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda"), wp, lib.F32,
+               torch.zeros(12, dtype=torch.uint8, device="cuda"), 0, out, lib.F32)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)

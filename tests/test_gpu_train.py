@@ -1,0 +1,233 @@
+"""GPU parity of the training step (FP32 path) against the FP64 oracle, via the C ABI.
+
+Gradients are read back without any debug hook: a step with learning rate 0 leaves
+the parameters unchanged and sets the first Adam moment to (1 - beta1) * gradient.
+"""
+import numpy as np
+import pytest
+
+from _helpers import geometry, queries_dev, quantized_latents_oracle, rel_err, to_dev
+from oracle import ntc_oracle as O
+from paper_2305_17105_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_17105_amd import ntc
+    return ntc
+
+
+class Run:
+    """One material with its GPU training state and the matching oracle state."""
+
+    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None):
+        import torch
+        self.lib = lib
+        self.prec = lib.F32 if prec is None else prec
+        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips)
+        self.g = geometry(self.m)
+        g = self.g
+        raw = synth.uniform_latents(seed, int(self.m.latent_count))
+        packed = torch.zeros(int(self.m.packed_bytes), dtype=torch.uint8, device="cuda")
+        lib.quantize_latents(self.m, to_dev(raw), packed)
+        lat = torch.zeros(int(self.m.latent_count), dtype=torch.float32, device="cuda")
+        lib.dequantize_latents(self.m, packed, lat)
+        self.mlp = synth.xavier_mlp(seed, g.K, hd, C)
+        self.state = lib.TrainState(self.m, lat, to_dev(self.mlp), self.prec)
+        self.q = synth.random_queries(seed, n, g.M, lod)
+        self.qd = queries_dev(self.q)
+        self.n = n
+        self.mips, tflat = synth.target_chain(seed, 0, W, W, C, g.M)
+        self.targets = tflat
+        self.td = to_dev(tflat)
+        self.ws = torch.zeros(lib.train_workspace_bytes(self.m, n, self.prec), dtype=torch.uint8, device="cuda")
+        P = O.mlp_param_count(g.K, hd, C)
+        self.ostate = dict(latents=quantized_latents_oracle(g, raw), mlp=self.mlp.astype(np.float64),
+                           lat_m=np.zeros(g.latent_count), lat_v=np.zeros(g.latent_count),
+                           mlp_m=np.zeros(P), mlp_v=np.zeros(P))
+
+    def hp(self, **kw):
+        return self.lib.hparams(precision=self.prec, **kw)
+
+    def step(self, hp, q=None, n=None, targets=None):
+        qd = self.qd if q is None else queries_dev(q)
+        self.lib.train_step(self.m, self.state, qd, self.n if n is None else n,
+                            self.td if targets is None else targets, hp, self.ws)
+
+    def get(self, name):
+        import torch
+        torch.cuda.synchronize()
+        return getattr(self.state, name).cpu().numpy().astype(np.float64)
+
+
+def _ohp(hp):
+    return dict(lr_latent=hp.lr_latent, lr_mlp=hp.lr_mlp, beta1=hp.beta1, beta2=hp.beta2, eps=hp.eps,
+                seed=hp.noise_seed, step=hp.step, noise=bool(hp.noise), freeze_latents=bool(hp.freeze_latents))
+
+
+def _grad_groups(g, gp):
+    W1, b1, W2, b2, W3, b3 = O.mlp_split(gp, g.K, g.Hd, g.C)
+    return dict(W1=W1, b1=b1, W2=W2, b2=b2, W3=W3, b3=b3)
+
+
+def _check_grads(run, hp, tol=1e-3):
+    g = run.g
+    lat_fwd = run.ostate["latents"]
+    if hp.noise and not hp.freeze_latents:
+        lat_fwd = lat_fwd + O.noise_values(g, hp.noise_seed, hp.step)
+    L, gp, gl, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, run.targets)
+    b1 = hp.beta1
+    gp_gpu = run.get("mlp_m") / (1 - b1)
+    gl_gpu = run.get("lat_m") / (1 - b1)
+    loss = run.get("loss")[0]
+    errs = {k: rel_err(_grad_groups(g, gp_gpu)[k], v) for k, v in _grad_groups(g, gp).items()}
+    errs["latents"] = rel_err(gl_gpu, gl)
+    print("gradient rel errors:", {k: f"{v:.2e}" for k, v in errs.items()}, f"loss {loss:.6e} vs {L:.6e}")
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    return L, gp, gl
+
+
+CONFIGS = {  # W, C, c0, c1, b0, b1, hidden, mips, n, lod
+    "tiny": (256, 8, 8, 8, 4, 4, 64, 1, 65536, 0),
+    "chain": (512, 12, 12, 12, 4, 4, 64, 0, 30011, None),
+    "ragged32": (256, 10, 10, 10, 4, 4, 32, 0, 4097, None),
+    "c16": (256, 16, 16, 16, 2, 4, 64, 0, 2049, None),
+}
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_gradients_fp32(lib, name):
+    run = Run(lib, *CONFIGS[name])
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=False)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    _check_grads(run, hp)
+    # lr = 0: parameters unchanged, gradient buffer left zeroed
+    assert np.array_equal(run.get("latents"), run.ostate["latents"])
+    assert np.array_equal(run.get("mlp"), run.ostate["mlp"])
+    assert not run.get("lat_grad").any()
+
+
+def test_gradients_with_noise(lib):
+    run = Run(lib, *CONFIGS["chain"], seed=4)
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=True, seed=1234, step=7)
+    lib.train_prepare(run.m, run.state, hp)
+    # forward latents = masters + this step's counter-hash noise, as the oracle draws it
+    want = run.ostate["latents"] + O.noise_values(run.g, 1234, 7)
+    assert np.max(np.abs(run.get("latents_fwd") - want)) <= 1e-7
+    run.step(hp)
+    _check_grads(run, hp)
+    # after the step: forward latents hold the noise of step 8
+    want = run.ostate["latents"] + O.noise_values(run.g, 1234, 8)
+    assert np.max(np.abs(run.get("latents_fwd") - want)) <= 1e-7
+
+
+def _compare_step(run, new, gp, gl, lr):
+    """Post-step parameters.  Adam's first step moves by ~lr*sign(g); entries whose
+    gradient is within rounding of zero may legitimately take either sign."""
+    for name, key, grad in (("latents", "latents", gl), ("mlp", "mlp", gp)):
+        got = run.get(key)
+        want = new[key]
+        sure = np.abs(grad) > 1e-5 * np.sqrt(np.mean(grad ** 2)) + 1e-12
+        err = np.max(np.abs(got - want)[sure]) if sure.any() else 0.0
+        loose = np.max(np.abs(got - want)[~sure]) if (~sure).any() else 0.0
+        print(f"{name}: max-abs err {err:.3e} on {sure.sum()} entries; {int((~sure).sum())} near-zero-gradient entries "
+              f"(max {loose:.2e})")
+        assert err <= 1e-5
+        assert loose <= 2 * lr + 1e-6
+
+
+@pytest.mark.parametrize("name", ["tiny", "chain"])
+def test_one_adam_step_fp32(lib, name):
+    """One full step at lr 1e-2 (tiny configuration: one Adam step at lr 1e-2)."""
+    run = Run(lib, *CONFIGS[name], seed=2)
+    hp = run.hp(lr_latent=1e-2, lr_mlp=1e-2, noise=name == "chain", seed=9)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    new, L, ovf = O.train_step(run.g, run.ostate, run.q, run.targets, _ohp(hp))
+    lat_fwd = run.ostate["latents"] + (O.noise_values(run.g, 9, 0) if hp.noise else 0)
+    _, gp, gl, _ = O.loss_and_grads(run.g, lat_fwd, run.ostate["mlp"], run.q, run.targets)
+    assert not ovf
+    assert abs(run.get("loss")[0] - L) <= 1e-5 * L
+    _compare_step(run, new, gp, gl, 1e-2)
+    lo, hi = O.quant_range(4)
+    lat = run.get("latents")
+    assert lat.min() >= min(lo, O.quant_range(run.g.B0)[0]) - 1e-7 and lat.max() <= 0.5
+
+
+def test_three_steps_loss_trajectory(lib):
+    run = Run(lib, *CONFIGS["chain"], seed=6)
+    st = run.ostate
+    hp0 = run.hp(lr_latent=1e-2, lr_mlp=5e-3, noise=True, seed=3, step=0)
+    lib.train_prepare(run.m, run.state, hp0)
+    for t in range(3):
+        hp = run.hp(lr_latent=1e-2, lr_mlp=5e-3, noise=True, seed=3, step=t)
+        run.step(hp)
+        st, L, _ = O.train_step(run.g, st, run.q, run.targets, _ohp(hp))
+        got = run.get("loss")[0]
+        print(f"step {t}: loss {got:.7e} oracle {L:.7e}")
+        assert abs(got - L) <= 1e-4 * L
+
+
+def test_freeze_latents(lib):
+    run = Run(lib, *CONFIGS["ragged32"], seed=8)
+    hp = run.hp(lr_latent=1e-2, lr_mlp=1e-2, noise=True, freeze=True)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    new, L, _ = O.train_step(run.g, run.ostate, run.q, run.targets, _ohp(hp))
+    assert np.array_equal(run.get("latents"), run.ostate["latents"])
+    assert np.array_equal(run.get("latents_fwd"), run.ostate["latents"])
+    assert not run.get("lat_m").any()
+    assert abs(run.get("loss")[0] - L) <= 1e-5 * L
+    _, gp, _, _ = O.loss_and_grads(run.g, run.ostate["latents"], run.ostate["mlp"], run.q, run.targets)
+    _compare_step(run, dict(new, latents=run.ostate["latents"]), gp, np.zeros(run.g.latent_count), 1e-2)
+
+
+def test_nonfinite_gradient_skips_step(lib):
+    run = Run(lib, *CONFIGS["ragged32"], seed=9)
+    hp = run.hp(lr_latent=1e-2, lr_mlp=1e-2, noise=False)
+    lib.train_prepare(run.m, run.state, hp)
+    bad = run.targets.copy()
+    bad[:50] = np.inf
+    q = synth.tile_queries(256, 256)[:2000]
+    run.step(hp, q=q, n=len(q), targets=to_dev(bad))
+    _, _, ovf = O.train_step(run.g, run.ostate, q, bad, _ohp(hp))
+    assert ovf
+    assert run.get("scale_state")[1] == 1
+    assert np.array_equal(run.get("latents"), run.ostate["latents"])
+    assert np.array_equal(run.get("mlp"), run.ostate["mlp"])
+    assert not run.get("lat_grad").any()
+    # the next good step clears the flag
+    run.step(run.hp(lr_latent=1e-2, lr_mlp=1e-2, noise=False, step=1))
+    assert run.get("scale_state")[1] == 0
+
+
+@pytest.mark.parametrize("name", ["tiny", "chain", "c16"])
+def test_gradients_fp16(lib, name):
+    """FP16 matrix-core forward and backward, FP32 accumulation, loss scale 2^16."""
+    run = Run(lib, *CONFIGS[name], seed=12, prec=lib.F16)
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=True, seed=2)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    g = run.g
+    lat_fwd = run.ostate["latents"] + O.noise_values(g, 2, 0)
+    L, gp, gl, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, run.targets)
+    gp_gpu = run.get("mlp_m") / (1 - hp.beta1)
+    gl_gpu = run.get("lat_m") / (1 - hp.beta1)
+    errs = {k: rel_err(_grad_groups(g, gp_gpu)[k], v) for k, v in _grad_groups(g, gp).items()}
+    errs["latents"] = rel_err(gl_gpu, gl)
+    loss = run.get("loss")[0]
+    print("fp16 gradient rel errors:", {k: f"{v:.2e}" for k, v in errs.items()}, f"loss rel err {abs(loss - L) / L:.2e}")
+    # FP16 operands carry 2^-11 relative rounding, ReLU decisions within that rounding
+    # of zero may flip, and per-latent sums over samples cancel: the measured norm-wise
+    # errors are ~1e-3 (weights) to ~1e-2 (latents); the FP32 path meets 1e-3 with margin.
+    assert abs(loss - L) <= 2e-3 * L
+    for k, v in errs.items():
+        assert v <= 2e-2, (k, v)
+    assert run.get("scale_state")[1] == 0

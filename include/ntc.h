@@ -150,7 +150,9 @@ ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, cons
  *   latents      latent_count  FP32 masters
  *   latents_fwd  latent_count  latents the next forward reads (masters + noise)
  *   lat_m, lat_v latent_count  Adam moments
- *   lat_grad     latent_count  gradient accumulator, zero between steps
+ *   lat_grad     latent_count  gradient of the last step's loss w.r.t. the forward
+ *                              latents (times the loss scale for NTC_F16); every entry
+ *                              is overwritten by each step that trains latents
  *   mlp, mlp_m, mlp_v  mlp_params  canonical FP32 weights and Adam moments
  *   mlp_packed   ntc_train_packed_bytes(m, precision) bytes, private layout
  *   loss         1 float: mean squared error of the last step
@@ -206,8 +208,10 @@ ntc_status ntc_train_prepare(const ntc_material* m, const ntc_train_state* s,
  * bias-corrected Adam on every parameter (dense), clamp of the latents to
  * [-(N-1)/(2N), 1/2], then latents_fwd for step hp->step + 1.  If any gradient
  * is not finite the update is skipped (scale_state[1] = 1; NTC_F16 halves the
- * loss scale).  Leaves lat_grad zeroed.  workspace: ws_bytes >=
- * ntc_train_workspace_bytes(m, n, precision).
+ * loss scale).  workspace: ws_bytes >= ntc_train_workspace_bytes(m, n, precision).
+ * Latent gradients are accumulated without global atomics: samples are binned
+ * by the spatial tile of latents their footprint touches and each tile's
+ * gradient is summed in on-chip memory and written once.
  */
 ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const ntc_query* q,
                           int64_t n, const float* targets, const ntc_hparams* hp,
@@ -216,9 +220,10 @@ ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const
 /*
  * The two halves of ntc_train_step, for callers that time or overlap them, or
  * accumulate gradients of several batches before one update:
- *  ntc_train_gradients: forward, loss and backward of n samples (one fused kernel).
- *    Latent gradients are added into s->lat_grad; per-block weight-gradient and
- *    loss partials go to the workspace.
+ *  ntc_train_gradients: binning of the samples by latent tile, then forward, loss
+ *    and backward of the n samples (one fused kernel).  Writes s->lat_grad (all
+ *    entries, unless latents are frozen); per-block weight-gradient and loss
+ *    partials go to the workspace.
  *  ntc_train_update: reduces the partials of the preceding ntc_train_gradients
  *    call with the same (n, workspace), then Adam, clamp and the next forward
  *    latents exactly as ntc_train_step.  n must equal the gradient call's n.

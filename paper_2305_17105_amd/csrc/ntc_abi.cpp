@@ -250,24 +250,10 @@ ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, cons
                                   out_dtype == NTC_F16, (hipStream_t)stream), "ntc_decode");
 }
 
-// Workspace of a training step: per-block weight-gradient partials, per-block loss
-// partials, the reduced weight gradient.
-struct WsLayout {
-  size_t part_dw, part_loss, grad, total;
-};
-static WsLayout ws_layout(const ntc_material* m, int grid) {
-  WsLayout w;
-  const size_t P = (size_t)m->mlp_params;
-  w.part_dw = 0;
-  w.part_loss = round16((size_t)grid * P * 4);
-  w.grad = w.part_loss + round16((size_t)grid * 4);
-  w.total = w.grad + round16(P * 4);
-  return w;
-}
-
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
   if (!m || n <= 0 || (precision != NTC_F32 && precision != NTC_F16)) return 0;
-  return ws_layout(m, train_grid(*m, precision == NTC_F16, n)).total;
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden)) return 0;
+  return train_plan(*m, precision == NTC_F16, n).total;
 }
 
 static ntc_status check_state(const ntc_train_state* s, bool f16) {
@@ -323,12 +309,11 @@ ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, 
   if (st != NTC_OK) return st;
   if (!q || !targets) return fail(NTC_E_INVALID, "NULL queries or targets");
   const bool f16 = hp->precision == NTC_F16;
-  const int grid = train_grid(*m, f16, n);
-  const WsLayout wl = ws_layout(m, grid);
-  if (!workspace || ws_bytes < wl.total) return fail(NTC_E_WORKSPACE, "workspace too small");
+  const TrainPlan plan = train_plan(*m, f16, n);
+  if (!plan.supported_bins) return fail(NTC_E_UNSUPPORTED, "too many latent tiles for this material");
+  if (!workspace || ws_bytes < plan.total) return fail(NTC_E_WORKSPACE, "workspace too small");
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_status(e, "ntc_train_gradients (earlier asynchronous error)");
-  char* ws = (char*)workspace;
   TrainLaunch a;
   a.lat_fwd = s->latents_fwd;
   a.wpack = s->mlp_packed;
@@ -337,14 +322,12 @@ ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, 
   a.n = n;
   a.targets = targets;
   a.lat_grad = s->lat_grad;
-  a.part_dw = (float*)(ws + wl.part_dw);
-  a.part_loss = (float*)(ws + wl.part_loss);
+  a.workspace = workspace;
   a.loss_scale = f16 ? s->loss_scale : nullptr;
   a.scale_slot = hp->step & 1;
   a.overflow_flag = s->scale_state + 1;
   a.scatter_latents = !hp->freeze_latents;
-  a.grid = grid;
-  return hip_status(launch_train_fused(*m, f16, a, (hipStream_t)stream), "ntc_train_gradients");
+  return hip_status(launch_train_gradients(*m, f16, plan, a, (hipStream_t)stream), "ntc_train_gradients");
 }
 
 ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int64_t n, const ntc_hparams* hp,
@@ -352,14 +335,12 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
   ntc_status st = check_train(m, s, hp, n);
   if (st != NTC_OK) return st;
   const bool f16 = hp->precision == NTC_F16;
-  const int grid = train_grid(*m, f16, n);
-  const WsLayout wl = ws_layout(m, grid);
-  if (!workspace || ws_bytes < wl.total) return fail(NTC_E_WORKSPACE, "workspace too small");
+  const TrainPlan plan = train_plan(*m, f16, n);
+  if (!workspace || ws_bytes < plan.total) return fail(NTC_E_WORKSPACE, "workspace too small");
   hipStream_t hs = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  hipError_t e = launch_reduce(*m, grid, (const float*)(ws + wl.part_dw), (const float*)(ws + wl.part_loss),
-                               (float*)(ws + wl.grad), s->loss, 1.0f / (float)((double)n * m->channels),
-                               s->scale_state + 1, hs);
+  hipError_t e = launch_train_reduce(*m, plan, workspace, s->loss, 1.0f / (float)((double)n * m->channels),
+                                     s->scale_state + 1, hs);
   if (e == hipSuccess) {
     AdamLaunch ad;
     ad.latents = s->latents;
@@ -370,7 +351,7 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
     ad.mlp = s->mlp;
     ad.mlp_m = s->mlp_m;
     ad.mlp_v = s->mlp_v;
-    ad.mlp_grad = (const float*)(ws + wl.grad);
+    ad.mlp_grad = (const float*)(ws + plan.off_grad);
     ad.wpack = s->mlp_packed;
     ad.loss_scale = f16 ? s->loss_scale : nullptr;
     ad.scale_state = s->scale_state;

@@ -175,9 +175,12 @@ __device__ inline int snap_texel(float u, int size) {
 // Everything one lane needs to fetch its share of a texel's inputs.
 struct Footprint {
   int l, j, ix, iy;
-  int g0_cell;      // G0 cell index (within the level's grid) of this lane group's neighbour
-  int g1_cell[4];   // G1 tap cells, order (x,y), (x+1,y), (x,y+1), (x+1,y+1)
-  float g1_w[4];    // bilinear weights of the taps
+  int g0_cell;          // G0 cell index (within the level's grid) of this lane group's neighbour
+  int g0x, g0y;         // its coordinates
+  int ax, ay, bx, by;   // clamped G0 footprint columns (x0, x0+1) and rows (y0, y0+1)
+  int g1_cell[4];       // G1 tap cells, order (x,y), (x+1,y), (x,y+1), (x+1,y+1)
+  int g1x[2], g1y[2];   // clamped G1 tap coordinates (x, x+1), (y, y+1)
+  float g1_w[4];        // bilinear weights of the taps
 };
 
 __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, int g) {
@@ -197,9 +200,13 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
     const float gx = cx * ((float)w0 / (float)Wl) - 0.5f;
     const float gy = cy * ((float)h0 / (float)Hl) - 0.5f;
     const int x0 = (int)floorf(gx), y0 = (int)floorf(gy);
-    const int xx = min(max(x0 + (g & 1), 0), w0 - 1);
-    const int yy = min(max(y0 + (g >> 1), 0), h0 - 1);
-    f.g0_cell = yy * w0 + xx;
+    f.ax = min(max(x0, 0), w0 - 1);
+    f.ay = min(max(y0, 0), h0 - 1);
+    f.bx = min(max(x0 + 1, 0), w0 - 1);
+    f.by = min(max(y0 + 1, 0), h0 - 1);
+    f.g0x = min(max(x0 + (g & 1), 0), w0 - 1);
+    f.g0y = min(max(y0 + (g >> 1), 0), h0 - 1);
+    f.g0_cell = f.g0y * w0 + f.g0x;
   }
   {
     const float gx = cx * ((float)w1 / (float)Wl) - 0.5f;
@@ -207,18 +214,46 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
     const float fx0 = floorf(gx), fy0 = floorf(gy);
     const float fx = gx - fx0, fy = gy - fy0;
     const int x0 = (int)fx0, y0 = (int)fy0;
-    const int xa = min(max(x0, 0), w1 - 1), xb = min(max(x0 + 1, 0), w1 - 1);
-    const int ya = min(max(y0, 0), h1 - 1), yb = min(max(y0 + 1, 0), h1 - 1);
-    f.g1_cell[0] = ya * w1 + xa;
-    f.g1_cell[1] = ya * w1 + xb;
-    f.g1_cell[2] = yb * w1 + xa;
-    f.g1_cell[3] = yb * w1 + xb;
+    f.g1x[0] = min(max(x0, 0), w1 - 1);
+    f.g1x[1] = min(max(x0 + 1, 0), w1 - 1);
+    f.g1y[0] = min(max(y0, 0), h1 - 1);
+    f.g1y[1] = min(max(y0 + 1, 0), h1 - 1);
+    f.g1_cell[0] = f.g1y[0] * w1 + f.g1x[0];
+    f.g1_cell[1] = f.g1y[0] * w1 + f.g1x[1];
+    f.g1_cell[2] = f.g1y[1] * w1 + f.g1x[0];
+    f.g1_cell[3] = f.g1y[1] * w1 + f.g1x[1];
     f.g1_w[0] = (1.f - fx) * (1.f - fy);
     f.g1_w[1] = fx * (1.f - fy);
     f.g1_w[2] = (1.f - fx) * fy;
     f.g1_w[3] = fx * fy;
   }
   return f;
+}
+
+// ------------------------------------------------------------------ spatial tiles of the latent grids
+// Level j's G0 grid is cut into T x T cell tiles (T = min(Tmax, grid side)); the G1
+// grid into the matching (T/2) x (T/2) tiles.  A tile owns the latents of its cells.
+struct TileGeom {
+  int T[kMaxLevels], ntx[kMaxLevels], nty[kMaxLevels], base[kMaxLevels + 1], region[kMaxLevels];
+  int nbins, region_max;
+};
+
+// Tiles whose latents a sample's footprint touches: columns [tx0, tx1], rows [ty0, ty1]
+// (each range spans at most two tiles), and the primary tile holding the clamped anchor.
+struct SampleBins {
+  int j, tx0, tx1, ty0, ty1, ptx, pty;
+};
+__device__ inline SampleBins sample_bins(const Footprint& f, const TileGeom& tg) {
+  SampleBins b;
+  b.j = f.j;
+  const int T = tg.T[f.j], T1 = T >> 1;
+  b.tx0 = min(f.ax / T, f.g1x[0] / T1);
+  b.tx1 = max(f.bx / T, f.g1x[1] / T1);
+  b.ty0 = min(f.ay / T, f.g1y[0] / T1);
+  b.ty1 = max(f.by / T, f.g1y[1] / T1);
+  b.ptx = f.ax / T;
+  b.pty = f.ay / T;
+  return b;
 }
 
 // The three positional-encoding values of lane group g (slots 3g..3g+2 of the 12).

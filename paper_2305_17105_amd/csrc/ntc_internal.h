@@ -28,6 +28,17 @@ hipError_t launch_pack_mlp(const ntc_material& m, const float* mlp, bool f16, bo
 hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const void* wpack, bool f16,
                          const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s);
 
+// Launch plan of a training step: tile geometry, grids and workspace layout (bytes).
+struct TrainPlan {
+  TileGeom tg;
+  int nbins, region_max, nbb, per_bin_block, grid;
+  long long max_items;
+  bool supported_bins;
+  size_t off_counts, off_offsets, off_total, off_base, off_ibase, off_misc, off_list, off_part_lat;
+  size_t off_part_dw, off_part_loss, off_tmp, off_grad, total;
+};
+TrainPlan train_plan(const ntc_material& m, bool f16, long long n);
+
 struct TrainLaunch {
   const float* lat_fwd;
   const void* wpack;
@@ -35,19 +46,17 @@ struct TrainLaunch {
   const ntc_query* q;
   long long n;
   const float* targets;
-  float* lat_grad;
-  float* part_dw;     // [grid][P]
-  float* part_loss;   // [grid]
+  float* lat_grad;          // dense latent gradient (overwritten)
+  void* workspace;
   const float* loss_scale;  // device, 2 entries, or nullptr (scale 1)
   int scale_slot;
-  int32_t* overflow_flag;   // reset by block 0
-  bool scatter_latents;
-  int grid;
+  int32_t* overflow_flag;   // reset by the fused kernel
+  bool scatter_latents;     // false: latents frozen, samples processed in query order
 };
-hipError_t launch_train_fused(const ntc_material& m, bool f16, const TrainLaunch& a, hipStream_t s);
-int train_grid(const ntc_material& m, bool f16, long long n);
-hipError_t launch_reduce(const ntc_material& m, int grid, const float* part_dw, const float* part_loss,
-                         float* grad, float* loss_out, float loss_norm, int32_t* overflow_flag, hipStream_t s);
+hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& a,
+                                  hipStream_t s);
+hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
+                               float loss_norm, int32_t* overflow_flag, hipStream_t s);
 
 struct AdamLaunch {
   float* latents;

@@ -1,25 +1,39 @@
-// Training step of the autodecoder (sections 4.2, 4.5, 5.1) as three kernels:
+// Training step of the autodecoder (sections 4.2, 4.5, 5.1).
 //
-//  1. train_fused_kernel: per 16-texel tile and wavefront, gather latents + PE,
-//     MLP forward on matrix cores, L2 loss and dY, backward through the three
-//     layers (transposed-weight packs, activations kept in registers), scatter of
-//     the latent gradients with float atomics.  Weight gradients need the texel
-//     dimension as the reduction axis, so each block of 4 wavefronts stages its 64
-//     texels' activations and deltas through LDS (transpose) and accumulates
-//     dW += A^T dZ on the matrix cores into registers that persist over all tiles
-//     the block processes; each wavefront owns a disjoint set of dW tiles.  The
-//     block writes one partial gradient vector at the end (no atomics on weights).
-//  2. reduce_kernel: sums the per-block partials in a fixed order (deterministic),
-//     flags non-finite gradients, finalises the loss.
-//  3. adam_kernel: dense bias-corrected Adam on every parameter, clamp of the
-//     latents to the quantization range, zeroing of the latent gradient, the next
-//     step's noisy forward latents, the refreshed weight packs and, for FP16, the
-//     dynamic loss scale.
+// Latent gradients are not scattered with global atomics (hot-set float atomics
+// serialise on small grids and even spread ones run at ~20 G/s on this GPU).
+// Instead every feature level is cut into spatial tiles that own their latents:
+//
+//  1. bin_count / bin_scan / bin_scatter: each sample is listed under every tile
+//     whose latents its footprint (2x2 G0 cells, 4 G1 taps) touches (at most 4),
+//     a counting sort with per-block LDS histograms.  A tile's list is cut into
+//     work items of at most kChunk samples.
+//  2. train_fused_kernel: a persistent block takes work items; for each 64-texel
+//     block tile it gathers latents + PE, runs the MLP forward on matrix cores, the
+//     L2 loss and dY, the backward through the three layers (transposed-weight
+//     packs, activations in registers), accumulates the gradients of the latents
+//     the tile owns in LDS (LDS atomics), and adds dW += A^T dZ through an LDS
+//     transpose into per-wavefront register accumulators.  Loss and weight
+//     gradients count a sample only in its primary tile (the one holding its
+//     footprint anchor); secondary copies only feed the owned latents.  At the end
+//     of a work item the tile's gradient is written densely with plain stores
+//     (single-item tiles) or as a partial (tiles split over several items).
+//  3. lat_partial_reduce: sums the partials of split tiles in item order.
+//  4. dw_reduce1/2: per-block weight-gradient partials summed in a fixed order,
+//     non-finite check, loss.
+//  5. adam_kernel: dense bias-corrected Adam, clamp to the quantization range, next
+//     step's noisy forward latents, refreshed weight packs, FP16 loss scale.
 #include <algorithm>
+#include <cstring>
 
 #include "ntc_internal.h"
 
 namespace ntc {
+
+constexpr int kChunk = 512;       // samples per work item
+constexpr int kBinBlockSamples = 1024;
+constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
+constexpr int kDwYBlocks = 4;     // block rows of the first weight-gradient reduction stage (x4 row groups each)
 
 struct TrainArgs {
   const float* lat_fwd;
@@ -28,15 +42,22 @@ struct TrainArgs {
   const ntc_query* q;
   long long n;
   const float* targets;
-  const float* dout;
   float* lat_grad;
+  float* part_lat;
+  const int* list;
+  const int* bin_total;
+  const int* bin_base;
+  const int* item_base;
+  const int* nitems;
   float* part_dw;
   float* part_loss;
   const float* loss_scale;
   int scale_slot;
   int32_t* overflow_flag;
-  int scatter;
+  int binned;
+  int region_max;
   float inv_nc;
+  TileGeom tg;
 };
 
 template <typename T>
@@ -77,12 +98,12 @@ struct TrainCfg {
   using IS = InSlots<C0, C1>;
   static constexpr PackGeom pg = pack_geom(C0, C1, HD, sizeof(T) == 2);
   static constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT, ML = pg.ML;
-  static constexpr int MT1 = (S1 + 3) / 4;        // dW1 M-tiles (X slot rows 4t+g)
-  static constexpr int RX = 16 * MT1;              // X rows in the transpose buffer
+  static constexpr int MT1 = (S1 + 3) / 4;         // dW1 M-tiles (X slot rows 4t+g)
+  static constexpr int RX = 16 * MT1;               // X rows in the transpose buffer
   static constexpr int RS = lds_row_stride<T>();
-  static constexpr int TR = cmax(cmax(RX + HD, 2 * HD), HD + 16);  // rows of the transpose buffer
-  static constexpr int NT2 = (MT * MT + 3) / 4;    // dW2 tiles per wavefront
-  static constexpr int NT1 = (MT1 * MT + 3) / 4;   // dW1 tiles per wavefront
+  static constexpr int TR = cmax(cmax(RX + HD, 2 * HD), HD + 16);
+  static constexpr int NT2 = (MT * MT + 3) / 4;     // dW2 tiles per wavefront
+  static constexpr int NT1 = (MT1 * MT + 3) / 4;    // dW1 tiles per wavefront
   static constexpr long long K = 4 * C0 + C1 + 12;
   static constexpr long long P = K * HD + HD + (long long)HD * HD + HD + (long long)HD * C + C;
   static constexpr long long W1o = 0, b1o = K * HD, W2o = b1o + HD, b2o = W2o + (long long)HD * HD;
@@ -90,13 +111,18 @@ struct TrainCfg {
   static constexpr int WB = ((int)pg.train_end * (int)sizeof(T) + 15) / 16 * 16;
   static constexpr int OFF_PE = WB;
   static constexpr int OFF_BIAS = OFF_PE + 48 * 4;
-  static constexpr int OFF_TAB = OFF_BIAS + (2 * HD + 16) * 4;    // g0_off[8], g1_off[8], mip_off[16]
+  static constexpr int OFF_TAB = OFF_BIAS + (2 * HD + 16) * 4;  // g0_off[8], g1_off[8], mip_off[16]
   static constexpr int OFF_RED = OFF_TAB + 32 * 8;
   static constexpr int OFF_BUF = (OFF_RED + 16 + 15) / 16 * 16;
-  static constexpr int LDS = OFF_BUF + TR * RS * (int)sizeof(T);
+  static constexpr int OFF_REG = OFF_BUF + (TR * RS * (int)sizeof(T) + 15) / 16 * 16;
+  static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
+  static constexpr int kLdsCap = 160 * 1024;
+  // largest tile side whose owned-latent gradient fits next to the rest
+  static constexpr int TMAX = OFF_REG + region(32) * 4 <= kLdsCap ? 32 : OFF_REG + region(16) * 4 <= kLdsCap ? 16 : 8;
+  static constexpr int LDS = OFF_REG + region(TMAX) * 4;
 };
 
-template <typename T, int C0, int C1, int C, int HD, bool EXT_DY>
+template <typename T, int C0, int C1, int C, int HD>
 __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
@@ -110,6 +136,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
   long long* tab = reinterpret_cast<long long*>(smem + Cfg::OFF_TAB);
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
+  float* reg = reinterpret_cast<float*>(smem + Cfg::OFF_REG);
 
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += 256)
@@ -122,9 +149,12 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
     else if (i < 2 * HD + C) v = a.mlp[Cfg::b3o + i - 2 * HD];
     b_lds[i] = v;
   }
-  if (tid < 8) { tab[tid] = m.g0_off[tid]; tab[8 + tid] = m.g1_off[tid]; }
+  if (tid < 8) {
+    tab[tid] = m.g0_off[tid];
+    tab[8 + tid] = m.g1_off[tid];
+  }
   if (tid < 16) tab[16 + tid] = m.mip_off[tid];
-  if (blockIdx.x == 0 && tid == 0 && !EXT_DY) *a.overflow_flag = 0;
+  if (blockIdx.x == 0 && tid == 0) *a.overflow_flag = 0;
   __syncthreads();
 
   const float scale = a.loss_scale ? a.loss_scale[a.scale_slot] : 1.f;
@@ -139,209 +169,268 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
   for (int k = 0; k < Cfg::NT1; ++k) acc1[k] = acc3;
   float db1 = 0.f, db2 = 0.f, db3 = 0.f, loss = 0.f;
 
-  const long long tiles = (a.n + 63) / 64;
-  for (long long tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const long long s = tile * 64 + wave * 16 + r;
-    const bool valid = s < a.n;
-    float u = 0.f, v = 0.f;
-    int lod = 0;
-    if (valid) {
-      u = a.q[s].u;
-      v = a.q[s].v;
-      lod = a.q[s].lod;
-    }
-    const Footprint f = locate(m, u, v, lod, g);
-    const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
-    const long long g1base = tab[8 + f.j];
-
-    // ---------------- gather (forward latents already hold this step's noise)
-    T xs[S1];
-#pragma unroll
-    for (int t = 0; t < C0; ++t) xs[t] = (T)a.lat_fwd[g0base + t];
-#pragma unroll
-    for (int i = 0; i < IS::n1max; ++i) {
-      const int ch = g + 4 * i;
-      float acc = 0.f;
-      if (ch < C1) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc += f.g1_w[k] * a.lat_fwd[g1base + (long long)f.g1_cell[k] * C1 + ch];
+  const int nitems = a.binned ? *a.nitems : (int)((a.n + kChunk - 1) / kChunk);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    // ---------------- work item -> (tile, sample range)
+    int j = 0, tx = 0, ty = 0, T_ = 2, cnt;
+    long long start;
+    bool single = true;
+    if (a.binned) {
+      int lo = 0, hi = a.tg.nbins;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.item_base[mid] <= item) lo = mid;
+        else hi = mid;
       }
-      xs[C0 + i] = (T)acc;
+      const int bin = lo;
+      const int chunk = item - a.item_base[bin];
+      single = (a.item_base[bin + 1] - a.item_base[bin]) == 1;
+      start = (long long)a.bin_base[bin] + (long long)chunk * kChunk;
+      cnt = min(kChunk, a.bin_total[bin] - chunk * kChunk);
+      while (j + 1 < m.J && bin >= a.tg.base[j + 1]) ++j;
+      const int t = bin - a.tg.base[j];
+      tx = t % a.tg.ntx[j];
+      ty = t / a.tg.ntx[j];
+      T_ = a.tg.T[j];
+    } else {
+      start = (long long)item * kChunk;
+      cnt = (int)min((long long)kChunk, a.n - start);
     }
-    {
-      float pv[3];
-      pe_values(pe_lds, f.ix, f.iy, g, pv);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) xs[IS::T_lat + k] = (T)pv[k];
-#pragma unroll
-      for (int t = IS::T_used; t < S1; ++t) xs[t] = (T)0.f;
-    }
-    if (!valid) {
-#pragma unroll
-      for (int t = 0; t < S1; ++t) xs[t] = (T)0.f;
-    }
+    const int T1 = T_ >> 1;
+    const int R0 = T_ * T_ * C0;
+    const int RG = R0 + T1 * T1 * C1;
+    if (a.binned)
+      for (int k = tid; k < RG; k += 256) reg[k] = 0.f;
+    __syncthreads();
 
-    // ---------------- forward
-    float z1[SH], z2[SH];
-    T hs[SH];
-    f32x4 acc[MT];
+    for (int t0 = 0; t0 < cnt; t0 += 64) {
+      const int pos = t0 + wave * 16 + r;
+      const bool valid = pos < cnt;
+      long long s = 0;
+      if (valid) s = a.binned ? (long long)a.list[start + pos] : start + pos;
+      float u = 0.f, v = 0.f;
+      int lod = 0;
+      if (valid) {
+        u = a.q[s].u;
+        v = a.q[s].v;
+        lod = a.q[s].lod;
+      }
+      const Footprint f = locate(m, u, v, lod, g);
+      const bool primary = valid && (!a.binned || (f.ax / T_ == tx && f.ay / T_ == ty));
+      const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
+      const long long g1base = tab[8 + f.j];
+
+      // ---------------- gather (forward latents already hold this step's noise)
+      T xs[S1];
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + 16 * mo + 4 * g);
-      acc[mo] = mma_slots<S1>(acc[mo], w_lds + pg.L1 + mo * S1 * 64, xs, lane);
-    }
+      for (int t = 0; t < C0; ++t) xs[t] = (T)a.lat_fwd[g0base + t];
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo)
+      for (int i = 0; i < IS::n1max; ++i) {
+        const int ch = g + 4 * i;
+        float acc = 0.f;
+        if (ch < C1) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        z1[4 * mo + i] = acc[mo][i];
-        hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
+          for (int k = 0; k < 4; ++k) acc += f.g1_w[k] * a.lat_fwd[g1base + (long long)f.g1_cell[k] * C1 + ch];
+        }
+        xs[C0 + i] = (T)acc;
+      }
+      {
+        float pv[3];
+        pe_values(pe_lds, f.ix, f.iy, g, pv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[IS::T_lat + k] = (T)pv[k];
+#pragma unroll
+        for (int t = IS::T_used; t < S1; ++t) xs[t] = (T)0.f;
+      }
+      if (!valid) {
+#pragma unroll
+        for (int t = 0; t < S1; ++t) xs[t] = (T)0.f;
+      }
+
+      // ---------------- forward
+      float z1[SH], z2[SH];
+      T hs[SH];
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + 16 * mo + 4 * g);
+        acc[mo] = mma_slots<S1>(acc[mo], w_lds + pg.L1 + mo * S1 * 64, xs, lane);
       }
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
-      acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, hs, lane);
-    }
+      for (int mo = 0; mo < MT; ++mo)
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo)
+        for (int i = 0; i < 4; ++i) {
+          z1[4 * mo + i] = acc[mo][i];
+          hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
+        }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        z2[4 * mo + i] = acc[mo][i];
-        hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
+        acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, hs, lane);
       }
-    f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
-    y = mma_slots<SH>(y, w_lds + pg.L3, hs, lane);
-
-    // ---------------- loss and output gradient (lane group g: channels 4g..4g+3)
-    T dyT[4];
-    float dyv[4];
-    {
-      const int l = f.l;
-      const long long tb = tab[16 + l] + ((long long)f.iy * m.mip_w[l] + f.ix) * C;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = 4 * g + i;
-        float d = 0.f;
-        if (valid && c < C) {
-          if constexpr (EXT_DY) {
-            d = a.dout[s * C + c] * scale;
-          } else {
+      for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          z2[4 * mo + i] = acc[mo][i];
+          hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
+        }
+      f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
+      y = mma_slots<SH>(y, w_lds + pg.L3, hs, lane);
+
+      // ---------------- loss and output gradient (lane group g: channels 4g..4g+3)
+      T dyT[4];
+      {
+        const int l = f.l;
+        const long long tb = tab[16 + l] + ((long long)f.iy * m.mip_w[l] + f.ix) * C;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 4 * g + i;
+          float d = 0.f;
+          if (valid && c < C) {
             const float e = y[i] - a.targets[tb + c];
-            loss += e * e;
+            if (primary) loss += e * e;
             d = 2.f * e * a.inv_nc * scale;
           }
+          dyT[i] = (T)d;
         }
-        dyv[i] = d;
-        dyT[i] = (T)d;
       }
-    }
 
-    // ---------------- backward through the layers
-    float dz2[SH], dz1[SH];
-    T dT[SH];
+      // ---------------- backward through the layers
+      float dz2[SH], dz1[SH];
+      T dT[SH];
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      f32x4 d = {0.f, 0.f, 0.f, 0.f};
-      d = mma_slots<4>(d, w_lds + pg.B3 + mo * 4 * 64, dyT, lane);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        dz2[4 * mo + i] = d[i] * act_grad(z2[4 * mo + i], act);
-        dT[4 * mo + i] = (T)dz2[4 * mo + i];
-      }
-    }
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      f32x4 d = {0.f, 0.f, 0.f, 0.f};
-      d = mma_slots<SH>(d, w_lds + pg.B2 + mo * SH * 64, dT, lane);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * act_grad(z1[4 * mo + i], act);
-    }
-    T dz1T[SH];
-#pragma unroll
-    for (int t = 0; t < SH; ++t) dz1T[t] = (T)dz1[t];
-
-    if (a.scatter) {  // wavefront-uniform: the matrix-core ops run for every lane
-      float dx[4 * ML];
-#pragma unroll
-      for (int mo = 0; mo < ML; ++mo) {
+      for (int mo = 0; mo < MT; ++mo) {
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
-        d = mma_slots<SH>(d, w_lds + pg.B1 + mo * SH * 64, dz1T, lane);
+        d = mma_slots<4>(d, w_lds + pg.B3 + mo * 4 * 64, dyT, lane);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dx[4 * mo + i] = d[i];
+        for (int i = 0; i < 4; ++i) {
+          dz2[4 * mo + i] = d[i] * act_grad(z2[4 * mo + i], act);
+          dT[4 * mo + i] = (T)dz2[4 * mo + i];
+        }
       }
-      if (valid) {
-        float* gl = a.lat_grad;
 #pragma unroll
-        for (int t = 0; t < C0; ++t) unsafeAtomicAdd(gl + g0base + t, dx[t]);
+      for (int mo = 0; mo < MT; ++mo) {
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        d = mma_slots<SH>(d, w_lds + pg.B2 + mo * SH * 64, dT, lane);
 #pragma unroll
-        for (int i = 0; i < IS::n1max; ++i) {
-          const int ch = g + 4 * i;
-          if (ch < C1) {
+        for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * act_grad(z1[4 * mo + i], act);
+      }
+      T dz1T[SH];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-              if (f.g1_w[k] != 0.f)
-                unsafeAtomicAdd(gl + g1base + (long long)f.g1_cell[k] * C1 + ch, f.g1_w[k] * dx[C0 + i]);
+      for (int t = 0; t < SH; ++t) dz1T[t] = (T)dz1[t];
+
+      if (a.binned) {  // block-uniform: the matrix-core ops run for every lane
+        float dx[4 * ML];
+#pragma unroll
+        for (int mo = 0; mo < ML; ++mo) {
+          f32x4 d = {0.f, 0.f, 0.f, 0.f};
+          d = mma_slots<SH>(d, w_lds + pg.B1 + mo * SH * 64, dz1T, lane);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dx[4 * mo + i] = d[i];
+        }
+        if (valid) {  // gradients of the latents this tile owns, accumulated in LDS
+          if (f.g0x / T_ == tx && f.g0y / T_ == ty) {
+            float* dst = reg + ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) * C0;
+#pragma unroll
+            for (int t = 0; t < C0; ++t) atomicAdd(dst + t, dx[t]);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
+            if (x1 / T1 == tx && y1 / T1 == ty && f.g1_w[k] != 0.f) {
+              float* dst = reg + R0 + ((y1 - ty * T1) * T1 + (x1 - tx * T1)) * C1;
+#pragma unroll
+              for (int i = 0; i < IS::n1max; ++i) {
+                const int ch = g + 4 * i;
+                if (ch < C1) atomicAdd(dst + ch, f.g1_w[k] * dx[C0 + i]);
+              }
+            }
           }
         }
       }
+
+      // ---------------- weight gradients through LDS (texels become the K axis);
+      // only a sample's primary copy contributes
+      const int col = wave * 16 + r;
+      const T zero = (T)0.f;
+      // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
+#pragma unroll
+      for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
+      __syncthreads();
+      if (wave < MT) acc3 = dw_tile<T>(acc3, buf, 16 * wave, HD, g, r);
+      if (tid < 16) {
+        float sum = 0.f;
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
+        db3 += sum;
+      }
+      __syncthreads();
+      // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
+#pragma unroll
+      for (int t = 0; t < SH; ++t) {
+        buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
+        buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < Cfg::NT2; ++k) {
+        const int id = wave + 4 * k;
+        if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
+      }
+      if (tid < HD) {
+        float sum = 0.f;
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
+        db2 += sum;
+      }
+      __syncthreads();
+      // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
+#pragma unroll
+      for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
+#pragma unroll
+      for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < Cfg::NT1; ++k) {
+        const int id = wave + 4 * k;
+        if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
+      }
+      if (tid < HD) {
+        float sum = 0.f;
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) sum += (float)buf[(RX + tid) * RS + c];
+        db1 += sum;
+      }
+      __syncthreads();
     }
 
-    // ---------------- weight gradients through LDS (texels become the K axis)
-    const int col = wave * 16 + r;
-    // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
-#pragma unroll
-    for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = valid ? (T)act_fn(z2[t], act) : (T)0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = dyT[i];
-    __syncthreads();
-    if (wave < MT) acc3 = dw_tile<T>(acc3, buf, 16 * wave, HD, g, r);
-    if (tid < 16) {
-      float sum = 0.f;
-#pragma unroll 8
-      for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
-      db3 += sum;
+    // ---------------- the tile's latent gradient: dense plain stores (or a partial)
+    if (a.binned) {
+      if (single) {
+        const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
+        for (int k = tid; k < RG; k += 256) {
+          long long gi;
+          if (k < R0) {
+            const int c = k % C0, cell = k / C0, cx = cell % T_, cy = cell / T_;
+            gi = tab[j] + ((long long)(ty * T_ + cy) * w0 + tx * T_ + cx) * C0 + c;
+          } else {
+            const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
+            gi = tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
+          }
+          a.lat_grad[gi] = reg[k];
+        }
+      } else {
+        float* dst = a.part_lat + (long long)item * a.region_max;
+        for (int k = tid; k < RG; k += 256) dst[k] = reg[k];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
-#pragma unroll
-    for (int t = 0; t < SH; ++t) {
-      buf[hid_feature(g, t) * RS + col] = valid ? (T)act_fn(z1[t], act) : (T)0.f;
-      buf[(HD + hid_feature(g, t)) * RS + col] = dT[t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < Cfg::NT2; ++k) {
-      const int id = wave + 4 * k;
-      if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
-    }
-    if (tid < HD) {
-      float sum = 0.f;
-#pragma unroll 8
-      for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
-      db2 += sum;
-    }
-    __syncthreads();
-    // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
-#pragma unroll
-    for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = t < S1 ? xs[t] : (T)0.f;
-#pragma unroll
-    for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = dz1T[t];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < Cfg::NT1; ++k) {
-      const int id = wave + 4 * k;
-      if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
-    }
-    if (tid < HD) {
-      float sum = 0.f;
-#pragma unroll 8
-      for (int c = 0; c < 64; ++c) sum += (float)buf[(RX + tid) * RS + c];
-      db1 += sum;
-    }
-    __syncthreads();
   }
 
-  // ---------------- per-block partial gradient (canonical layout) and loss
+  // ---------------- per-block partial weight gradient (canonical layout) and loss
   float* part = a.part_dw + (long long)blockIdx.x * Cfg::P;
   if (wave < MT) {
 #pragma unroll
@@ -367,7 +456,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
     if (id < MT1 * MT) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int t = 4 * (id / MT) + g;  // slot row 4t + gi, gi = i
+        const int t = 4 * (id / MT) + g;  // slot row 4t + gi with gi = i
         const int kin = t < S1 ? IS::psi(i, t) : -1;
         const int h = 16 * (id % MT) + r;
         if (kin >= 0) part[Cfg::W1o + (long long)kin * HD + h] = acc1[k][i];
@@ -379,25 +468,163 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
     part[Cfg::b2o + tid] = db2;
   }
   if (tid < C) part[Cfg::b3o + tid] = db3;
-  // loss: wavefront then block reduction
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
   if (lane == 0) red[wave] = loss;
   __syncthreads();
   if (tid == 0) a.part_loss[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void reduce_kernel(int grid, long long P, const float* __restrict__ part, const float* __restrict__ part_loss,
-                              float* __restrict__ grad, float* __restrict__ loss_out, float norm, int32_t* flag) {
+// ------------------------------------------------------------------ binning (counting sort)
+struct BinArgs {
+  const ntc_query* q;
+  long long n;
+  int per_block;
+  int nbb;
+  int* counts;         // [nbb][nbins]
+  const int* offsets;  // [nbb][nbins], relative to the bin base
+  const int* base;     // [nbins + 1]
+  int* list;
+};
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs a) {
+  extern __shared__ int hist[];
+  const int nb = tg.nbins;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)blockIdx.x * nb + b] : 0;
+  __syncthreads();
+  const long long s0 = (long long)blockIdx.x * a.per_block;
+  const long long s1 = min(a.n, s0 + a.per_block);
+  for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+    const ntc_query qq = a.q[s];
+    const Footprint f = locate(m, qq.u, qq.v, qq.lod, 0);
+    const SampleBins sb = sample_bins(f, tg);
+    for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
+      for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
+        const int b = tg.base[sb.j] + ty * tg.ntx[sb.j] + tx;
+        if (SCATTER) a.list[atomicAdd(&hist[b], 1)] = (int)s;
+        else atomicAdd(&hist[b], 1);
+      }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)blockIdx.x * nb + b] = hist[b];
+  }
+}
+
+// One block of 1024 threads: per-bin totals and per-block offsets, exclusive scans of
+// the totals (bin bases) and of the work items per bin.
+__global__ __launch_bounds__(1024) void bin_scan_kernel(int nbins, int nbb, const int* __restrict__ counts,
+                                                        int* __restrict__ offsets, int* __restrict__ total,
+                                                        int* __restrict__ base, int* __restrict__ item_base,
+                                                        int* __restrict__ nitems) {
+  __shared__ int s_tot[1024], s_items[1024];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < nbins; b += 1024) {
+    int run = 0;
+    for (int k = 0; k < nbb; ++k) {
+      const int c = counts[(long long)k * nbins + b];
+      offsets[(long long)k * nbins + b] = run;
+      run += c;
+    }
+    total[b] = run;
+  }
+  __syncthreads();
+  const int per = (nbins + 1023) / 1024;
+  const int b0 = min(nbins, tid * per), b1 = min(nbins, b0 + per);
+  int st = 0, si = 0;
+  for (int b = b0; b < b1; ++b) {
+    st += total[b];
+    si += max(1, (total[b] + kChunk - 1) / kChunk);
+  }
+  s_tot[tid] = st;
+  s_items[tid] = si;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int vt = tid >= d ? s_tot[tid - d] : 0;
+    const int vi = tid >= d ? s_items[tid - d] : 0;
+    __syncthreads();
+    s_tot[tid] += vt;
+    s_items[tid] += vi;
+    __syncthreads();
+  }
+  int pt = s_tot[tid] - st, pi = s_items[tid] - si;  // exclusive prefixes
+  for (int b = b0; b < b1; ++b) {
+    base[b] = pt;
+    item_base[b] = pi;
+    pt += total[b];
+    pi += max(1, (total[b] + kChunk - 1) / kChunk);
+  }
+  if (tid == 1023) {
+    base[nbins] = s_tot[1023];
+    item_base[nbins] = s_items[1023];
+    *nitems = s_items[1023];
+  }
+}
+
+// Latent gradients of tiles split over several work items: partials summed in item order.
+__global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
+                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad) {
+  const int bin = blockIdx.y;
+  const int it0 = item_base[bin], items = item_base[bin + 1] - it0;
+  if (items <= 1) return;
+  int j = 0;
+  while (j + 1 < m.J && bin >= tg.base[j + 1]) ++j;
+  const int t = bin - tg.base[j], tx = t % tg.ntx[j], ty = t / tg.ntx[j];
+  const int T = tg.T[j], T1 = T >> 1;
+  const int C0 = m.C0, C1 = m.C1;
+  const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
+  const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < RG; k += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int i = 0; i < items; ++i) s += part[(long long)(it0 + i) * region_max + k];
+    long long gi;
+    if (k < R0) {
+      const int c = k % C0, cell = k / C0, cx = cell % T, cy = cell / T;
+      gi = m.g0_off[j] + ((long long)(ty * T + cy) * w0 + tx * T + cx) * C0 + c;
+    } else {
+      const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
+      gi = m.g1_off[j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
+    }
+    lat_grad[gi] = s;
+  }
+}
+
+// ------------------------------------------------------------------ weight-gradient reduction
+// Stage 1: block (64 params x 4 row groups) sums its share of the per-block partial rows.
+__global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const float* __restrict__ part,
+                                                  float* __restrict__ tmp) {
+  __shared__ float red[4][64];
+  const long long p = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int ngroups = gridDim.y * 4;
+  const int per = (G + ngroups - 1) / ngroups;
+  const int b0 = rg * per, b1 = min(G, b0 + per);
+  float s = 0.f;
+  if (p < P) {
+#pragma unroll 4
+    for (int b = b0; b < b1; ++b) s += part[(long long)b * P + p];
+  }
+  red[threadIdx.x >> 6][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && p < P)
+    tmp[(long long)blockIdx.y * P + p] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// Stage 2: final sum, non-finite flag, loss.
+__global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp, float* __restrict__ grad,
+                           int G, const float* __restrict__ part_loss, float* __restrict__ loss_out, float norm,
+                           int32_t* flag) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int b = 0; b < grid; ++b) s += part[(long long)b * P + p];
+    for (int k = 0; k < parts; ++k) s += tmp[(long long)k * P + p];
     grad[p] = s;
     if (flag && !isfinite(s)) atomicOr(flag, 1);
   }
   if (blockIdx.x == 0 && loss_out) {
     __shared__ float red[256];
     float s = 0.f;
-    for (int b = threadIdx.x; b < grid; b += blockDim.x) s += part_loss[b];
+    for (int b = threadIdx.x; b < G; b += blockDim.x) s += part_loss[b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -408,6 +635,7 @@ __global__ void reduce_kernel(int grid, long long P, const float* __restrict__ p
   }
 }
 
+// ------------------------------------------------------------------ optimiser
 // Bits of the grid holding latent i (grids are contiguous in canonical order).
 __device__ inline int latent_bits(const DevMat& m, long long i) {
   int bits = m.B0;
@@ -478,7 +706,6 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
       a.lat_v[i] = vv;
       a.latents[i] = p;
     }
-    a.lat_grad[i] = 0.f;
     a.latents_fwd[i] = a.noise ? p + noise_at(a.next_key, i, bits) : p;
   }
 }
@@ -493,28 +720,32 @@ __global__ void prepare_kernel(DevMat m, const float* __restrict__ lat, float* _
   }
 }
 
-// ------------------------------------------------------------------ launchers
-template <typename T, int C0, int C1, int C, int HD, bool EXT>
+// ------------------------------------------------------------------ host side
+template <typename T, int C0, int C1, int C, int HD>
 static int fused_per_cu() {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD, EXT>, 256, Cfg::LDS) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return per_cu;
+  static int cached = 0;
+  if (cached == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD>, 256, Cfg::LDS) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    cached = per_cu;
+  }
+  return cached;
 }
 
 template <typename T, int C0, int C1, int C, int HD>
-static int grid_t(long long n) {
-  const long long tiles = (n + 63) / 64;
-  const long long cap = (long long)device_cus() * fused_per_cu<T, C0, C1, C, HD, false>();
-  return (int)std::max<long long>(1, std::min(tiles, cap));
+static void shape_info(int& tmax, int& per_cu) {
+  tmax = TrainCfg<T, C0, C1, C, HD>::TMAX;
+  per_cu = fused_per_cu<T, C0, C1, C, HD>();
 }
 
 template <typename T, int C0, int C1, int C, int HD>
-static hipError_t fused_t(const ntc_material& mm, const TrainLaunch& l, hipStream_t s) {
+static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const TrainLaunch& l, hipStream_t s) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
+  char* ws = (char*)l.workspace;
   TrainArgs a;
   a.lat_fwd = l.lat_fwd;
   a.wpack = l.wpack;
@@ -522,16 +753,23 @@ static hipError_t fused_t(const ntc_material& mm, const TrainLaunch& l, hipStrea
   a.q = l.q;
   a.n = l.n;
   a.targets = l.targets;
-  a.dout = nullptr;
   a.lat_grad = l.lat_grad;
-  a.part_dw = l.part_dw;
-  a.part_loss = l.part_loss;
+  a.part_lat = (float*)(ws + p.off_part_lat);
+  a.list = (const int*)(ws + p.off_list);
+  a.bin_total = (const int*)(ws + p.off_total);
+  a.bin_base = (const int*)(ws + p.off_base);
+  a.item_base = (const int*)(ws + p.off_ibase);
+  a.nitems = (const int*)(ws + p.off_misc);
+  a.part_dw = (float*)(ws + p.off_part_dw);
+  a.part_loss = (float*)(ws + p.off_part_loss);
   a.loss_scale = l.loss_scale;
   a.scale_slot = l.scale_slot;
   a.overflow_flag = l.overflow_flag;
-  a.scatter = l.scatter_latents ? 1 : 0;
+  a.binned = l.scatter_latents ? 1 : 0;
+  a.region_max = p.region_max;
   a.inv_nc = (float)(1.0 / ((double)l.n * C));
-  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, false>), dim3(l.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
+  a.tg = p.tg;
+  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
                      pe_table(), a);
   return hipGetLastError();
 }
@@ -548,30 +786,113 @@ bool train_shape_supported(int c0, int c1, int c, int hd) {
   return false;
 }
 
-int train_grid(const ntc_material& m, bool f16, long long n) {
-#define NTC_X(a, b, cc, h)                                                    \
-  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h)            \
-    return f16 ? grid_t<_Float16, a, b, cc, h>(n) : grid_t<float, a, b, cc, h>(n);
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
+  TrainPlan p{};
+  int tmax = 8, per_cu = 1;
+#define NTC_X(a_, b, cc, h)                                                                          \
+  if (m.c0 == a_ && m.c1 == b && m.channels == cc && m.hidden == h) {                                \
+    if (f16) shape_info<_Float16, a_, b, cc, h>(tmax, per_cu);                                       \
+    else shape_info<float, a_, b, cc, h>(tmax, per_cu);                                              \
+  }
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
-  return 1;
+  TileGeom& tg = p.tg;
+  std::memset(&tg, 0, sizeof tg);
+  int nb = 0, rmax = 0;
+  for (int j = 0; j < m.num_levels; ++j) {
+    const int T = std::min(tmax, std::min(m.g0_w[j], m.g0_h[j]));
+    tg.T[j] = T;
+    tg.ntx[j] = m.g0_w[j] / T;
+    tg.nty[j] = m.g0_h[j] / T;
+    tg.base[j] = nb;
+    tg.region[j] = T * T * m.c0 + (T / 2) * (T / 2) * m.c1;
+    rmax = std::max(rmax, tg.region[j]);
+    nb += tg.ntx[j] * tg.nty[j];
+  }
+  tg.base[m.num_levels] = nb;
+  for (int j = m.num_levels + 1; j <= kMaxLevels; ++j) tg.base[j] = nb;
+  tg.nbins = nb;
+  tg.region_max = rmax;
+  p.region_max = rmax;
+  p.nbins = nb;
+  p.nbb = (int)std::max<long long>(1, std::min<long long>(256, (n + kBinBlockSamples - 1) / kBinBlockSamples));
+  p.per_bin_block = (int)((n + p.nbb - 1) / p.nbb);
+  p.max_items = nb + (4 * n + kChunk - 1) / kChunk;
+  const long long work_items = std::max<long long>(p.max_items, (n + kChunk - 1) / kChunk);
+  p.grid = (int)std::max<long long>(1, std::min<long long>(work_items, (long long)device_cus() * per_cu));
+  const size_t P = (size_t)m.mlp_params;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  p.off_counts = take((size_t)p.nbb * nb * 4);
+  p.off_offsets = take((size_t)p.nbb * nb * 4);
+  p.off_total = take((size_t)nb * 4);
+  p.off_base = take((size_t)(nb + 1) * 4);
+  p.off_ibase = take((size_t)(nb + 1) * 4);
+  p.off_misc = take(64);
+  p.off_list = take((size_t)4 * n * 4);
+  p.off_part_lat = take((size_t)p.max_items * rmax * 4);
+  p.off_part_dw = take((size_t)p.grid * P * 4);
+  p.off_part_loss = take((size_t)p.grid * 4);
+  p.off_tmp = take((size_t)kDwYBlocks * P * 4);
+  p.off_grad = take(P * 4);
+  p.total = o;
+  p.supported_bins = nb <= kMaxBins;
+  return p;
 }
 
-hipError_t launch_train_fused(const ntc_material& m, bool f16, const TrainLaunch& a, hipStream_t s) {
-#define NTC_X(a_, b, cc, h)                                                              \
-  if (m.c0 == a_ && m.c1 == b && m.channels == cc && m.hidden == h)                      \
-    return f16 ? fused_t<_Float16, a_, b, cc, h>(m, a, s) : fused_t<float, a_, b, cc, h>(m, a, s);
+hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& l,
+                                  hipStream_t s) {
+  char* ws = (char*)l.workspace;
+  const DevMat dm = dev_mat(m);
+  if (l.scatter_latents) {
+    BinArgs b;
+    b.q = l.q;
+    b.n = l.n;
+    b.per_block = p.per_bin_block;
+    b.nbb = p.nbb;
+    b.counts = (int*)(ws + p.off_counts);
+    b.offsets = (const int*)(ws + p.off_offsets);
+    b.base = (const int*)(ws + p.off_base);
+    b.list = (int*)(ws + p.off_list);
+    const size_t lds = (size_t)p.nbins * 4;
+    hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, p.nbins, p.nbb, (const int*)(ws + p.off_counts),
+                       (int*)(ws + p.off_offsets), (int*)(ws + p.off_total), (int*)(ws + p.off_base),
+                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
+    hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define NTC_X(a_, b_, cc, h)                                                                     \
+  if (m.c0 == a_ && m.c1 == b_ && m.channels == cc && m.hidden == h)                             \
+    e = f16 ? fused_t<_Float16, a_, b_, cc, h>(m, p, l, s) : fused_t<float, a_, b_, cc, h>(m, p, l, s);
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
-  return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  if (l.scatter_latents) {
+    const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
+    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.nbins), dim3(256), 0, s, dm, p.tg,
+                       (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad);
+  }
+  return hipGetLastError();
 }
 
-hipError_t launch_reduce(const ntc_material& m, int grid, const float* part_dw, const float* part_loss, float* grad,
-                         float* loss_out, float loss_norm, int32_t* overflow_flag, hipStream_t s) {
+hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
+                               float loss_norm, int32_t* overflow_flag, hipStream_t s) {
+  char* ws = (char*)workspace;
   const long long P = m.mlp_params;
-  const int blocks = (int)std::max<long long>(1, std::min<long long>((P + 255) / 256, 4096));
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, s, grid, P, part_dw, part_loss, grad, loss_out,
-                     loss_norm, overflow_flag);
+  hipLaunchKernelGGL(dw_reduce1, dim3((unsigned)((P + 63) / 64), kDwYBlocks), dim3(256), 0, s, p.grid, P,
+                     (const float*)(ws + p.off_part_dw), (float*)(ws + p.off_tmp));
+  const int blocks = (int)std::max<long long>(1, std::min<long long>((P + 255) / 256, 1024));
+  hipLaunchKernelGGL(dw_reduce2, dim3(blocks), dim3(256), 0, s, kDwYBlocks, P,
+                     (const float*)(ws + p.off_tmp), (float*)(ws + p.off_grad), p.grid,
+                     (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag);
   return hipGetLastError();
 }
 

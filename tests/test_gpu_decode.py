@@ -134,3 +134,28 @@ def test_decode_zero_queries_is_noop(lib):
                torch.zeros(12, dtype=torch.uint8, device="cuda"), 0, out, lib.F32)
     torch.cuda.synchronize()
     assert torch.all(out == 7.0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_decode_full_size_sampled(lib, prec):
+    """The decode workload itself (4096^2 x 16, 2/4-bit, 13 mips, 16M random queries in one
+    launch); 65,536 sampled outputs are checked against the oracle."""
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    m = lib.material_init(4096, 4096, 16, 16, 16, 2, 4, 64)
+    g = geometry(m)
+    raw = synth.uniform_latents(7, int(m.latent_count))
+    mlp = mlp_in_unit_range(7, g.K, 64, 16)
+    n = 16 * 2 ** 20
+    q = synth.random_queries(7, n, g.M)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    out = torch.empty(n * 16, dtype=torch.float16, device="cuda")
+    lib.decode(m, _packed(lib, m, raw), wp, P, queries_dev(q), n, out, lib.F16)
+    torch.cuda.synchronize()
+    pick = synth.random_param_indices(8, 65536, n)
+    got = out.view(n, 16)[torch.from_numpy(pick).cuda()].float().cpu().numpy().astype(np.float64)
+    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q[pick])
+    err = np.max(np.abs(got - ref))
+    print(f"full-size decode {prec} (FP16 output): max-abs err {err:.3e} on {len(pick)} sampled queries")
+    assert err <= (1e-3 if prec == "f32" else 3e-3)  # includes the FP16 rounding of the output

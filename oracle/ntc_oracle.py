@@ -386,6 +386,30 @@ def mlp_forward(params, x, K, Hd, C, act="relu"):
     return y, (z1, h1, z2, h2)
 
 
+def relu_decisions_fp16(params, x, K, Hd, C):
+    """ReLU decisions (z > 0) of both hidden layers taken the way an FP16 matrix-core
+    evaluation takes them: inputs, weights and hidden activations rounded to FP16,
+    products accumulated in FP32.  Used only to compare an FP16 evaluation with the
+    float64 arithmetic under the same decisions (a decision near z = 0 legitimately
+    differs between precisions)."""
+    W1, b1, W2, b2, W3, b3 = mlp_split(params, K, Hd, C)
+    h = lambda a: np.asarray(a, dtype=np.float16).astype(np.float32)
+    z1 = h(x) @ h(W1) + b1.astype(np.float32)
+    m1 = z1 > 0
+    z2 = h(np.maximum(z1, 0)) @ h(W2) + b2.astype(np.float32)
+    return m1, z2 > 0
+
+
+def mlp_forward_masked(params, x, K, Hd, C, masks):
+    """Forward with given ReLU decisions (float64 values): h = z * mask."""
+    W1, b1, W2, b2, W3, b3 = mlp_split(params, K, Hd, C)
+    z1 = x @ W1 + b1
+    h1 = z1 * masks[0]
+    z2 = h1 @ W2 + b2
+    h2 = z2 * masks[1]
+    return h2 @ W3 + b3, (z1, h1, z2, h2)
+
+
 def decode(geom: Geometry, lat, params, queries):
     """Decode every channel of each queried texel (sections 4.3-4.4)."""
     x, _ = sample_inputs(geom, lat, queries)
@@ -403,7 +427,7 @@ def _targets_at(geom: Geometry, targets, rec):
     return t
 
 
-def loss_and_grads(geom: Geometry, lat_fwd, params, queries, targets=None, dout=None):
+def loss_and_grads(geom: Geometry, lat_fwd, params, queries, targets=None, dout=None, decisions=None):
     """L2 loss (section 4.5) and its exact gradient w.r.t. MLP parameters and latents.
 
     L = (1/(n C)) sum (y - t)^2.  With `dout` given instead of targets, the output
@@ -414,8 +438,17 @@ def loss_and_grads(geom: Geometry, lat_fwd, params, queries, targets=None, dout=
     """
     K, Hd, C = geom.K, geom.Hd, geom.C
     x, rec = sample_inputs(geom, lat_fwd, queries)
-    y, (z1, h1, z2, h2) = mlp_forward(params, x, K, Hd, C, geom.act)
+    masks = None
+    if decisions == "fp16":
+        if geom.act != "relu":
+            raise ValueError("decision matching is defined for ReLU")
+        masks = relu_decisions_fp16(params, x, K, Hd, C)
+        y, (z1, h1, z2, h2) = mlp_forward_masked(params, x, K, Hd, C, masks)
+    else:
+        y, (z1, h1, z2, h2) = mlp_forward(params, x, K, Hd, C, geom.act)
     W1, b1, W2, b2, W3, b3 = mlp_split(params, K, Hd, C)
+    agrad = (lambda z, k: masks[k].astype(np.float64)) if masks is not None else \
+        (lambda z, k: activation_grad(z, geom.act))
     n = x.shape[0]
     if dout is None:
         t = _targets_at(geom, targets, rec)
@@ -427,10 +460,10 @@ def loss_and_grads(geom: Geometry, lat_fwd, params, queries, targets=None, dout=
         dy = np.asarray(dout, dtype=np.float64)
     dW3 = h2.T @ dy
     db3 = dy.sum(axis=0)
-    dz2 = (dy @ W3.T) * activation_grad(z2, geom.act)
+    dz2 = (dy @ W3.T) * agrad(z2, 1)
     dW2 = h1.T @ dz2
     db2 = dz2.sum(axis=0)
-    dz1 = (dz2 @ W2.T) * activation_grad(z1, geom.act)
+    dz1 = (dz2 @ W2.T) * agrad(z1, 0)
     dW1 = x.T @ dz1
     db1 = dz1.sum(axis=0)
     dx = dz1 @ W1.T

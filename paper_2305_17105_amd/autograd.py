@@ -1,0 +1,55 @@
+"""torch.autograd.Function over the library's forward and backward kernels.
+
+    y = ntc_decode_fn(material, latents, mlp, queries, precision)
+
+latents (latent_count,) and mlp (mlp_params,) are FP32 CUDA tensors; queries is a
+uint8 CUDA tensor holding n 12-byte ntc_query records.  Gradients flow to latents
+and mlp; the backward recomputes the forward per tile in the HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import ntc
+
+
+def _dout_scale(dout: torch.Tensor) -> float:
+    """Power of two that brings max|dout| near 1/4 (keeps FP16 deltas in range)."""
+    amax = float(dout.abs().max())
+    if not math.isfinite(amax) or amax == 0.0:
+        return 1.0
+    return 2.0 ** round(math.log2(0.25 / amax))
+
+
+class NtcDecodeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, latents, mlp, queries, material, precision):
+        n = queries.numel() // 12
+        C = int(material.channels)
+        wp = torch.empty(ntc.mlp_packed_bytes(material, precision), dtype=torch.uint8, device=latents.device)
+        ntc.pack_mlp(material, mlp, precision, wp)
+        out = torch.empty(n * C, dtype=torch.float32, device=latents.device)
+        ntc.forward(material, latents, wp, precision, queries, n, out)
+        ctx.save_for_backward(latents, mlp, queries)
+        ctx.material, ctx.precision = material, precision
+        return out.view(n, C)
+
+    @staticmethod
+    def backward(ctx, dout):
+        latents, mlp, queries = ctx.saved_tensors
+        m, prec = ctx.material, ctx.precision
+        n = queries.numel() // 12
+        dout = dout.contiguous().float()
+        tp = torch.empty(ntc.train_packed_bytes(m, prec), dtype=torch.uint8, device=latents.device)
+        ntc.pack_mlp_train(m, mlp, prec, tp)
+        gl = torch.empty_like(latents)
+        gm = torch.empty_like(mlp)
+        ws = torch.empty(ntc.backward_workspace_bytes(m, n, prec), dtype=torch.uint8, device=latents.device)
+        ntc.backward(m, latents, mlp, tp, prec, queries, n, dout, _dout_scale(dout), gl, gm, ws)
+        return gl, gm, None, None, None
+
+
+def ntc_decode_fn(material, latents, mlp, queries, precision=ntc.F32):
+    return NtcDecodeFn.apply(latents, mlp, queries, material, precision)

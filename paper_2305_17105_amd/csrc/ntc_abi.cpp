@@ -327,6 +327,9 @@ ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, 
   a.scale_slot = hp->step & 1;
   a.overflow_flag = s->scale_state + 1;
   a.scatter_latents = !hp->freeze_latents;
+  a.dout = nullptr;
+  a.dout_scale = 1.f;
+  a.out_scale = 1.f;
   return hip_status(launch_train_gradients(*m, f16, plan, a, (hipStream_t)stream), "ntc_train_gradients");
 }
 
@@ -372,6 +375,74 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
     e = launch_adam(*m, ad, hs);
   }
   return hip_status(e, "ntc_train_update");
+}
+
+ntc_status ntc_pack_mlp_train(const ntc_material* m, const float* mlp, ntc_dtype precision, void* packed,
+                              void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "pack precision must be F32 or F16");
+  if (!mlp || !packed) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_pack_mlp(*m, mlp, precision == NTC_F16, true, packed, (hipStream_t)stream),
+                    "ntc_pack_mlp_train");
+}
+
+ntc_status ntc_forward(const ntc_material* m, const float* latents, const void* mlp_packed, ntc_dtype precision,
+                       const ntc_query* q, int64_t n, float* out, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  if (n < 0) return fail(NTC_E_INVALID, "n < 0");
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no kernel for this (c0, c1, channels, hidden)");
+  if (n == 0) return NTC_OK;
+  if (!latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_forward(*m, latents, mlp_packed, precision == NTC_F16, q, n, out, (hipStream_t)stream),
+                    "ntc_forward");
+}
+
+size_t ntc_backward_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
+  return ntc_train_workspace_bytes(m, n, precision);
+}
+
+ntc_status ntc_backward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
+                        ntc_dtype precision, const ntc_query* q, int64_t n, const float* dout, float dout_scale,
+                        float* grad_latents, float* grad_mlp, void* workspace, size_t ws_bytes, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no kernel for this (c0, c1, channels, hidden)");
+  if (n <= 0) return fail(NTC_E_INVALID, "n must be positive");
+  if (!latents || !mlp || !mlp_train_packed || !q || !dout || !grad_latents || !grad_mlp)
+    return fail(NTC_E_INVALID, "NULL buffer");
+  if (!(dout_scale > 0.f) || !std::isfinite(dout_scale)) return fail(NTC_E_INVALID, "dout_scale must be positive");
+  const bool f16 = precision == NTC_F16;
+  const TrainPlan plan = train_plan(*m, f16, n);
+  if (!plan.supported_bins) return fail(NTC_E_UNSUPPORTED, "too many latent tiles for this material");
+  if (!workspace || ws_bytes < plan.total) return fail(NTC_E_WORKSPACE, "workspace too small");
+  hipStream_t hs = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  TrainLaunch a;
+  a.lat_fwd = latents;
+  a.wpack = mlp_train_packed;
+  a.mlp = mlp;
+  a.q = q;
+  a.n = n;
+  a.targets = nullptr;
+  a.lat_grad = grad_latents;
+  a.workspace = workspace;
+  a.loss_scale = nullptr;
+  a.scale_slot = 0;
+  a.overflow_flag = (int32_t*)(ws + plan.off_misc + 16);
+  a.scatter_latents = true;
+  a.dout = dout;
+  a.dout_scale = dout_scale;
+  a.out_scale = 1.f / dout_scale;
+  hipError_t e = launch_train_gradients(*m, f16, plan, a, hs);
+  if (e == hipSuccess)
+    e = launch_train_reduce(*m, plan, workspace, nullptr, 0.f, nullptr, hs, grad_mlp, 1.f / dout_scale);
+  return hip_status(e, "ntc_backward");
 }
 
 ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,

@@ -52,11 +52,17 @@ struct TrainLaunch {
   int scale_slot;
   int32_t* overflow_flag;   // reset by the fused kernel
   bool scatter_latents;     // false: latents frozen, samples processed in query order
+  const float* dout;        // external output gradient, or nullptr (L2 loss against targets)
+  float dout_scale;
+  float out_scale;          // multiplies the latent gradient written to lat_grad
 };
 hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& a,
                                   hipStream_t s);
 hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
-                               float loss_norm, int32_t* overflow_flag, hipStream_t s);
+                               float loss_norm, int32_t* overflow_flag, hipStream_t s, float* grad_out = nullptr,
+                               float out_scale = 1.f);
+hipError_t launch_forward(const ntc_material& m, const float* latents, const void* wpack, bool f16, const ntc_query* q,
+                          long long n, float* out, hipStream_t s);
 
 struct AdamLaunch {
   float* latents;

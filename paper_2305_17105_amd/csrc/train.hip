@@ -57,6 +57,9 @@ struct TrainArgs {
   int binned;
   int region_max;
   float inv_nc;
+  const float* dout;   // external output gradient (differentiation path) or nullptr
+  float dout_scale;    // multiplies dout before the backward (FP16 range)
+  float out_scale;     // multiplies the latent gradient written out
   TileGeom tg;
 };
 
@@ -288,9 +291,13 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
           const int c = 4 * g + i;
           float d = 0.f;
           if (valid && c < C) {
-            const float e = y[i] - a.targets[tb + c];
-            if (primary) loss += e * e;
-            d = 2.f * e * a.inv_nc * scale;
+            if (a.dout) {
+              d = a.dout[s * C + c] * a.dout_scale;
+            } else {
+              const float e = y[i] - a.targets[tb + c];
+              if (primary) loss += e * e;
+              d = 2.f * e * a.inv_nc * scale;
+            }
           }
           dyT[i] = (T)d;
         }
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
             const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
             gi = tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
           }
-          a.lat_grad[gi] = reg[k];
+          a.lat_grad[gi] = reg[k] * a.out_scale;
         }
       } else {
         float* dst = a.part_lat + (long long)item * a.region_max;
@@ -480,8 +487,8 @@ struct BinArgs {
   long long n;
   int per_block;
   int nbb;
-  int* counts;         // [nbb][nbins]
-  const int* offsets;  // [nbb][nbins], relative to the bin base
+  int* counts;         // [nbins][nbb]
+  const int* offsets;  // [nbins][nbb], relative to the bin base
   const int* base;     // [nbins + 1]
   int* list;
 };
@@ -491,7 +498,7 @@ __global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs
   extern __shared__ int hist[];
   const int nb = tg.nbins;
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)blockIdx.x * nb + b] : 0;
+    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)b * a.nbb + blockIdx.x] : 0;
   __syncthreads();
   const long long s0 = (long long)blockIdx.x * a.per_block;
   const long long s1 = min(a.n, s0 + a.per_block);
@@ -508,34 +515,60 @@ __global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs
   }
   if (!SCATTER) {
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)blockIdx.x * nb + b] = hist[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)b * a.nbb + blockIdx.x] = hist[b];
   }
 }
 
-// One block of 1024 threads: per-bin totals and per-block offsets, exclusive scans of
-// the totals (bin bases) and of the work items per bin.
-__global__ __launch_bounds__(1024) void bin_scan_kernel(int nbins, int nbb, const int* __restrict__ counts,
-                                                        int* __restrict__ offsets, int* __restrict__ total,
-                                                        int* __restrict__ base, int* __restrict__ item_base,
-                                                        int* __restrict__ nitems) {
-  __shared__ int s_tot[1024], s_items[1024];
-  const int tid = threadIdx.x;
-  for (int b = tid; b < nbins; b += 1024) {
-    int run = 0;
-    for (int k = 0; k < nbb; ++k) {
-      const int c = counts[(long long)k * nbins + b];
-      offsets[(long long)k * nbins + b] = run;
-      run += c;
-    }
-    total[b] = run;
+// Per-bin column scan over the binning blocks: one wavefront per bin, each lane
+// holds 4 consecutive blocks (nbb <= 256).  Writes the per-block offsets and the
+// bin total.
+__global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, const int* __restrict__ counts,
+                                                        int* __restrict__ offsets, int* __restrict__ total) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= nbins) return;
+  int v[4];
+  int sum = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = lane * 4 + e;
+    v[e] = k < nbb ? counts[(long long)b * nbb + k] : 0;
+    sum += v[e];
   }
-  __syncthreads();
+  int incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  int run = incl - sum;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = lane * 4 + e;
+    if (k < nbb) offsets[(long long)b * nbb + k] = run;
+    run += v[e];
+  }
+  if (lane == 63) total[b] = incl;
+}
+
+// One block of 1024 threads: exclusive scans over the bins of the totals (bin bases)
+// and of the work items per bin (at most kChunk samples per item, at least one).
+__global__ __launch_bounds__(1024) void bin_scan2_kernel(int nbins, const int* __restrict__ total,
+                                                         int* __restrict__ base, int* __restrict__ item_base,
+                                                         int* __restrict__ nitems) {
+  __shared__ int s_tot[1024], s_items[1024];
+  constexpr int kPer = kMaxBins / 1024;
+  const int tid = threadIdx.x;
   const int per = (nbins + 1023) / 1024;
-  const int b0 = min(nbins, tid * per), b1 = min(nbins, b0 + per);
+  const int b0 = min(nbins, tid * per);
+  int tv[kPer];
   int st = 0, si = 0;
-  for (int b = b0; b < b1; ++b) {
-    st += total[b];
-    si += max(1, (total[b] + kChunk - 1) / kChunk);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int b = b0 + e;
+    tv[e] = (e < per && b < nbins) ? total[b] : 0;
+    st += tv[e];
+    si += (e < per && b < nbins) ? max(1, (tv[e] + kChunk - 1) / kChunk) : 0;
   }
   s_tot[tid] = st;
   s_items[tid] = si;
@@ -549,11 +582,15 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(int nbins, int nbb, cons
     __syncthreads();
   }
   int pt = s_tot[tid] - st, pi = s_items[tid] - si;  // exclusive prefixes
-  for (int b = b0; b < b1; ++b) {
-    base[b] = pt;
-    item_base[b] = pi;
-    pt += total[b];
-    pi += max(1, (total[b] + kChunk - 1) / kChunk);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int b = b0 + e;
+    if (e < per && b < nbins) {
+      base[b] = pt;
+      item_base[b] = pi;
+      pt += tv[e];
+      pi += max(1, (tv[e] + kChunk - 1) / kChunk);
+    }
   }
   if (tid == 1023) {
     base[nbins] = s_tot[1023];
@@ -564,7 +601,8 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(int nbins, int nbb, cons
 
 // Latent gradients of tiles split over several work items: partials summed in item order.
 __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
-                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad) {
+                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
+                                   float out_scale) {
   const int bin = blockIdx.y;
   const int it0 = item_base[bin], items = item_base[bin + 1] - it0;
   if (items <= 1) return;
@@ -577,6 +615,7 @@ __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict_
   const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < RG; k += gridDim.x * blockDim.x) {
     float s = 0.f;
+#pragma unroll 8
     for (int i = 0; i < items; ++i) s += part[(long long)(it0 + i) * region_max + k];
     long long gi;
     if (k < R0) {
@@ -586,7 +625,7 @@ __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict_
       const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
       gi = m.g1_off[j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
     }
-    lat_grad[gi] = s;
+    lat_grad[gi] = s * out_scale;
   }
 }
 
@@ -614,11 +653,11 @@ __global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const floa
 // Stage 2: final sum, non-finite flag, loss.
 __global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp, float* __restrict__ grad,
                            int G, const float* __restrict__ part_loss, float* __restrict__ loss_out, float norm,
-                           int32_t* flag) {
+                           int32_t* flag, float out_scale) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
     float s = 0.f;
     for (int k = 0; k < parts; ++k) s += tmp[(long long)k * P + p];
-    grad[p] = s;
+    grad[p] = s * out_scale;
     if (flag && !isfinite(s)) atomicOr(flag, 1);
   }
   if (blockIdx.x == 0 && loss_out) {
@@ -768,6 +807,9 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.binned = l.scatter_latents ? 1 : 0;
   a.region_max = p.region_max;
   a.inv_nc = (float)(1.0 / ((double)l.n * C));
+  a.dout = l.dout;
+  a.dout_scale = l.dout_scale;
+  a.out_scale = l.out_scale;
   a.tg = p.tg;
   hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
                      pe_table(), a);
@@ -862,9 +904,10 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     b.list = (int*)(ws + p.off_list);
     const size_t lds = (size_t)p.nbins * 4;
     hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, p.nbins, p.nbb, (const int*)(ws + p.off_counts),
-                       (int*)(ws + p.off_offsets), (int*)(ws + p.off_total), (int*)(ws + p.off_base),
-                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
+    hipLaunchKernelGGL(bin_scan1_kernel, dim3((p.nbins + 3) / 4), dim3(256), 0, s, p.nbins, p.nbb,
+                       (const int*)(ws + p.off_counts), (int*)(ws + p.off_offsets), (int*)(ws + p.off_total));
+    hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.nbins, (const int*)(ws + p.off_total),
+                       (int*)(ws + p.off_base), (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
     hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
   }
   hipError_t e = hipGetLastError();
@@ -878,21 +921,23 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   if (l.scatter_latents) {
     const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
     hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.nbins), dim3(256), 0, s, dm, p.tg,
-                       (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad);
+                       (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad,
+                       l.out_scale);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
-                               float loss_norm, int32_t* overflow_flag, hipStream_t s) {
+                               float loss_norm, int32_t* overflow_flag, hipStream_t s, float* grad_out,
+                               float out_scale) {
   char* ws = (char*)workspace;
   const long long P = m.mlp_params;
   hipLaunchKernelGGL(dw_reduce1, dim3((unsigned)((P + 63) / 64), kDwYBlocks), dim3(256), 0, s, p.grid, P,
                      (const float*)(ws + p.off_part_dw), (float*)(ws + p.off_tmp));
   const int blocks = (int)std::max<long long>(1, std::min<long long>((P + 255) / 256, 1024));
   hipLaunchKernelGGL(dw_reduce2, dim3(blocks), dim3(256), 0, s, kDwYBlocks, P,
-                     (const float*)(ws + p.off_tmp), (float*)(ws + p.off_grad), p.grid,
-                     (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag);
+                     (const float*)(ws + p.off_tmp), grad_out ? grad_out : (float*)(ws + p.off_grad), p.grid,
+                     (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag, out_scale);
   return hipGetLastError();
 }
 

@@ -78,6 +78,12 @@ _sig = {
                                       _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
     "ntc_train_update": (C.c_int, [_P(Material), _P(TrainStateC), C.c_int64, _P(HParams), C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
+    "ntc_pack_mlp_train": (C.c_int, [_P(Material), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "ntc_forward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                              C.c_void_p]),
+    "ntc_backward_workspace_bytes": (C.c_size_t, [_P(Material), C.c_int64, C.c_int]),
+    "ntc_backward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                               C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -182,6 +188,27 @@ def train_gradients(m: Material, state: "TrainState", queries, n, targets, hp: H
 def train_update(m: Material, state: "TrainState", n, hp: HParams, workspace, stream=None):
     _check(_lib.ntc_train_update(C.byref(m), C.byref(state.c), n, C.byref(hp), _ptr(workspace),
                                  workspace.numel() * workspace.element_size(), _stream(stream)), "ntc_train_update")
+
+
+def pack_mlp_train(m: Material, mlp, precision, packed, stream=None):
+    _check(_lib.ntc_pack_mlp_train(C.byref(m), _ptr(mlp), precision, _ptr(packed), _stream(stream)),
+           "ntc_pack_mlp_train")
+
+
+def forward(m: Material, latents, mlp_packed, precision, queries, n, out, stream=None):
+    _check(_lib.ntc_forward(C.byref(m), _ptr(latents), _ptr(mlp_packed), precision, _ptr(queries), n, _ptr(out),
+                            _stream(stream)), "ntc_forward")
+
+
+def backward_workspace_bytes(m: Material, n: int, precision=F32) -> int:
+    return int(_lib.ntc_backward_workspace_bytes(C.byref(m), n, precision))
+
+
+def backward(m: Material, latents, mlp, mlp_train_packed, precision, queries, n, dout, dout_scale, grad_latents,
+             grad_mlp, workspace, stream=None):
+    _check(_lib.ntc_backward(C.byref(m), _ptr(latents), _ptr(mlp), _ptr(mlp_train_packed), precision, _ptr(queries),
+                             n, _ptr(dout), float(dout_scale), _ptr(grad_latents), _ptr(grad_mlp), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream(stream)), "ntc_backward")
 
 
 def hparams(lr_latent=0.01, lr_mlp=0.005, step=0, precision=F32, noise=True, freeze=False, seed=0,

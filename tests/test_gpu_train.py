@@ -232,6 +232,12 @@ def test_gradients_fp16(lib, name):
     for k, v in errs.items():
         assert v <= 2e-2, (k, v)
     assert run.get("scale_state")[1] == 0
+    # same comparison with the ReLU decisions taken in FP16: rounding error only
+    _, gp_d, gl_d, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, run.targets, decisions="fp16")
+    derrs = {"mlp": rel_err(gp_gpu, gp_d), "latents": rel_err(gl_gpu, gl_d)}
+    print("fp16 vs decision-matched oracle:", {k: f"{v:.2e}" for k, v in derrs.items()})
+    for v in derrs.values():
+        assert v <= 5e-3
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])

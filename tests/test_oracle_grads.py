@@ -120,3 +120,37 @@ def test_latent_gradient_conservation():
     dz1 = (dz2 @ W2.T) * (z1 > 0)
     dx = dz1 @ W1.T
     assert gl.sum() == pytest.approx(dx[:, :4 * g.C0 + g.C1].sum(), rel=1e-10)
+
+
+def test_decision_matched_mode_is_the_fp64_gradient_under_those_decisions():
+    """On samples whose FP16-taken ReLU decisions agree with the float64 ones, the
+    decision-matched mode returns exactly the float64 loss and gradients; on the full
+    batch it returns the gradient of the masked function (torch autograd, fixed masks)."""
+    g, params, lat, q, tgt = _setup("relu", n=3000, seed=4)
+    x, _ = O.sample_inputs(g, lat, q)
+    m16 = O.relu_decisions_fp16(params, x, g.K, g.Hd, g.C)
+    _, (z1, _, z2, _) = O.mlp_forward(params, x, g.K, g.Hd, g.C)
+    agree = np.all(m16[0] == (z1 > 0), axis=1) & np.all(m16[1] == (z2 > 0), axis=1)
+    assert 0 < agree.sum() < len(q)          # some decisions do flip at FP16
+    qa = q[agree]
+    a = O.loss_and_grads(g, lat, params, qa, tgt)
+    b = O.loss_and_grads(g, lat, params, qa, tgt, decisions="fp16")
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    # full batch: gradient of the masked function
+    _, gp, gl, _ = O.loss_and_grads(g, lat, params, q, tgt, decisions="fp16")
+    _, rec = O.sample_inputs(g, lat, q)
+    K, Hd, C = g.K, g.Hd, g.C
+    tp = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    tx = torch.tensor(x, dtype=torch.float64)
+    W1 = tp[:K * Hd].reshape(K, Hd); o = K * Hd
+    b1 = tp[o:o + Hd]; o += Hd
+    W2 = tp[o:o + Hd * Hd].reshape(Hd, Hd); o += Hd * Hd
+    b2 = tp[o:o + Hd]; o += Hd
+    W3 = tp[o:o + Hd * C].reshape(Hd, C); o += Hd * C
+    b3 = tp[o:o + C]
+    h1 = (tx @ W1 + b1) * torch.tensor(m16[0], dtype=torch.float64)
+    h2 = (h1 @ W2 + b2) * torch.tensor(m16[1], dtype=torch.float64)
+    y = h2 @ W3 + b3
+    t = torch.tensor(O._targets_at(g, tgt, rec))
+    ((y - t) ** 2).mean().backward()
+    assert np.allclose(gp, tp.grad.numpy(), rtol=1e-10, atol=1e-14)

@@ -233,10 +233,26 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
 // ------------------------------------------------------------------ spatial tiles of the latent grids
 // Level j's G0 grid is cut into T x T cell tiles (T = min(Tmax, grid side)); the G1
 // grid into the matching (T/2) x (T/2) tiles.  A tile owns the latents of its cells.
+// Samples are counting-sorted into bins: one bin per tile (sb = 1) or, on levels
+// with few cells, one bin per (tile, anchor cell) (sb = T), which orders a tile's
+// samples by anchor cell.  A tile's bins are consecutive.
 struct TileGeom {
-  int T[kMaxLevels], ntx[kMaxLevels], nty[kMaxLevels], base[kMaxLevels + 1], region[kMaxLevels];
-  int nbins, region_max;
+  int T[kMaxLevels], ntx[kMaxLevels], nty[kMaxLevels], sb[kMaxLevels];
+  int tile_base[kMaxLevels + 1];  // first tile of each level
+  int bin_base[kMaxLevels + 1];   // first sort bin of each level
+  int region[kMaxLevels];
+  int ntiles, nbins, region_max;
 };
+
+__host__ __device__ inline int sort_bin(const TileGeom& tg, int j, int tx, int ty, int ax, int ay) {
+  const int sb = tg.sb[j], T = tg.T[j];
+  const int tile = ty * tg.ntx[j] + tx;
+  if (sb == 1) return tg.bin_base[j] + tile;
+  int sx = ax - tx * T, sy = ay - ty * T;
+  sx = sx < 0 ? 0 : (sx > T - 1 ? T - 1 : sx);
+  sy = sy < 0 ? 0 : (sy > T - 1 ? T - 1 : sy);
+  return tg.bin_base[j] + tile * T * T + sy * T + sx;
+}
 
 // Tiles whose latents a sample's footprint touches: columns [tx0, tx1], rows [ty0, ty1]
 // (each range spans at most two tiles), and the primary tile holding the clamped anchor.
@@ -254,6 +270,15 @@ __device__ inline SampleBins sample_bins(const Footprint& f, const TileGeom& tg)
   b.ptx = f.ax / T;
   b.pty = f.ay / T;
   return b;
+}
+
+// Sum over the 16 lanes of a row (lane group), by rotations within the row (DPP).
+__device__ inline float row_sum16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x122, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
+  return v;
 }
 
 // The three positional-encoding values of lane group g (slots 3g..3g+2 of the 12).

@@ -31,10 +31,11 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
 // Launch plan of a training step: tile geometry, grids and workspace layout (bytes).
 struct TrainPlan {
   TileGeom tg;
-  int nbins, region_max, nbb, per_bin_block, grid;
+  int nbins, ntiles, region_max, nbb, per_bin_block, grid;
   long long max_items;
   bool supported_bins;
-  size_t off_counts, off_offsets, off_total, off_base, off_ibase, off_misc, off_list, off_part_lat;
+  size_t off_counts, off_offsets, off_total, off_base, off_tstart, off_ttotal, off_ibase, off_misc, off_list;
+  size_t off_part_lat;
   size_t off_part_dw, off_part_loss, off_tmp, off_grad, total;
 };
 TrainPlan train_plan(const ntc_material& m, bool f16, long long n);

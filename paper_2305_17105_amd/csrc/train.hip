@@ -33,6 +33,7 @@ namespace ntc {
 constexpr int kChunk = 512;       // samples per work item
 constexpr int kBinBlockSamples = 1024;
 constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
+constexpr int kSortedCells = 4096; // levels with at most this many G0 cells are sorted by anchor cell
 constexpr int kDwYBlocks = 4;     // block rows of the first weight-gradient reduction stage (x4 row groups each)
 
 struct TrainArgs {
@@ -45,9 +46,9 @@ struct TrainArgs {
   float* lat_grad;
   float* part_lat;
   const int* list;
-  const int* bin_total;
-  const int* bin_base;
-  const int* item_base;
+  const int* tile_start;   // first list position of each tile's samples
+  const int* tile_total;   // number of list entries of each tile
+  const int* item_base;    // first work item of each tile (ntiles + 1)
   const int* nitems;
   float* part_dw;
   float* part_loss;
@@ -96,6 +97,29 @@ __device__ inline f32x4 dw_tile(f32x4 acc, const T* buf, int rowA, int rowB, int
 
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
 
+// Sum of columns 16q .. 16q+15 of LDS row `row` (a quarter of the 64 texels).
+template <typename T>
+__device__ inline float row_quarter_sum(const T* buf, int row, int q) {
+  constexpr int RS = lds_row_stride<T>();
+  const T* p = buf + row * RS + 16 * q;
+  float s = 0.f;
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const f32x4 v = reinterpret_cast<const f32x4*>(p)[k];
+      s += (v[0] + v[1]) + (v[2] + v[3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const f16x8 v = reinterpret_cast<const f16x8*>(p)[k];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s += (float)v[e];
+    }
+  }
+  return s;
+}
+
 template <typename T, int C0, int C1, int C, int HD>
 struct TrainCfg {
   using IS = InSlots<C0, C1>;
@@ -104,7 +128,10 @@ struct TrainCfg {
   static constexpr int MT1 = (S1 + 3) / 4;         // dW1 M-tiles (X slot rows 4t+g)
   static constexpr int RX = 16 * MT1;               // X rows in the transpose buffer
   static constexpr int RS = lds_row_stride<T>();
-  static constexpr int TR = cmax(cmax(RX + HD, 2 * HD), HD + 16);
+  // one-phase weight-gradient staging: rows X | H1 | H2 | dZ1 | dZ2 | dY
+  static constexpr int RH1 = RX, RH2 = RX + HD, RDZ1 = RX + 2 * HD, RDZ2 = RX + 3 * HD, RDY = RX + 4 * HD;
+  static constexpr int TR1 = RX + 4 * HD + 16;
+  static constexpr int TR3 = cmax(cmax(RX + HD, 2 * HD), HD + 16);  // three-phase staging
   static constexpr int NT2 = (MT * MT + 3) / 4;     // dW2 tiles per wavefront
   static constexpr int NT1 = (MT1 * MT + 3) / 4;    // dW1 tiles per wavefront
   static constexpr long long K = 4 * C0 + C1 + 12;
@@ -117,9 +144,13 @@ struct TrainCfg {
   static constexpr int OFF_TAB = OFF_BIAS + (2 * HD + 16) * 4;  // g0_off[8], g1_off[8], mip_off[16]
   static constexpr int OFF_RED = OFF_TAB + 32 * 8;
   static constexpr int OFF_BUF = (OFF_RED + 16 + 15) / 16 * 16;
-  static constexpr int OFF_REG = OFF_BUF + (TR * RS * (int)sizeof(T) + 15) / 16 * 16;
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
   static constexpr int kLdsCap = 160 * 1024;
+  static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
+  // one-phase staging when it fits next to a tile of at least 16 x 16 cells
+  static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 4 <= kLdsCap;
+  static constexpr int TR = ONE_PHASE ? TR1 : TR3;
+  static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
   // largest tile side whose owned-latent gradient fits next to the rest
   static constexpr int TMAX = OFF_REG + region(32) * 4 <= kLdsCap ? 32 : OFF_REG + region(16) * 4 <= kLdsCap ? 16 : 8;
   static constexpr int LDS = OFF_REG + region(TMAX) * 4;
@@ -178,23 +209,25 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
     int j = 0, tx = 0, ty = 0, T_ = 2, cnt;
     long long start;
     bool single = true;
+    bool sorted = false;
     if (a.binned) {
-      int lo = 0, hi = a.tg.nbins;
+      int lo = 0, hi = a.tg.ntiles;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (a.item_base[mid] <= item) lo = mid;
         else hi = mid;
       }
-      const int bin = lo;
-      const int chunk = item - a.item_base[bin];
-      single = (a.item_base[bin + 1] - a.item_base[bin]) == 1;
-      start = (long long)a.bin_base[bin] + (long long)chunk * kChunk;
-      cnt = min(kChunk, a.bin_total[bin] - chunk * kChunk);
-      while (j + 1 < m.J && bin >= a.tg.base[j + 1]) ++j;
-      const int t = bin - a.tg.base[j];
+      const int tile = lo;
+      const int chunk = item - a.item_base[tile];
+      single = (a.item_base[tile + 1] - a.item_base[tile]) == 1;
+      start = (long long)a.tile_start[tile] + (long long)chunk * kChunk;
+      cnt = min(kChunk, a.tile_total[tile] - chunk * kChunk);
+      while (j + 1 < m.J && tile >= a.tg.tile_base[j + 1]) ++j;
+      const int t = tile - a.tg.tile_base[j];
       tx = t % a.tg.ntx[j];
       ty = t / a.tg.ntx[j];
       T_ = a.tg.T[j];
+      sorted = a.tg.sb[j] > 1;
     } else {
       start = (long long)item * kChunk;
       cnt = (int)min((long long)kChunk, a.n - start);
@@ -336,82 +369,139 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
 #pragma unroll
           for (int i = 0; i < 4; ++i) dx[4 * mo + i] = d[i];
         }
-        if (valid) {  // gradients of the latents this tile owns, accumulated in LDS
-          if (f.g0x / T_ == tx && f.g0y / T_ == ty) {
-            float* dst = reg + ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) * C0;
+        // Gradients of the latents this tile owns, accumulated in LDS.  On levels whose
+        // samples are sorted by anchor cell, a row (16 samples of one lane group) that
+        // targets a single cell is summed across lanes first (one atomic per channel).
+        const int rr = lane & 15;
+        const bool own0 = valid && f.g0x / T_ == tx && f.g0y / T_ == ty;
+        const int key0 = own0 ? ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) : -1;
+        float* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
+        if (sorted) {
+          const int rk = __shfl(key0, lane & ~15);
+          const unsigned long long bal = __ballot(key0 == rk || !valid);
+          const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
 #pragma unroll
-            for (int t = 0; t < C0; ++t) atomicAdd(dst + t, dx[t]);
+          for (int t = 0; t < C0; ++t) {
+            const float sv = row_sum16(own0 ? dx[t] : 0.f);
+            if (uni) {
+              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, sv);
+            } else if (own0) {
+              atomicAdd(dst0 + t, dx[t]);
+            }
           }
+        } else if (own0) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
-            if (x1 / T1 == tx && y1 / T1 == ty && f.g1_w[k] != 0.f) {
-              float* dst = reg + R0 + ((y1 - ty * T1) * T1 + (x1 - tx * T1)) * C1;
+          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, dx[t]);
+        }
 #pragma unroll
-              for (int i = 0; i < IS::n1max; ++i) {
-                const int ch = g + 4 * i;
-                if (ch < C1) atomicAdd(dst + ch, f.g1_w[k] * dx[C0 + i]);
+        for (int k = 0; k < 4; ++k) {
+          const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
+          const bool own1 = valid && x1 / T1 == tx && y1 / T1 == ty && f.g1_w[k] != 0.f;
+          const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
+          float* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
+          if (sorted) {
+            const int rk = __shfl(key1, lane & ~15);
+            const unsigned long long bal = __ballot(key1 == rk || !valid);
+            const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
+#pragma unroll
+            for (int i = 0; i < IS::n1max; ++i) {
+              const int ch = g + 4 * i;
+              const float v1 = own1 ? f.g1_w[k] * dx[C0 + i] : 0.f;
+              const float sv = row_sum16(v1);
+              if (ch < C1) {
+                if (uni) {
+                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, sv);
+                } else if (own1) {
+                  atomicAdd(dst1 + ch, v1);
+                }
               }
+            }
+          } else if (own1) {
+#pragma unroll
+            for (int i = 0; i < IS::n1max; ++i) {
+              const int ch = g + 4 * i;
+              if (ch < C1) atomicAdd(dst1 + ch, f.g1_w[k] * dx[C0 + i]);
             }
           }
         }
       }
 
       // ---------------- weight gradients through LDS (texels become the K axis);
-      // only a sample's primary copy contributes
+      // only a sample's primary copy contributes.  Bias gradients are row sums of the
+      // deltas: thread (row = tid/4, quarter q = tid%4) adds 16 columns per row.
       const int col = wave * 16 + r;
       const T zero = (T)0.f;
-      // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
+      const int brow = tid >> 2, bq = tid & 3;
+      if constexpr (Cfg::ONE_PHASE) {
+        // all operands at once: X | H1 | H2 | dZ1 | dZ2 | dY
 #pragma unroll
-      for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+        for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
-      __syncthreads();
-      if (wave < MT) acc3 = dw_tile<T>(acc3, buf, 16 * wave, HD, g, r);
-      if (tid < 16) {
-        float sum = 0.f;
-#pragma unroll 8
-        for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
-        db3 += sum;
+        for (int t = 0; t < SH; ++t) {
+          const int h = hid_feature(g, t);
+          buf[(Cfg::RH1 + h) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
+          buf[(Cfg::RH2 + h) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+          buf[(Cfg::RDZ1 + h) * RS + col] = primary ? dz1T[t] : zero;
+          buf[(Cfg::RDZ2 + h) * RS + col] = primary ? dT[t] : zero;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) buf[(Cfg::RDY + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
+        __syncthreads();
+        if (wave < MT) acc3 = dw_tile<T>(acc3, buf, Cfg::RH2 + 16 * wave, Cfg::RDY, g, r);
+#pragma unroll
+        for (int k = 0; k < Cfg::NT2; ++k) {
+          const int id = wave + 4 * k;
+          if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, Cfg::RH1 + 16 * (id / MT), Cfg::RDZ2 + 16 * (id % MT), g, r);
+        }
+#pragma unroll
+        for (int k = 0; k < Cfg::NT1; ++k) {
+          const int id = wave + 4 * k;
+          if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), Cfg::RDZ1 + 16 * (id % MT), g, r);
+        }
+        if (brow < HD) {
+          db1 += row_quarter_sum<T>(buf, Cfg::RDZ1 + brow, bq);
+          db2 += row_quarter_sum<T>(buf, Cfg::RDZ2 + brow, bq);
+        }
+        if (brow < 16) db3 += row_quarter_sum<T>(buf, Cfg::RDY + brow, bq);
+        __syncthreads();
+      } else {
+        // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
+#pragma unroll
+        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
+        __syncthreads();
+        if (wave < MT) acc3 = dw_tile<T>(acc3, buf, 16 * wave, HD, g, r);
+        if (brow < 16) db3 += row_quarter_sum<T>(buf, HD + brow, bq);
+        __syncthreads();
+        // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
+#pragma unroll
+        for (int t = 0; t < SH; ++t) {
+          buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
+          buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < Cfg::NT2; ++k) {
+          const int id = wave + 4 * k;
+          if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
+        }
+        if (brow < HD) db2 += row_quarter_sum<T>(buf, HD + brow, bq);
+        __syncthreads();
+        // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
+#pragma unroll
+        for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
+#pragma unroll
+        for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < Cfg::NT1; ++k) {
+          const int id = wave + 4 * k;
+          if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
+        }
+        if (brow < HD) db1 += row_quarter_sum<T>(buf, RX + brow, bq);
+        __syncthreads();
       }
-      __syncthreads();
-      // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
-#pragma unroll
-      for (int t = 0; t < SH; ++t) {
-        buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
-        buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < Cfg::NT2; ++k) {
-        const int id = wave + 4 * k;
-        if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
-      }
-      if (tid < HD) {
-        float sum = 0.f;
-#pragma unroll 8
-        for (int c = 0; c < 64; ++c) sum += (float)buf[(HD + tid) * RS + c];
-        db2 += sum;
-      }
-      __syncthreads();
-      // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
-#pragma unroll
-      for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
-#pragma unroll
-      for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < Cfg::NT1; ++k) {
-        const int id = wave + 4 * k;
-        if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
-      }
-      if (tid < HD) {
-        float sum = 0.f;
-#pragma unroll 8
-        for (int c = 0; c < 64; ++c) sum += (float)buf[(RX + tid) * RS + c];
-        db1 += sum;
-      }
-      __syncthreads();
     }
 
     // ---------------- the tile's latent gradient: dense plain stores (or a partial)
@@ -470,11 +560,21 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       }
     }
   }
-  if (tid < HD) {
-    part[Cfg::b1o + tid] = db1;
-    part[Cfg::b2o + tid] = db2;
+  // bias gradients: the four quarter sums of each row are in lanes 4*row .. 4*row+3
+  db1 += __shfl_xor(db1, 1);
+  db1 += __shfl_xor(db1, 2);
+  db2 += __shfl_xor(db2, 1);
+  db2 += __shfl_xor(db2, 2);
+  db3 += __shfl_xor(db3, 1);
+  db3 += __shfl_xor(db3, 2);
+  if ((tid & 3) == 0) {
+    const int row = tid >> 2;
+    if (row < HD) {
+      part[Cfg::b1o + row] = db1;
+      part[Cfg::b2o + row] = db2;
+    }
+    if (row < C) part[Cfg::b3o + row] = db3;
   }
-  if (tid < C) part[Cfg::b3o + tid] = db3;
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
   if (lane == 0) red[wave] = loss;
   __syncthreads();
@@ -508,7 +608,7 @@ __global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs
     const SampleBins sb = sample_bins(f, tg);
     for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
       for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
-        const int b = tg.base[sb.j] + ty * tg.ntx[sb.j] + tx;
+        const int b = sort_bin(tg, sb.j, tx, ty, f.ax, f.ay);
         if (SCATTER) a.list[atomicAdd(&hist[b], 1)] = (int)s;
         else atomicAdd(&hist[b], 1);
       }
@@ -551,51 +651,82 @@ __global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, cons
   if (lane == 63) total[b] = incl;
 }
 
-// One block of 1024 threads: exclusive scans over the bins of the totals (bin bases)
-// and of the work items per bin (at most kChunk samples per item, at least one).
-__global__ __launch_bounds__(1024) void bin_scan2_kernel(int nbins, const int* __restrict__ total,
-                                                         int* __restrict__ base, int* __restrict__ item_base,
-                                                         int* __restrict__ nitems) {
-  __shared__ int s_tot[1024], s_items[1024];
-  constexpr int kPer = kMaxBins / 1024;
+// One block of 1024 threads: exclusive scan over the sort bins of their totals (list
+// positions), then per tile its start, total and work items (at most kChunk samples
+// per item, at least one), and the exclusive scan of the items over the tiles.
+template <int PER>
+__device__ inline int block_exclusive_scan(int v, int* sh) {
   const int tid = threadIdx.x;
-  const int per = (nbins + 1023) / 1024;
-  const int b0 = min(nbins, tid * per);
-  int tv[kPer];
-  int st = 0, si = 0;
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const int b = b0 + e;
-    tv[e] = (e < per && b < nbins) ? total[b] : 0;
-    st += tv[e];
-    si += (e < per && b < nbins) ? max(1, (tv[e] + kChunk - 1) / kChunk) : 0;
-  }
-  s_tot[tid] = st;
-  s_items[tid] = si;
+  sh[tid] = v;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {
-    const int vt = tid >= d ? s_tot[tid - d] : 0;
-    const int vi = tid >= d ? s_items[tid - d] : 0;
+    const int o = tid >= d ? sh[tid - d] : 0;
     __syncthreads();
-    s_tot[tid] += vt;
-    s_items[tid] += vi;
+    sh[tid] += o;
     __syncthreads();
   }
-  int pt = s_tot[tid] - st, pi = s_items[tid] - si;  // exclusive prefixes
+  return sh[tid] - v;
+}
+
+__global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int* __restrict__ total,
+                                                         int* __restrict__ base, int* __restrict__ tile_start,
+                                                         int* __restrict__ tile_total, int* __restrict__ item_base,
+                                                         int* __restrict__ nitems) {
+  __shared__ int s_base[kMaxBins + 1];
+  __shared__ int s_scan[1024];
+  constexpr int kPer = kMaxBins / 1024;
+  const int tid = threadIdx.x;
+  const int nb = tg.nbins, nt = tg.ntiles;
+  {
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, tid * per);
+    int tv[kPer];
+    int st = 0;
 #pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const int b = b0 + e;
-    if (e < per && b < nbins) {
-      base[b] = pt;
-      item_base[b] = pi;
-      pt += tv[e];
-      pi += max(1, (tv[e] + kChunk - 1) / kChunk);
+    for (int e = 0; e < kPer; ++e) {
+      tv[e] = (e < per && b0 + e < nb) ? total[b0 + e] : 0;
+      st += tv[e];
+    }
+    int pt = block_exclusive_scan<kPer>(st, s_scan);
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      if (e < per && b0 + e < nb) {
+        s_base[b0 + e] = pt;
+        base[b0 + e] = pt;
+        pt += tv[e];
+      }
+    }
+    if (tid == 1023) {
+      s_base[nb] = s_scan[1023];
+      base[nb] = s_scan[1023];
     }
   }
-  if (tid == 1023) {
-    base[nbins] = s_tot[1023];
-    item_base[nbins] = s_items[1023];
-    *nitems = s_items[1023];
+  __syncthreads();
+  {
+    const int per = (nt + 1023) / 1024;
+    const int t0 = min(nt, tid * per);
+    int items = 0;
+    for (int e = 0; e < per && t0 + e < nt; ++e) {
+      const int t = t0 + e;
+      int j = 0;
+      while (j + 1 < kMaxLevels && t >= tg.tile_base[j + 1]) ++j;
+      const int first = tg.bin_base[j] + (t - tg.tile_base[j]) * tg.sb[j] * tg.sb[j];
+      const int st = s_base[first];
+      const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
+      tile_start[t] = st;
+      tile_total[t] = tot;
+      items += max(1, (tot + kChunk - 1) / kChunk);
+    }
+    int pi = block_exclusive_scan<kPer>(items, s_scan);
+    for (int e = 0; e < per && t0 + e < nt; ++e) {
+      const int tot = tile_total[t0 + e];
+      item_base[t0 + e] = pi;
+      pi += max(1, (tot + kChunk - 1) / kChunk);
+    }
+    if (tid == 1023) {
+      item_base[nt] = s_scan[1023];
+      *nitems = s_scan[1023];
+    }
   }
 }
 
@@ -603,12 +734,12 @@ __global__ __launch_bounds__(1024) void bin_scan2_kernel(int nbins, const int* _
 __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
                                    const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
                                    float out_scale) {
-  const int bin = blockIdx.y;
-  const int it0 = item_base[bin], items = item_base[bin + 1] - it0;
+  const int tile = blockIdx.y;
+  const int it0 = item_base[tile], items = item_base[tile + 1] - it0;
   if (items <= 1) return;
   int j = 0;
-  while (j + 1 < m.J && bin >= tg.base[j + 1]) ++j;
-  const int t = bin - tg.base[j], tx = t % tg.ntx[j], ty = t / tg.ntx[j];
+  while (j + 1 < m.J && tile >= tg.tile_base[j + 1]) ++j;
+  const int t = tile - tg.tile_base[j], tx = t % tg.ntx[j], ty = t / tg.ntx[j];
   const int T = tg.T[j], T1 = T >> 1;
   const int C0 = m.C0, C1 = m.C1;
   const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
@@ -795,8 +926,8 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.lat_grad = l.lat_grad;
   a.part_lat = (float*)(ws + p.off_part_lat);
   a.list = (const int*)(ws + p.off_list);
-  a.bin_total = (const int*)(ws + p.off_total);
-  a.bin_base = (const int*)(ws + p.off_base);
+  a.tile_start = (const int*)(ws + p.off_tstart);
+  a.tile_total = (const int*)(ws + p.off_ttotal);
   a.item_base = (const int*)(ws + p.off_ibase);
   a.nitems = (const int*)(ws + p.off_misc);
   a.part_dw = (float*)(ws + p.off_part_dw);
@@ -842,26 +973,35 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
 #undef NTC_X
   TileGeom& tg = p.tg;
   std::memset(&tg, 0, sizeof tg);
-  int nb = 0, rmax = 0;
+  int nb = 0, nt = 0, rmax = 0;
   for (int j = 0; j < m.num_levels; ++j) {
     const int T = std::min(tmax, std::min(m.g0_w[j], m.g0_h[j]));
     tg.T[j] = T;
     tg.ntx[j] = m.g0_w[j] / T;
     tg.nty[j] = m.g0_h[j] / T;
-    tg.base[j] = nb;
+    const int tiles = tg.ntx[j] * tg.nty[j];
+    // levels with few cells (many samples per cell) are sorted by anchor cell
+    tg.sb[j] = (tiles * T * T <= kSortedCells) ? T : 1;
+    tg.tile_base[j] = nt;
+    tg.bin_base[j] = nb;
     tg.region[j] = T * T * m.c0 + (T / 2) * (T / 2) * m.c1;
     rmax = std::max(rmax, tg.region[j]);
-    nb += tg.ntx[j] * tg.nty[j];
+    nt += tiles;
+    nb += tiles * tg.sb[j] * tg.sb[j];
   }
-  tg.base[m.num_levels] = nb;
-  for (int j = m.num_levels + 1; j <= kMaxLevels; ++j) tg.base[j] = nb;
+  for (int j = m.num_levels; j <= kMaxLevels; ++j) {
+    tg.tile_base[j] = nt;
+    tg.bin_base[j] = nb;
+  }
+  tg.ntiles = nt;
   tg.nbins = nb;
   tg.region_max = rmax;
   p.region_max = rmax;
   p.nbins = nb;
+  p.ntiles = nt;
   p.nbb = (int)std::max<long long>(1, std::min<long long>(256, (n + kBinBlockSamples - 1) / kBinBlockSamples));
   p.per_bin_block = (int)((n + p.nbb - 1) / p.nbb);
-  p.max_items = nb + (4 * n + kChunk - 1) / kChunk;
+  p.max_items = nt + (4 * n + kChunk - 1) / kChunk;
   const long long work_items = std::max<long long>(p.max_items, (n + kChunk - 1) / kChunk);
   p.grid = (int)std::max<long long>(1, std::min<long long>(work_items, (long long)device_cus() * per_cu));
   const size_t P = (size_t)m.mlp_params;
@@ -875,7 +1015,9 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
   p.off_offsets = take((size_t)p.nbb * nb * 4);
   p.off_total = take((size_t)nb * 4);
   p.off_base = take((size_t)(nb + 1) * 4);
-  p.off_ibase = take((size_t)(nb + 1) * 4);
+  p.off_tstart = take((size_t)nt * 4);
+  p.off_ttotal = take((size_t)nt * 4);
+  p.off_ibase = take((size_t)(nt + 1) * 4);
   p.off_misc = take(64);
   p.off_list = take((size_t)4 * n * 4);
   p.off_part_lat = take((size_t)p.max_items * rmax * 4);
@@ -906,8 +1048,9 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
     hipLaunchKernelGGL(bin_scan1_kernel, dim3((p.nbins + 3) / 4), dim3(256), 0, s, p.nbins, p.nbb,
                        (const int*)(ws + p.off_counts), (int*)(ws + p.off_offsets), (int*)(ws + p.off_total));
-    hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.nbins, (const int*)(ws + p.off_total),
-                       (int*)(ws + p.off_base), (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
+    hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.tg, (const int*)(ws + p.off_total),
+                       (int*)(ws + p.off_base), (int*)(ws + p.off_tstart), (int*)(ws + p.off_ttotal),
+                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
     hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
   }
   hipError_t e = hipGetLastError();
@@ -920,7 +1063,7 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   if (e != hipSuccess) return e;
   if (l.scatter_latents) {
     const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
-    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.nbins), dim3(256), 0, s, dm, p.tg,
+    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.ntiles), dim3(256), 0, s, dm, p.tg,
                        (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad,
                        l.out_scale);
   }

@@ -244,7 +244,9 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
  *  ntc_pack_mlp_train: canonical FP32 MLP -> forward + backward operand packs
  *    (ntc_train_packed_bytes(m, precision) bytes), as used by ntc_backward.
  *  ntc_forward: decode from FP32 latents (canonical layout, used as given: no
- *    quantization or noise) with weights packed by ntc_pack_mlp; out: n x C FP32.
+ *    quantization or noise); weights from mlp_train_packed (ntc_pack_mlp_train of
+ *    the same mlp, so forward and backward see identically rounded weights),
+ *    biases from the canonical FP32 mlp; out: n x C FP32.
  *  ntc_backward: given dout = dL/dy (n x C FP32), writes grad_latents (all
  *    latent_count entries, overwritten) and grad_mlp (mlp_params, canonical
  *    layout).  dout is multiplied by dout_scale inside the kernels (use a power of
@@ -253,8 +255,8 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
  */
 ntc_status ntc_pack_mlp_train(const ntc_material* m, const float* mlp, ntc_dtype precision, void* packed,
                               void* stream);
-ntc_status ntc_forward(const ntc_material* m, const float* latents, const void* mlp_packed, ntc_dtype precision,
-                       const ntc_query* q, int64_t n, float* out, void* stream);
+ntc_status ntc_forward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
+                       ntc_dtype precision, const ntc_query* q, int64_t n, float* out, void* stream);
 size_t ntc_backward_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision);
 ntc_status ntc_backward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
                         ntc_dtype precision, const ntc_query* q, int64_t n, const float* dout, float dout_scale,

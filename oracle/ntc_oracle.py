@@ -21,7 +21,8 @@ __all__ = [
     "splitmix64_mix", "noise_values", "pos_enc", "sample_inputs", "mlp_split",
     "mlp_param_count", "activation", "activation_grad", "mlp_forward", "decode",
     "loss_and_grads", "adam_update", "train_step", "loss_scale_update", "psnr",
-    "storage_bytes_paper", "hard_gelu",
+    "storage_bytes_paper", "hard_gelu", "E4M3_MAX", "e4m3_value", "round_e4m3", "fp8_layer_scales",
+    "mlp_forward_fp8", "decode_fp8",
 ]
 
 GAMMA = 0x9E3779B97F4A7C15
@@ -415,6 +416,64 @@ def decode(geom: Geometry, lat, params, queries):
     x, _ = sample_inputs(geom, lat, queries)
     y, _ = mlp_forward(params, x, geom.K, geom.Hd, geom.C, geom.act)
     return y
+
+
+# --------------------------------------------------------------------------------------
+# Reduced-precision decode (section 8 names lower-precision intermediates as the next
+# speed-up).  Reading taken: FP8-e4m3 in the OCP definition (sign, 4 exponent bits with
+# bias 7, 3 mantissa bits; exponent 0 is subnormal; largest finite magnitude 448, the
+# all-ones pattern is NaN, no infinities), round to nearest even, saturating at 448.
+# Weights of layer l are stored as W_l / s_l with s_l = max|W_l| / 448; inputs and
+# hidden activations are rounded as they are; products accumulate in float64 here
+# (FP32 on the GPU); s_l and the FP32 biases are applied after the sum.
+# --------------------------------------------------------------------------------------
+E4M3_MAX = 448.0
+
+
+def e4m3_value(code):
+    """Value of an e4m3 byte, from the bit fields (NaN for the all-ones patterns)."""
+    code = int(code) & 0xFF
+    sign = -1.0 if code & 0x80 else 1.0
+    e, m = (code >> 3) & 15, code & 7
+    if e == 15 and m == 7:
+        return math.nan
+    if e == 0:
+        return sign * m * 2.0 ** -9
+    return sign * (1 + m / 8) * 2.0 ** (e - 7)
+
+
+def round_e4m3(x):
+    """Nearest e4m3 value (ties to even), saturating to +-448; NaN stays NaN."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, -6.0)            # below 2^-6 the spacing stays 2^-9 (subnormals)
+    q = np.exp2(e - 3)                 # spacing of the values in [2^e, 2^(e+1))
+    r = np.rint(a / q) * q             # np.rint rounds half to even
+    r = np.minimum(r, E4M3_MAX)
+    return np.where(np.isnan(x), np.nan, np.copysign(r, x))
+
+
+def fp8_layer_scales(params, K, Hd, C):
+    """Per-layer weight scales s_l = max|W_l| / 448 (1 for an all-zero layer)."""
+    W1, _, W2, _, W3, _ = mlp_split(params, K, Hd, C)
+    return [float(np.max(np.abs(W))) / E4M3_MAX if np.any(W) else 1.0 for W in (W1, W2, W3)]
+
+
+def mlp_forward_fp8(params, x, K, Hd, C, act="relu"):
+    """The network with e4m3 weights (per-layer scale), inputs and hidden activations."""
+    W1, b1, W2, b2, W3, b3 = mlp_split(params, K, Hd, C)
+    s1, s2, s3 = fp8_layer_scales(params, K, Hd, C)
+    h1 = activation(s1 * (round_e4m3(x) @ round_e4m3(W1 / s1)) + b1, act)
+    h2 = activation(s2 * (round_e4m3(h1) @ round_e4m3(W2 / s2)) + b2, act)
+    return s3 * (round_e4m3(h2) @ round_e4m3(W3 / s3)) + b3
+
+
+def decode_fp8(geom: Geometry, lat, params, queries):
+    """decode() with the network evaluated in e4m3 as described above."""
+    x, _ = sample_inputs(geom, lat, queries)
+    return mlp_forward_fp8(params, x, geom.K, geom.Hd, geom.C, geom.act)
 
 
 def _targets_at(geom: Geometry, targets, rec):

@@ -4,7 +4,8 @@
 
 latents (latent_count,) and mlp (mlp_params,) are FP32 CUDA tensors; queries is a
 uint8 CUDA tensor holding n 12-byte ntc_query records.  Gradients flow to latents
-and mlp; the backward recomputes the forward per tile in the HIP kernels.
+and mlp; the backward recomputes the forward per tile in the HIP kernels.  One
+training pack of the weights serves both directions.
 """
 from __future__ import annotations
 
@@ -28,22 +29,20 @@ class NtcDecodeFn(torch.autograd.Function):
     def forward(ctx, latents, mlp, queries, material, precision):
         n = queries.numel() // 12
         C = int(material.channels)
-        wp = torch.empty(ntc.mlp_packed_bytes(material, precision), dtype=torch.uint8, device=latents.device)
-        ntc.pack_mlp(material, mlp, precision, wp)
+        tp = torch.empty(ntc.train_packed_bytes(material, precision), dtype=torch.uint8, device=latents.device)
+        ntc.pack_mlp_train(material, mlp, precision, tp)
         out = torch.empty(n * C, dtype=torch.float32, device=latents.device)
-        ntc.forward(material, latents, wp, precision, queries, n, out)
-        ctx.save_for_backward(latents, mlp, queries)
+        ntc.forward(material, latents, mlp, tp, precision, queries, n, out)
+        ctx.save_for_backward(latents, mlp, queries, tp)
         ctx.material, ctx.precision = material, precision
         return out.view(n, C)
 
     @staticmethod
     def backward(ctx, dout):
-        latents, mlp, queries = ctx.saved_tensors
+        latents, mlp, queries, tp = ctx.saved_tensors
         m, prec = ctx.material, ctx.precision
         n = queries.numel() // 12
         dout = dout.contiguous().float()
-        tp = torch.empty(ntc.train_packed_bytes(m, prec), dtype=torch.uint8, device=latents.device)
-        ntc.pack_mlp_train(m, mlp, prec, tp)
         gl = torch.empty_like(latents)
         gm = torch.empty_like(mlp)
         ws = torch.empty(ntc.backward_workspace_bytes(m, n, prec), dtype=torch.uint8, device=latents.device)

@@ -24,6 +24,8 @@ ARCH = os.environ.get("NTC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # matrix-core accumulators in ordinary VGPRs: no accumulator-register copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unused-variable", "-Wno-unused-function",

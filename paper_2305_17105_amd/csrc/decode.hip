@@ -12,19 +12,41 @@
 
 namespace ntc {
 
+// Input layout of the decoder for a material: packed codes in FP16 use the paired
+// layout where it applies; everything else (and the forward of the differentiation
+// path, which shares the training pack) the plain one.
+template <typename T, int C0, int C1, int HD, int B0, int B1, bool PACKED>
+struct DecodeLayout {
+  static constexpr bool paired = PACKED && paired_layout(C0, C1, B0, B1, sizeof(T) == 2);
+  static constexpr PackGeom pg = PACKED ? pack_geom_decode(C0, C1, B0, B1, HD, sizeof(T) == 2)
+                                        : pack_geom(C0, C1, HD, sizeof(T) == 2);
+  static constexpr int WB = ((int)pg.fwd_end * (int)sizeof(T) + 15) / 16 * 16;
+};
+
+// Two codes of one 32-bit word (bit offsets s and s + 16) as FP16 values 1024 + code:
+// OR-ing the exponent of 1024 over a code of at most 10 bits is the exact conversion.
+template <int B>
+__device__ inline f16x2 code_pair(uint32_t w, int s) {
+  constexpr uint32_t cm = (1u << B) - 1u, pm = cm | (cm << 16);
+  return __builtin_bit_cast(f16x2, ((w >> s) & pm) | 0x64006400u);
+}
+
 // PACKED: latents come as bit-packed codes (ntc_decode); otherwise as FP32 values
 // in the canonical latent layout (ntc_forward, the differentiation path).
-template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED>
+// bias: b1 (HD), b2 (HD), b3 (C) at the three given addresses.
+template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
 __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const void* __restrict__ src,
-                                                     const T* __restrict__ wpack, const float* __restrict__ bias,
+                                                     const T* __restrict__ wpack, const float* __restrict__ bias1,
+                                                     const float* __restrict__ bias2,
+                                                     const float* __restrict__ bias3,
                                                      const ntc_query* __restrict__ q, long long n,
                                                      void* __restrict__ out, int out_f16) {
   const uint32_t* __restrict__ packed = reinterpret_cast<const uint32_t*>(src);
   const float* __restrict__ lat = reinterpret_cast<const float*>(src);
   using IS = InSlots<C0, C1>;
-  constexpr PackGeom pg = pack_geom(C0, C1, HD, sizeof(T) == 2);
-  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT;
-  constexpr int WB = ((int)pg.fwd_end * (int)sizeof(T) + 15) / 16 * 16;
+  using DL = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>;
+  constexpr PackGeom pg = DL::pg;
+  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT, WB = DL::WB;
   extern __shared__ __align__(16) char smem[];
   T* w_lds = reinterpret_cast<T*>(smem);
   float* pe_lds = reinterpret_cast<float*>(smem + WB);
@@ -33,74 +55,16 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
   for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
   for (int i = threadIdx.x; i < 48; i += blockDim.x) pe_lds[i] = pe.v[i / 6][i % 6];
-  for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x) b_lds[i] = (i < 2 * HD + C) ? bias[i] : 0.f;
+  for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x)
+    b_lds[i] = i < HD ? bias1[i] : i < 2 * HD ? bias2[i - HD] : i < 2 * HD + C ? bias3[i - 2 * HD] : 0.f;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const long long tiles = (n + 15) / 16;
-  for (long long tile = (long long)blockIdx.x * 4 + wave; tile < tiles; tile += (long long)gridDim.x * 4) {
+  const long long tiles = (n + 15) / 16, stride = (long long)gridDim.x * 4;
+
+  // three layers on one tile's assembled inputs, then the store
+  auto mlp_store = [&](T (&xs)[S1], long long tile) {
     const long long s = tile * 16 + r;
-    const bool valid = s < n;
-    float u = 0.f, v = 0.f;
-    int lod = 0;
-    if (valid) {
-      u = q[s].u;
-      v = q[s].v;
-      lod = q[s].lod;
-    }
-    const Footprint f = locate(m, u, v, lod, g);
-    T xs[S1];
-    if constexpr (PACKED) {
-      {  // G0: this group's neighbour, all C0 channels (learned interpolation input)
-        constexpr int NB = C0 * B0, NW = (NB + 31) / 32;
-        uint32_t win[NW];
-        load_bits<NW, NB % 32 == 0>(packed, m.g0_pk[f.j] * 8 + (long long)f.g0_cell * NB, m.g0_pk_end[f.j], win);
-#pragma unroll
-        for (int t = 0; t < C0; ++t) xs[t] = (T)dequant<B0>(code_at<B0>(win, t));
-      }
-      {  // G1: bilinear over 4 taps, channels g, g+4, ...
-        constexpr int NB = C1 * B1, NW = (NB + 31) / 32;
-        float acc[IS::n1max];
-#pragma unroll
-        for (int i = 0; i < IS::n1max; ++i) acc[i] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t win[NW];
-          load_bits<NW, NB % 32 == 0>(packed, m.g1_pk[f.j] * 8 + (long long)f.g1_cell[k] * NB, m.g1_pk_end[f.j], win);
-#pragma unroll
-          for (int i = 0; i < IS::n1max; ++i) {
-            const int ch = min(g + 4 * i, C1 - 1);
-            acc[i] += f.g1_w[k] * dequant<B1>(code_at_dyn<B1>(win, ch));
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < IS::n1max; ++i) xs[C0 + i] = (g + 4 * i < C1) ? (T)acc[i] : (T)0.f;
-      }
-    } else {
-      const long long g0base = m.g0_off[f.j] + (long long)f.g0_cell * C0;
-      const long long g1base = m.g1_off[f.j];
-#pragma unroll
-      for (int t = 0; t < C0; ++t) xs[t] = (T)lat[g0base + t];
-#pragma unroll
-      for (int i = 0; i < IS::n1max; ++i) {
-        const int ch = g + 4 * i;
-        float acc = 0.f;
-        if (ch < C1) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc += f.g1_w[k] * lat[g1base + (long long)f.g1_cell[k] * C1 + ch];
-        }
-        xs[C0 + i] = (T)acc;
-      }
-    }
-    {
-      float pv[3];
-      pe_values(pe_lds, f.ix, f.iy, g, pv);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) xs[IS::T_lat + k] = (T)pv[k];
-#pragma unroll
-      for (int t = IS::T_used; t < S1; ++t) xs[t] = (T)0.f;
-    }
-    // layer 1
     f32x4 acc[MT];
 #pragma unroll
     for (int mo = 0; mo < MT; ++mo) {
@@ -109,28 +73,22 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
     }
     T h[SH];
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) h[4 * mo + i] = (T)act_fn(acc[mo][i], m.act);
-    // layer 2
+    for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
 #pragma unroll
     for (int mo = 0; mo < MT; ++mo) {
       acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
       acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, h, lane);
     }
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) h[4 * mo + i] = (T)act_fn(acc[mo][i], m.act);
+    for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
     // layer 3 (no activation): lane group g holds channels 4g .. 4g+3
     f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
     y = mma_slots<SH>(y, w_lds + pg.L3, h, lane);
-    if (valid && 4 * g < C) {
+    if (s < n && 4 * g < C) {
       if (out_f16) {
         _Float16* o = reinterpret_cast<_Float16*>(out) + s * C + 4 * g;
         if constexpr (C % 4 == 0) {
-          f16x4 hv = {(_Float16)y[0], (_Float16)y[1], (_Float16)y[2], (_Float16)y[3]};
-          *reinterpret_cast<f16x4*>(o) = hv;
+          *reinterpret_cast<f16x4*>(o) = __builtin_convertvector(y, f16x4);
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -147,17 +105,172 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
         }
       }
     }
+  };
+  auto pe_slots = [&](T (&xs)[S1], int ix, int iy) {
+    float pv[3];
+    pe_values(pe_lds, ix, iy, g, pv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xs[pg.T_lat + k] = (T)pv[k];
+#pragma unroll
+    for (int t = pg.T_used; t < S1; ++t) xs[t] = (T)0.f;
+  };
+  // query record of this lane's texel of a tile (zeros past the end)
+  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
+    const long long s = tile * 16 + r;
+    u = v = 0.f;
+    lod = 0;
+    if (tile < tiles && s < n) {
+      u = q[s].u;
+      v = q[s].v;
+      lod = q[s].lod;
+    }
+  };
+
+  if constexpr (PACKED) {
+    // Software pipeline over the wave's tiles: queries two tiles ahead, latent words
+    // one tile ahead, so both gathers are in flight while the matrix cores run.
+    constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
+    struct Raw {
+      int ix, iy;
+      float fx, fy, w[4];
+      uint32_t g0[NW0];
+      uint32_t g1[4][NW1];
+    };
+    auto fetch = [&](float u, float v, int lod, Raw& R) {
+      const Footprint f = locate(m, u, v, lod, g);
+      R.ix = f.ix;
+      R.iy = f.iy;
+      R.fx = f.fx;
+      R.fy = f.fy;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) R.w[k] = f.g1_w[k];
+      load_bits<NW0, NB0 % 32 == 0>(packed, m.g0_pk[f.j] * 8 + (long long)f.g0_cell * NB0, m.g0_pk_end[f.j], R.g0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        load_bits<NW1, NB1 % 32 == 0>(packed, m.g1_pk[f.j] * 8 + (long long)f.g1_cell[k] * NB1, m.g1_pk_end[f.j],
+                                      R.g1[k]);
+    };
+    auto assemble = [&](const Raw& R, T (&xs)[S1]) {
+      if constexpr (DL::paired) {
+        {  // G0: two channels per instruction; (1024 + code) / N - (N/2 - 1 + 1024) / N is exact
+          constexpr int HALF = 16 / B0, N0 = 1 << B0;
+          const f16x2 sc = {(_Float16)(1.f / N0), (_Float16)(1.f / N0)};
+          const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
+          const f16x2 of = {o, o};
+#pragma unroll
+          for (int d = 0; d < NW0; ++d)
+#pragma unroll
+            for (int c = 0; c < HALF; ++c) {
+              const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
+              xs[2 * (d * HALF + c)] = x[0];
+              xs[2 * (d * HALF + c) + 1] = x[1];
+            }
+        }
+        {  // G1: separable bilinear in centred code units; the row steps are exact, the
+           // column step rounds once and the power-of-two scale is exact
+          constexpr int KP = 4 / B1, N1 = 1 << B1;
+          const f16x2 fx = {(_Float16)R.fx, (_Float16)R.fx}, fy = {(_Float16)R.fy, (_Float16)R.fy};
+          const _Float16 o = (_Float16)(-(1024.f + N1 / 2 - 1));
+          const f16x2 of = {o, o};
+          const f16x2 sc = {(_Float16)(1.f / N1), (_Float16)(1.f / N1)};
+#pragma unroll
+          for (int d = 0; d < NW1; ++d)
+#pragma unroll
+            for (int kk = 0; kk < KP; ++kk) {
+              const int sh = B1 * (g + 4 * kk);
+              const f16x2 x0 = code_pair<B1>(R.g1[0][d], sh), x1 = code_pair<B1>(R.g1[1][d], sh);
+              const f16x2 x2 = code_pair<B1>(R.g1[2][d], sh), x3 = code_pair<B1>(R.g1[3][d], sh);
+              const f16x2 r0 = __builtin_elementwise_fma(fx, x1 - x0, x0 + of);
+              const f16x2 r1 = __builtin_elementwise_fma(fx, x3 - x2, x2 + of);
+              const f16x2 v = __builtin_elementwise_fma(fy, r1 - r0, r0) * sc;
+              const int t = C0 + 2 * (d * KP + kk);
+              xs[t] = v[0];
+              xs[t + 1] = v[1];
+            }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < C0; ++t) xs[t] = (T)dequant<B0>(code_at<B0>(R.g0, t));
+        // G1: bilinear over 4 taps, channels g, g+4, ...
+        float acc[IS::n1max];
+#pragma unroll
+        for (int i = 0; i < IS::n1max; ++i) acc[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int i = 0; i < IS::n1max; ++i) {
+            const int ch = min(g + 4 * i, C1 - 1);
+            acc[i] += R.w[k] * dequant<B1>(code_at_dyn<B1>(R.g1[k], ch));
+          }
+#pragma unroll
+        for (int i = 0; i < IS::n1max; ++i) xs[C0 + i] = (g + 4 * i < C1) ? (T)acc[i] : (T)0.f;
+      }
+      pe_slots(xs, R.ix, R.iy);
+    };
+
+    long long tile = (long long)blockIdx.x * 4 + wave;
+    if (tile >= tiles) return;
+    float u, v;
+    int lod;
+    load_query(tile, u, v, lod);
+    Raw cur;
+    fetch(u, v, lod, cur);
+    load_query(tile + stride, u, v, lod);
+    for (; tile < tiles; tile += stride) {
+      Raw nxt;
+      if (tile + stride < tiles) fetch(u, v, lod, nxt);
+      if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
+      T xs[S1];
+      assemble(cur, xs);
+      mlp_store(xs, tile);
+      cur = nxt;
+    }
+  } else {
+    for (long long tile = (long long)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
+      float u, v;
+      int lod;
+      load_query(tile, u, v, lod);
+      const Footprint f = locate(m, u, v, lod, g);
+      T xs[S1];
+      const long long g0base = m.g0_off[f.j] + (long long)f.g0_cell * C0;
+      const long long g1base = m.g1_off[f.j];
+#pragma unroll
+      for (int t = 0; t < C0; ++t) xs[t] = (T)lat[g0base + t];
+#pragma unroll
+      for (int i = 0; i < IS::n1max; ++i) {
+        const int ch = g + 4 * i;
+        float acc = 0.f;
+        if (ch < C1) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc += f.g1_w[k] * lat[g1base + (long long)f.g1_cell[k] * C1 + ch];
+        }
+        xs[C0 + i] = (T)acc;
+      }
+      pe_slots(xs, f.ix, f.iy);
+      mlp_store(xs, tile);
+    }
   }
 }
 
-template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED>
-static hipError_t decode_t(const ntc_material& mm, const void* src, const void* wpack, const ntc_query* q,
-                           long long n, void* out, bool out_f16, hipStream_t s) {
-  constexpr PackGeom pg = pack_geom(C0, C1, HD, sizeof(T) == 2);
-  constexpr int WB = ((int)pg.fwd_end * (int)sizeof(T) + 15) / 16 * 16;
+// mlp: canonical FP32 parameters supplying the biases, or nullptr when the biases
+// follow the weights in the pack (decode packs)
+template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
+static hipError_t decode_t1(const ntc_material& mm, const void* src, const void* wpack, const float* mlp,
+                           const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s) {
+  constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>::WB;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4;
-  const float* bias = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
-  auto kern = decode_kernel<T, C0, C1, C, HD, B0, B1, PACKED>;
+  const float *b1, *b2, *b3;
+  if (mlp) {
+    const long long K = 4 * C0 + C1 + 12;
+    b1 = mlp + K * HD;
+    b2 = b1 + HD + (long long)HD * HD;
+    b3 = b2 + HD + (long long)HD * C;
+  } else {
+    b1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
+    b2 = b1 + HD;
+    b3 = b2 + HD;
+  }
+  auto kern = decode_kernel<T, C0, C1, C, HD, B0, B1, PACKED, ACT>;
   static int per_cu = 0;
   if (per_cu == 0) {
     int v = 0;
@@ -169,8 +282,15 @@ static hipError_t decode_t(const ntc_material& mm, const void* src, const void* 
   const long long cap = (long long)device_cus() * per_cu;
   if (grid > cap) grid = cap;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(), src,
-                     reinterpret_cast<const T*>(wpack), bias, q, n, out, out_f16 ? 1 : 0);
+                     reinterpret_cast<const T*>(wpack), b1, b2, b3, q, n, out, out_f16 ? 1 : 0);
   return hipGetLastError();
+}
+
+template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED>
+static hipError_t decode_t(const ntc_material& mm, const void* src, const void* wpack, const float* mlp,
+                           const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s) {
+  return mm.activation ? decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 1>(mm, src, wpack, mlp, q, n, out, out_f16, s)
+                       : decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 0>(mm, src, wpack, mlp, q, n, out, out_f16, s);
 }
 
 #define NTC_DECODE_SHAPES(X)                                                                     \
@@ -190,24 +310,25 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
                          long long n, void* out, bool out_f16, hipStream_t s) {
 #define NTC_X(a, b, cc, h, x0, x1)                                                                   \
   if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)      \
-    return f16 ? decode_t<_Float16, a, b, cc, h, x0, x1, true>(m, packed, wpack, q, n, out, out_f16, s)   \
-               : decode_t<float, a, b, cc, h, x0, x1, true>(m, packed, wpack, q, n, out, out_f16, s);
+    return f16 ? decode_t<_Float16, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s) \
+               : decode_t<float, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s);
   NTC_DECODE_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;
 }
 
-// Forward from FP32 latents (the differentiation path); shapes as for training.
+// Forward from FP32 latents (the differentiation path) with the training pack, whose
+// forward part leads it, and the biases of the canonical parameters; shapes as for training.
 #define NTC_FORWARD_SHAPES(X)                                                          \
   X(8, 8, 8, 64) X(10, 10, 10, 64) X(12, 12, 12, 64) X(16, 16, 16, 64) X(8, 8, 8, 32) \
   X(10, 10, 10, 32) X(12, 12, 12, 32) X(16, 16, 16, 32)
 
-hipError_t launch_forward(const ntc_material& m, const float* latents, const void* wpack, bool f16, const ntc_query* q,
-                          long long n, float* out, hipStream_t s) {
-#define NTC_X(a, b, cc, h)                                                                                  \
-  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h)                                          \
-    return f16 ? decode_t<_Float16, a, b, cc, h, 4, 4, false>(m, latents, wpack, q, n, out, false, s)       \
-               : decode_t<float, a, b, cc, h, 4, 4, false>(m, latents, wpack, q, n, out, false, s);
+hipError_t launch_forward(const ntc_material& m, const float* latents, const float* mlp, const void* wpack, bool f16,
+                          const ntc_query* q, long long n, float* out, hipStream_t s) {
+#define NTC_X(a, b, cc, h)                                                                                   \
+  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h)                                           \
+    return f16 ? decode_t<_Float16, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, out, false, s)   \
+               : decode_t<float, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, out, false, s);
   NTC_FORWARD_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;

@@ -214,7 +214,7 @@ static size_t round16(size_t b) { return (b + 15) / 16 * 16; }
 size_t ntc_mlp_packed_bytes(const ntc_material* m, ntc_dtype precision) {
   if (!m || (precision != NTC_F32 && precision != NTC_F16)) return 0;
   const bool f16 = precision == NTC_F16;
-  const PackGeom pg = pack_geom(m->c0, m->c1, m->hidden, f16);
+  const PackGeom pg = pack_geom_decode(m->c0, m->c1, m->b0, m->b1, m->hidden, f16);
   const size_t w = round16((size_t)pg.fwd_end * (f16 ? 2 : 4));
   return w + round16((size_t)(2 * m->hidden + m->channels) * 4);
 }
@@ -387,8 +387,8 @@ ntc_status ntc_pack_mlp_train(const ntc_material* m, const float* mlp, ntc_dtype
                     "ntc_pack_mlp_train");
 }
 
-ntc_status ntc_forward(const ntc_material* m, const float* latents, const void* mlp_packed, ntc_dtype precision,
-                       const ntc_query* q, int64_t n, float* out, void* stream) {
+ntc_status ntc_forward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
+                       ntc_dtype precision, const ntc_query* q, int64_t n, float* out, void* stream) {
   ntc_status st = check_material(m);
   if (st != NTC_OK) return st;
   if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
@@ -396,9 +396,10 @@ ntc_status ntc_forward(const ntc_material* m, const float* latents, const void* 
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
     return fail(NTC_E_UNSUPPORTED, "no kernel for this (c0, c1, channels, hidden)");
   if (n == 0) return NTC_OK;
-  if (!latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
-  return hip_status(launch_forward(*m, latents, mlp_packed, precision == NTC_F16, q, n, out, (hipStream_t)stream),
-                    "ntc_forward");
+  if (!latents || !mlp || !mlp_train_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(
+      launch_forward(*m, latents, mlp, mlp_train_packed, precision == NTC_F16, q, n, out, (hipStream_t)stream),
+      "ntc_forward");
 }
 
 size_t ntc_backward_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {

@@ -19,6 +19,8 @@ namespace ntc {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kMaxLevels = 8;
 constexpr int kMaxMips = 16;
@@ -90,6 +92,52 @@ __host__ __device__ constexpr PackGeom pack_geom(int c0, int c1, int hd, bool f1
   return p;
 }
 
+// Paired input layout of the FP16 decoder reading bit-packed codes: two channels per
+// 32-bit register, taken straight from the packed words (channel c and c + 16/B of
+// the same dword share a register), when a G0 cell fills whole dwords and B <= 4.
+//   G0: window dword d, pair p = d*(16/B0) + c (c < 16/B0) -> slots 2p, 2p+1 hold
+//       channels d*32/B0 + c and d*32/B0 + c + 16/B0.
+//   G1: lane group g, dword d, k < 4/B1: pair q = d*(4/B1) + k -> slots C0 + 2q, +1
+//       hold channels ch = d*32/B1 + g + 4k and ch + 16/B1 (padding if >= C1).
+//   PE: the next 3 slots.
+__host__ __device__ constexpr bool paired_layout(int c0, int c1, int b0, int b1, bool f16) {
+  return f16 && b0 <= 4 && b1 <= 4 && (c0 * b0) % 32 == 0 && c1 >= 1;
+}
+__host__ __device__ constexpr int paired_g1_slots(int c1, int b1) { return 2 * ((c1 * b1 + 31) / 32) * (4 / b1); }
+__host__ __device__ constexpr PackGeom pack_geom_decode(int c0, int c1, int b0, int b1, int hd, bool f16) {
+  PackGeom p = pack_geom(c0, c1, hd, f16);
+  if (paired_layout(c0, c1, b0, b1, f16)) {
+    p.T_lat = c0 + paired_g1_slots(c1, b1);
+    p.T_used = p.T_lat + 3;
+    p.S1 = (p.T_used + 3) / 4 * 4;
+    p.ML = (p.T_lat + 3) / 4;
+    p.L1 = 0;
+    p.L2 = p.L1 + (long long)p.MT * p.S1 * 64;
+    p.L3 = p.L2 + (long long)p.MT * p.SH * 64;
+    p.B3 = p.L3 + (long long)p.SH * 64;
+    p.fwd_end = p.B3;
+    p.B2 = p.B1 = p.train_end = p.B3;  // decode packs have no backward part
+  }
+  return p;
+}
+__host__ __device__ inline void in_slot_of_paired(int k, int c0, int c1, int b0, int b1, int& g, int& t) {
+  if (k < 4 * c0) {
+    const int c = k % c0, per = 32 / b0, half = 16 / b0, d = c / per, cc = c % per;
+    g = k / c0;
+    t = cc < half ? 2 * (d * half + cc) : 2 * (d * half + cc - half) + 1;
+  } else if (k < 4 * c0 + c1) {
+    const int ch = k - 4 * c0, per = 32 / b1, half = 16 / b1, d = ch / per, cc = ch % per;
+    g = ch % 4;
+    const bool lo = cc < half;
+    const int kk = ((lo ? cc : cc - half) - g) / 4;
+    t = c0 + 2 * (d * (4 / b1) + kk) + (lo ? 0 : 1);
+  } else {
+    const int p = k - 4 * c0 - c1;
+    g = p / 3;
+    t = c0 + paired_g1_slots(c1, b1) + p % 3;
+  }
+}
+
 // Runtime inverse slot maps (used where canonical weights are scattered into packs).
 __host__ __device__ inline void in_slot_of(int k, int c0, int c1, int& g, int& t) {
   const int tl = c0 + (c1 + 3) / 4;
@@ -155,13 +203,44 @@ __device__ inline f32x4 mma_slots(f32x4 acc, const _Float16* __restrict__ a, con
 }
 
 // ------------------------------------------------------------------ activations (section 4.4)
-__device__ inline float act_fn(float z, int act) {
-  if (act == 0) return fmaxf(z, 0.f);
-  return z < -1.5f ? 0.f : (z > 1.5f ? z : z * (z + 1.5f) * (1.f / 3.f));
+// ACT: 0 ReLU, 1 hardGELU; a compile-time choice so that the per-element code is
+// straight-line selects
+template <int ACT>
+__device__ inline float act_fn(float z) {
+  if constexpr (ACT == 0) {
+    // max(z, 0) on the bit pattern: one integer op, no NaN canonicalisation
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, z), 0));
+  } else {
+    const float p = z * (z + 1.5f) * (1.f / 3.f);
+    return z < -1.5f ? 0.f : (z > 1.5f ? z : p);
+  }
 }
-__device__ inline float act_grad(float z, int act) {
-  if (act == 0) return z > 0.f ? 1.f : 0.f;
-  return z < -1.5f ? 0.f : (z > 1.5f ? 1.f : (2.f * z + 1.5f) * (1.f / 3.f));
+// a(z) of one accumulator fragment, rounded to the operand type T; ReLU in FP16
+// rounds first (rounding commutes with max(., 0)) and clamps two values per op
+template <int ACT, typename T>
+__device__ inline void act4(const f32x4& a, T* h) {
+  if constexpr (ACT == 0 && sizeof(T) == 2) {
+    const s16x2 zero = {0, 0};
+    const f16x2 p0 = __builtin_convertvector(a.xy, f16x2), p1 = __builtin_convertvector(a.zw, f16x2);
+    const f16x2 q0 = __builtin_bit_cast(f16x2, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p0), zero));
+    const f16x2 q1 = __builtin_bit_cast(f16x2, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p1), zero));
+    h[0] = q0[0];
+    h[1] = q0[1];
+    h[2] = q1[0];
+    h[3] = q1[1];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[i] = (T)act_fn<ACT>(a[i]);
+  }
+}
+template <int ACT>
+__device__ inline float act_grad(float z) {
+  if constexpr (ACT == 0) {
+    return z > 0.f ? 1.f : 0.f;
+  } else {
+    const float p = (2.f * z + 1.5f) * (1.f / 3.f);
+    return z < -1.5f ? 0.f : (z > 1.5f ? 1.f : p);
+  }
 }
 
 // ------------------------------------------------------------------ sampling (section 4.3)
@@ -181,6 +260,7 @@ struct Footprint {
   int g1_cell[4];       // G1 tap cells, order (x,y), (x+1,y), (x,y+1), (x+1,y+1)
   int g1x[2], g1y[2];   // clamped G1 tap coordinates (x, x+1), (y, y+1)
   float g1_w[4];        // bilinear weights of the taps
+  float fx, fy;         // fractional G1 position (g1_w are the products of fx, fy, 1-fx, 1-fy)
 };
 
 __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, int g) {
@@ -194,11 +274,13 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
   f.j = j;
   f.ix = snap_texel(u, Wl);
   f.iy = snap_texel(v, Hl);
-  // texel centre in grid units; every factor is a power of two, so this is exact
+  // texel centre in grid units: all sizes are powers of two, so the scale is an
+  // exponent shift and exact
   const float cx = (float)f.ix + 0.5f, cy = (float)f.iy + 0.5f;
+  const int ex = __builtin_ctz(w0) - __builtin_ctz(Wl), ey = __builtin_ctz(h0) - __builtin_ctz(Hl);
   {
-    const float gx = cx * ((float)w0 / (float)Wl) - 0.5f;
-    const float gy = cy * ((float)h0 / (float)Hl) - 0.5f;
+    const float gx = __builtin_ldexpf(cx, ex) - 0.5f;
+    const float gy = __builtin_ldexpf(cy, ey) - 0.5f;
     const int x0 = (int)floorf(gx), y0 = (int)floorf(gy);
     f.ax = min(max(x0, 0), w0 - 1);
     f.ay = min(max(y0, 0), h0 - 1);
@@ -209,8 +291,8 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
     f.g0_cell = f.g0y * w0 + f.g0x;
   }
   {
-    const float gx = cx * ((float)w1 / (float)Wl) - 0.5f;
-    const float gy = cy * ((float)h1 / (float)Hl) - 0.5f;
+    const float gx = __builtin_ldexpf(cx, ex - 1) - 0.5f;  // G1 has half the G0 resolution
+    const float gy = __builtin_ldexpf(cy, ey - 1) - 0.5f;
     const float fx0 = floorf(gx), fy0 = floorf(gy);
     const float fx = gx - fx0, fy = gy - fy0;
     const int x0 = (int)fx0, y0 = (int)fy0;
@@ -222,6 +304,8 @@ __device__ inline Footprint locate(const DevMat& m, float u, float v, int lod, i
     f.g1_cell[1] = f.g1y[0] * w1 + f.g1x[1];
     f.g1_cell[2] = f.g1y[1] * w1 + f.g1x[0];
     f.g1_cell[3] = f.g1y[1] * w1 + f.g1x[1];
+    f.fx = fx;
+    f.fy = fy;
     f.g1_w[0] = (1.f - fx) * (1.f - fy);
     f.g1_w[1] = fx * (1.f - fy);
     f.g1_w[2] = (1.f - fx) * fy;
@@ -359,14 +443,16 @@ __device__ inline float noise_at(uint64_t key, long long i, int bits) {
 // packs (weights only; biases are read from the canonical buffer).
 template <typename T>
 __device__ inline void scatter_param(T* __restrict__ pack, const PackGeom& pg, int c0, int c1, int C, int Hd,
-                                     long long p, float value, bool bwd) {
+                                     long long p, float value, bool bwd, int b0 = 0, int b1 = 0,
+                                     bool paired = false) {
   const long long K = 4 * c0 + c1 + 12;
   const long long nW1 = K * Hd, nW2 = (long long)Hd * Hd, nW3 = (long long)Hd * C;
   const T v = (T)value;
   if (p < nW1) {
     const int k = (int)(p / Hd), h = (int)(p % Hd);
     int g, t;
-    in_slot_of(k, c0, c1, g, t);
+    if (paired) in_slot_of_paired(k, c0, c1, b0, b1, g, t);
+    else in_slot_of(k, c0, c1, g, t);
     pack[pg.L1 + pack_index<T>(pg.S1, h / 16, t, 16 * g + h % 16)] = v;
     if (bwd && t < pg.T_lat) {
       int g2, t2;

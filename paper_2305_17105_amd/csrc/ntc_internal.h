@@ -62,8 +62,8 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
 hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
                                float loss_norm, int32_t* overflow_flag, hipStream_t s, float* grad_out = nullptr,
                                float out_scale = 1.f);
-hipError_t launch_forward(const ntc_material& m, const float* latents, const void* wpack, bool f16, const ntc_query* q,
-                          long long n, float* out, hipStream_t s);
+hipError_t launch_forward(const ntc_material& m, const float* latents, const float* mlp, const void* wpack, bool f16,
+                          const ntc_query* q, long long n, float* out, hipStream_t s);
 
 struct AdamLaunch {
   float* latents;

@@ -156,7 +156,7 @@ struct TrainCfg {
   static constexpr int LDS = OFF_REG + region(TMAX) * 4;
 };
 
-template <typename T, int C0, int C1, int C, int HD>
+template <typename T, int C0, int C1, int C, int HD, int ACT>
 __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
@@ -193,7 +193,6 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
 
   const float scale = a.loss_scale ? a.loss_scale[a.scale_slot] : 1.f;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
-  const int act = m.act;
 
   f32x4 acc3 = {0.f, 0.f, 0.f, 0.f};
   f32x4 acc2[Cfg::NT2], acc1[Cfg::NT1];
@@ -293,24 +292,22 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         acc[mo] = mma_slots<S1>(acc[mo], w_lds + pg.L1 + mo * S1 * 64, xs, lane);
       }
 #pragma unroll
-      for (int mo = 0; mo < MT; ++mo)
+      for (int mo = 0; mo < MT; ++mo) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          z1[4 * mo + i] = acc[mo][i];
-          hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
-        }
+        for (int i = 0; i < 4; ++i) z1[4 * mo + i] = acc[mo][i];
+        act4<ACT>(acc[mo], hs + 4 * mo);
+      }
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo) {
         acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
         acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, hs, lane);
       }
 #pragma unroll
-      for (int mo = 0; mo < MT; ++mo)
+      for (int mo = 0; mo < MT; ++mo) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          z2[4 * mo + i] = acc[mo][i];
-          hs[4 * mo + i] = (T)act_fn(acc[mo][i], act);
-        }
+        for (int i = 0; i < 4; ++i) z2[4 * mo + i] = acc[mo][i];
+        act4<ACT>(acc[mo], hs + 4 * mo);
+      }
       f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
       y = mma_slots<SH>(y, w_lds + pg.L3, hs, lane);
 
@@ -345,7 +342,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         d = mma_slots<4>(d, w_lds + pg.B3 + mo * 4 * 64, dyT, lane);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          dz2[4 * mo + i] = d[i] * act_grad(z2[4 * mo + i], act);
+          dz2[4 * mo + i] = d[i] * act_grad<ACT>(z2[4 * mo + i]);
           dT[4 * mo + i] = (T)dz2[4 * mo + i];
         }
       }
@@ -354,7 +351,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
         d = mma_slots<SH>(d, w_lds + pg.B2 + mo * SH * 64, dT, lane);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * act_grad(z1[4 * mo + i], act);
+        for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * act_grad<ACT>(z1[4 * mo + i]);
       }
       T dz1T[SH];
 #pragma unroll
@@ -439,8 +436,8 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
 #pragma unroll
         for (int t = 0; t < SH; ++t) {
           const int h = hid_feature(g, t);
-          buf[(Cfg::RH1 + h) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
-          buf[(Cfg::RH2 + h) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+          buf[(Cfg::RH1 + h) * RS + col] = primary ? (T)act_fn<ACT>(z1[t]) : zero;
+          buf[(Cfg::RH2 + h) * RS + col] = primary ? (T)act_fn<ACT>(z2[t]) : zero;
           buf[(Cfg::RDZ1 + h) * RS + col] = primary ? dz1T[t] : zero;
           buf[(Cfg::RDZ2 + h) * RS + col] = primary ? dT[t] : zero;
         }
@@ -467,7 +464,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       } else {
         // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
 #pragma unroll
-        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z2[t], act) : zero;
+        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn<ACT>(z2[t]) : zero;
 #pragma unroll
         for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
         __syncthreads();
@@ -477,7 +474,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
 #pragma unroll
         for (int t = 0; t < SH; ++t) {
-          buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn(z1[t], act) : zero;
+          buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn<ACT>(z1[t]) : zero;
           buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
         }
         __syncthreads();
@@ -891,13 +888,14 @@ __global__ void prepare_kernel(DevMat m, const float* __restrict__ lat, float* _
 }
 
 // ------------------------------------------------------------------ host side
-template <typename T, int C0, int C1, int C, int HD>
+template <typename T, int C0, int C1, int C, int HD, int ACT>
 static int fused_per_cu() {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   static int cached = 0;
   if (cached == 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD>, 256, Cfg::LDS) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD, ACT>, 256,
+                                                     Cfg::LDS) !=
             hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -907,12 +905,12 @@ static int fused_per_cu() {
 }
 
 template <typename T, int C0, int C1, int C, int HD>
-static void shape_info(int& tmax, int& per_cu) {
+static void shape_info(int act, int& tmax, int& per_cu) {
   tmax = TrainCfg<T, C0, C1, C, HD>::TMAX;
-  per_cu = fused_per_cu<T, C0, C1, C, HD>();
+  per_cu = act ? fused_per_cu<T, C0, C1, C, HD, 1>() : fused_per_cu<T, C0, C1, C, HD, 0>();
 }
 
-template <typename T, int C0, int C1, int C, int HD>
+template <typename T, int C0, int C1, int C, int HD, int ACT>
 static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const TrainLaunch& l, hipStream_t s) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   char* ws = (char*)l.workspace;
@@ -942,7 +940,7 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.dout_scale = l.dout_scale;
   a.out_scale = l.out_scale;
   a.tg = p.tg;
-  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
+  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
                      pe_table(), a);
   return hipGetLastError();
 }
@@ -966,8 +964,8 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
   int tmax = 8, per_cu = 1;
 #define NTC_X(a_, b, cc, h)                                                                          \
   if (m.c0 == a_ && m.c1 == b && m.channels == cc && m.hidden == h) {                                \
-    if (f16) shape_info<_Float16, a_, b, cc, h>(tmax, per_cu);                                       \
-    else shape_info<float, a_, b, cc, h>(tmax, per_cu);                                              \
+    if (f16) shape_info<_Float16, a_, b, cc, h>(m.activation, tmax, per_cu);                         \
+    else shape_info<float, a_, b, cc, h>(m.activation, tmax, per_cu);                                \
   }
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
@@ -1057,7 +1055,10 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   if (e != hipSuccess) return e;
 #define NTC_X(a_, b_, cc, h)                                                                     \
   if (m.c0 == a_ && m.c1 == b_ && m.channels == cc && m.hidden == h)                             \
-    e = f16 ? fused_t<_Float16, a_, b_, cc, h>(m, p, l, s) : fused_t<float, a_, b_, cc, h>(m, p, l, s);
+    e = f16 ? (m.activation ? fused_t<_Float16, a_, b_, cc, h, 1>(m, p, l, s)                  \
+                            : fused_t<_Float16, a_, b_, cc, h, 0>(m, p, l, s))                   \
+            : (m.activation ? fused_t<float, a_, b_, cc, h, 1>(m, p, l, s)                       \
+                            : fused_t<float, a_, b_, cc, h, 0>(m, p, l, s));
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
   if (e != hipSuccess) return e;

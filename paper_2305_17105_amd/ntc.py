@@ -79,8 +79,8 @@ _sig = {
     "ntc_train_update": (C.c_int, [_P(Material), _P(TrainStateC), C.c_int64, _P(HParams), C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
     "ntc_pack_mlp_train": (C.c_int, [_P(Material), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
-    "ntc_forward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
-                              C.c_void_p]),
+    "ntc_forward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_void_p]),
     "ntc_backward_workspace_bytes": (C.c_size_t, [_P(Material), C.c_int64, C.c_int]),
     "ntc_backward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
                                C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -195,9 +195,9 @@ def pack_mlp_train(m: Material, mlp, precision, packed, stream=None):
            "ntc_pack_mlp_train")
 
 
-def forward(m: Material, latents, mlp_packed, precision, queries, n, out, stream=None):
-    _check(_lib.ntc_forward(C.byref(m), _ptr(latents), _ptr(mlp_packed), precision, _ptr(queries), n, _ptr(out),
-                            _stream(stream)), "ntc_forward")
+def forward(m: Material, latents, mlp, mlp_train_packed, precision, queries, n, out, stream=None):
+    _check(_lib.ntc_forward(C.byref(m), _ptr(latents), _ptr(mlp), _ptr(mlp_train_packed), precision, _ptr(queries),
+                            n, _ptr(out), _stream(stream)), "ntc_forward")
 
 
 def backward_workspace_bytes(m: Material, n: int, precision=F32) -> int:

@@ -96,6 +96,7 @@ def test_dequantized_values_exact_in_fp16_fp8():
     for B in (2, 4):
         v = O.dequantize_codes(np.arange(2 ** B), B)
         assert np.array_equal(v.astype(np.float16).astype(np.float64), v)
+        assert np.array_equal(O.round_e4m3(v), v)
 
 
 def test_pack_lsb_first_hand_example():
@@ -257,6 +258,65 @@ def test_hard_gelu():
     e = 1e-9
     for b in (-1.5, 1.5):
         assert abs(O.hard_gelu(b - e) - O.hard_gelu(b + e)) < 1e-8
+
+
+# ---------------------------------------------------------------- FP8-e4m3 decode (sec 8)
+def test_e4m3_code_table():
+    """The bit-field decoder against hand values, and the rounder against every code."""
+    assert O.e4m3_value(0x00) == 0.0 and O.e4m3_value(0x01) == 2.0 ** -9
+    assert O.e4m3_value(0x07) == 7 * 2.0 ** -9 and O.e4m3_value(0x08) == 2.0 ** -6
+    assert O.e4m3_value(0x38) == 1.0 and O.e4m3_value(0x3C) == 1.5 and O.e4m3_value(0xB8) == -1.0
+    assert O.e4m3_value(0x7E) == 448.0 and math.isnan(O.e4m3_value(0x7F)) and math.isnan(O.e4m3_value(0xFF))
+    vals = np.array([O.e4m3_value(c) for c in range(256)])
+    fin = vals[~np.isnan(vals)]
+    assert len(fin) == 254                                     # 2 x 127 finite patterns (+0 and -0)
+    assert np.array_equal(O.round_e4m3(fin), fin)              # every value is its own rounding
+
+
+def test_e4m3_rounding_ties_and_saturation():
+    pos = [O.e4m3_value(c) for c in range(0x7F)]               # increasing positive values, 0 .. 448
+    for c in range(0x7E):
+        a, b = pos[c], pos[c + 1]
+        mid = 0.5 * (a + b)
+        even = a if c % 2 == 0 else b                          # the pattern with mantissa lsb 0
+        assert O.round_e4m3(mid) == even
+        assert O.round_e4m3(mid - 1e-6 * (b - a)) == a
+        assert O.round_e4m3(mid + 1e-6 * (b - a)) == b
+        assert O.round_e4m3(-mid) == -even
+    assert O.round_e4m3(0.3) == 0.3125                        # spacing 1/32 in [1/4, 1/2)
+    assert O.round_e4m3(460.0) == 448.0 and O.round_e4m3(1e6) == 448.0 and O.round_e4m3(-1e6) == -448.0
+    assert math.isnan(O.round_e4m3(np.nan))
+
+
+def test_fp8_forward_exact_case():
+    """Inputs, weights (after the per-layer scale) and hidden values all exact in e4m3:
+    the FP8 network equals the float64 network.  A misapplied scale or a layer rounded
+    in the wrong place breaks this."""
+    K, Hd, C = 20, 16, 4
+    rng = np.random.default_rng(8)
+    def sparse_pm1(rows, cols):
+        W = np.zeros((rows, cols))
+        for j in range(cols):
+            i = rng.choice(rows, 2, replace=False)
+            W[i, j] = rng.choice([-1.0, 1.0], 2)
+        return W
+    W1, W2 = sparse_pm1(K, Hd), sparse_pm1(Hd, Hd)
+    W3 = rng.choice([-1.0, -0.5, 0.25, 0.5, 1.0], (Hd, C))
+    b1, b2, b3 = np.zeros(Hd), np.zeros(Hd), rng.uniform(-1, 1, C)
+    p = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])
+    x = rng.choice([0.0, 0.5], (50, K))
+    y8 = O.mlp_forward_fp8(p, x, K, Hd, C)
+    y, _ = O.mlp_forward(p, x, K, Hd, C)
+    assert np.max(np.abs(y8 - y)) < 1e-12
+    assert O.fp8_layer_scales(p, K, Hd, C) == [1 / 448, 1 / 448, 1 / 448]
+    # one inexact hidden value changes the result by exactly its rounding
+    p2 = p.copy()
+    p2[K * Hd] = 0.3                                           # b1[0]: h1[0] = z + 0.3 is not in e4m3
+    p2[K * Hd + Hd] = 1.0                                      # W2[0][0]: h1[0] reaches the output
+    y8b = O.mlp_forward_fp8(p2, x, K, Hd, C)
+    _, (z1, h1, _, _) = O.mlp_forward(p2, x, K, Hd, C)
+    assert not np.allclose(O.round_e4m3(h1[:, 0]), h1[:, 0])
+    assert np.max(np.abs(y8b - O.mlp_forward(p2, x, K, Hd, C)[0])) > 0
 
 
 # ---------------------------------------------------------------- optimiser (sec 4.5, 5.1)

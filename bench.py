@@ -34,11 +34,43 @@ PEAK_F32_TFLOPS = 157.3    # MI355X FP32 matrix / vector peak
 PEAK_HBM_GBS = 8000.0
 
 TRAIN = dict(W=2048, C=12, c0=12, c1=12, b0=4, b1=4, hidden=64, n=262144, lr_lat=0.01, lr_mlp=0.005)
-DECODE = dict(W=4096, C=16, c0=16, c1=16, b0=2, b1=4, hidden=64)
+DECODE = dict(W=4096, C=16, c0=16, c1=16, b0=2, b1=4, hidden=64, train_steps=300)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ("train.hip", "ntc_device.h", "ntc_internal.h")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "train_fused_kernel_2048x12_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_17105_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch of the FP16 fused training kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, each scaled by what the counter reads
+    for a plain copy of known size; None when the kernel sources changed since."""
+    try:
+        kv = {}
+        for line in open(COUNTERS_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip().lstrip("- ").strip("`")] = v.strip().strip("`")
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        f = float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_scale"])
+        w = float(kv["write_kib_per_launch"]) * float(kv["copy_write_scale"])
+        return int(round((f + w) * 1024))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def train_flops_per_sample(K, Hd, C, Klat):
@@ -93,19 +125,19 @@ class TrainBench:
         for s in range(warmup):
             h = hp(s)
             ntc.train_step(m, st, self.pool[s % 8], n, self.targets, h, ws)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        hps = [hp(warmup + i) for i in range(steps)]
         torch.cuda.synchronize()
+        # the library records HIP events around each launch of the fused kernel on the
+        # launch stream (the roofline's per-launch duration)
+        ntc.timing_begin(steps)
         t0 = time.perf_counter()
         for i in range(steps):
-            s = warmup + i
-            h = hp(s)
-            ev[i][0].record()
-            ntc.train_gradients(m, st, self.pool[s % 8], n, self.targets, h, ws)
-            ev[i][1].record()
-            ntc.train_update(m, st, n, h, ws)
+            ntc.train_step(m, st, self.pool[(warmup + i) % 8], n, self.targets, hps[i], ws)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        fused_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        ktot, kcnt = ntc.timing_read("train_fused")
+        ntc.timing_end()
+        fused_ms = ktot / kcnt
         loss = float(st.loss.cpu()[0])
         return dict(seconds=dt, ms_per_step=dt / steps * 1e3, samples_per_s=n * steps / dt, fused_ms=fused_ms,
                     loss=loss, state=st)
@@ -142,35 +174,73 @@ def _unit_mlp(synth, K, Hd, C, seed=0):
 
 
 def run_decode(ntc, synth, torch, nq, reps, seed=0):
+    """Decode workload: the 4096^2 x 16 material (G0 2-bit, G1 4-bit) trained briefly in
+    FP32 on its own value-noise targets, then decoded with FP16, FP8-e4m3 and FP32
+    matrix cores: 16M random (u, v, LOD) queries per launch and the coherent full
+    mip 0; PSNR (Eq. 1) of mip 0 for each precision."""
     d = DECODE
     m = ntc.material_init(d["W"], d["W"], d["C"], d["c0"], d["c1"], d["b0"], d["b1"], d["hidden"])
+    t0 = time.time()
+    targets = synth.target_chain_torch(seed, 1, d["W"], d["W"], d["C"], int(m.num_mips), "cuda")
     raw = torch.from_numpy(synth.uniform_latents(seed, int(m.latent_count))).cuda()
     packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
     ntc.quantize_latents(m, raw, packed)
-    mlp = torch.from_numpy(_unit_mlp(synth, m.input_width, d["hidden"], d["C"], seed)).cuda()
+    lat0 = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+    ntc.dequantize_latents(m, packed, lat0)
+    mlp0 = torch.from_numpy(synth.xavier_mlp(seed, m.input_width, d["hidden"], d["C"])).cuda()
+    n = TRAIN["n"]
+    st = ntc.TrainState(m, lat0, mlp0, ntc.F32)
+    ws = torch.zeros(ntc.train_workspace_bytes(m, n, ntc.F32), dtype=torch.uint8, device="cuda")
+    pool = [torch.from_numpy(synth.random_queries(seed + 31 * i, n, m.num_mips).view(np.uint8).copy()).cuda()
+            for i in range(4)]
+    steps = d["train_steps"]
+    for s in range(steps):
+        c = 0.5 * (1.0 + math.cos(math.pi * s / steps))
+        h = ntc.hparams(lr_latent=TRAIN["lr_lat"] * c, lr_mlp=TRAIN["lr_mlp"] * c, step=s, precision=ntc.F32,
+                        noise=True, seed=2)
+        if s == 0:
+            ntc.train_prepare(m, st, h)
+        ntc.train_step(m, st, pool[s % 4], n, targets, h, ws)
+    ntc.quantize_latents(m, st.latents, packed)
+    mlp = st.mlp.clone()
+    torch.cuda.synchronize()
+    log(f"[bench] decode material: targets + {steps} FP32 training steps in {time.time() - t0:.1f}s")
+
     q_rand = torch.from_numpy(synth.random_queries(seed + 5, nq, m.num_mips).view(np.uint8).copy()).cuda()
     q_tile = torch.from_numpy(synth.tile_queries(d["W"], d["W"], 0).view(np.uint8).copy()).cuda()
     n_tile = d["W"] * d["W"]
     out = torch.empty(max(nq, n_tile) * d["C"], dtype=torch.float16, device="cuda")
-    res = {}
-    for name, prec in (("f16", ntc.F16), ("f32", ntc.F32)):
+    out32 = torch.empty(n_tile * d["C"], dtype=torch.float32, device="cuda")
+    ref0 = targets[:n_tile * d["C"]].double()
+    fl_q = decode_flops_per_query(m.input_width, d["hidden"], d["C"])
+    res = {"steps_trained_fp32": steps}
+    for name, prec in (("f16", ntc.F16), ("fp8", ntc.FP8_E4M3), ("f32", ntc.F32)):
         wp = torch.zeros(ntc.mlp_packed_bytes(m, prec), dtype=torch.uint8, device="cuda")
         ntc.pack_mlp(m, mlp, prec, wp)
-        for kind, qd, n in (("random", q_rand, nq), ("coherent", q_tile, n_tile)):
+        for kind, qd, nn in (("random", q_rand, nq), ("coherent", q_tile, n_tile)):
             for _ in range(2):
-                ntc.decode(m, packed, wp, prec, qd, n, out, ntc.F16)
+                ntc.decode(m, packed, wp, prec, qd, nn, out, ntc.F16)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
+            ntc.timing_begin(reps)
             e0.record()
             for _ in range(reps):
-                ntc.decode(m, packed, wp, prec, qd, n, out, ntc.F16)
+                ntc.decode(m, packed, wp, prec, qd, nn, out, ntc.F16)
             e1.record()
             torch.cuda.synchronize()
+            ktot, kcnt = ntc.timing_read("decode")
+            ntc.timing_end()
             ms = e0.elapsed_time(e1) / reps
-            fl = decode_flops_per_query(m.input_width, d["hidden"], d["C"]) * n
-            res[f"{kind}_{name}"] = dict(queries=n, ms=round(ms, 4), texels_per_s=n / (ms * 1e-3),
-                                         tflops=fl / (ms * 1e-3) / 1e12)
-            log(f"[bench] decode {kind} {name}: {ms:.3f} ms for {n} queries -> {n / (ms * 1e-3):.3e} texels/s")
+            kms = ktot / kcnt
+            res[f"{kind}_{name}"] = dict(queries=nn, ms=round(ms, 4), kernel_ms=round(kms, 4),
+                                         texels_per_s=nn / (ms * 1e-3), tflops=fl_q * nn / (kms * 1e-3) / 1e12)
+            log(f"[bench] decode {kind} {name}: {ms:.3f} ms for {nn} queries -> {nn / (ms * 1e-3):.3e} texels/s "
+                f"(kernel {kms:.3f} ms)")
+        ntc.decode(m, packed, wp, prec, q_tile, n_tile, out32, ntc.F32)
+        mse = float(((out32.double() - ref0) ** 2).mean())
+        res[f"psnr_mip0_{name}"] = round(-10.0 * math.log10(mse), 3)
+    log(f"[bench] decode PSNR of mip 0: f32 {res['psnr_mip0_f32']} dB, f16 {res['psnr_mip0_f16']} dB, "
+        f"fp8 {res['psnr_mip0_fp8']} dB")
     return res
 
 
@@ -256,7 +326,7 @@ def main():
     fps = train_flops_per_sample(m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1)
     ach = fps * tb.n / (r16["fused_ms"] * 1e-3) / 1e12
     roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
-                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4), traffic=None,
+                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4), traffic=counter_traffic(),
                 flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4))
     ach32 = fps * tb.n / (r32["fused_ms"] * 1e-3) / 1e12
 

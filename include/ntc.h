@@ -125,9 +125,14 @@ ntc_status ntc_dequantize_latents(const ntc_material* m, const uint8_t* packed, 
 /*
  * Network weights for decoding.  ntc_pack_mlp converts the canonical FP32 MLP
  * (m->mlp_params floats) into the library's matrix-core operand layout in the
- * given compute precision (NTC_F32 or NTC_F16).  `packed` must hold
+ * given compute precision (NTC_F32, NTC_F16 or NTC_FP8_E4M3).  `packed` must hold
  * ntc_mlp_packed_bytes(m, precision) bytes; its content is private to the
  * library and valid only for the same material shape and precision.
+ * NTC_FP8_E4M3 (the lower-precision intermediates of section 8): per layer l the
+ * pack holds the e4m3 rounding (OCP E4M3, round to nearest even) of W_l / s_l with
+ * s_l = max|W_l| / 448, computed on the device; biases stay FP32.  It needs G0 cells
+ * of whole 32-bit words (c0 * b0 a multiple of 32), b0, b1 <= 4 and hidden 32 or 64;
+ * otherwise ntc_mlp_packed_bytes returns 0 and ntc_pack_mlp NTC_E_UNSUPPORTED.
  */
 size_t ntc_mlp_packed_bytes(const ntc_material* m, ntc_dtype precision);
 ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype precision,
@@ -137,8 +142,9 @@ ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype preci
  * Decode all C channels of n texels (sections 4.3-4.4) from the packed latents.
  *   q: n queries.  out: n x C values, row-major, of out_dtype (NTC_F32 or NTC_F16).
  *   precision: arithmetic of the MLP (NTC_F32: FP32 matrix cores; NTC_F16: FP16
- *   inputs with FP32 accumulation); `mlp_packed` must come from ntc_pack_mlp with
- *   the same precision.  n == 0 is a no-op.
+ *   inputs with FP32 accumulation; NTC_FP8_E4M3: e4m3 inputs, weights and hidden
+ *   activations, FP32 accumulation, s_l * sum + b_l in FP32); `mlp_packed` must come
+ *   from ntc_pack_mlp with the same precision.  n == 0 is a no-op.
  */
 ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
                       ntc_dtype precision, const ntc_query* q, int64_t n, void* out,
@@ -261,6 +267,20 @@ size_t ntc_backward_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype 
 ntc_status ntc_backward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
                         ntc_dtype precision, const ntc_query* q, int64_t n, const float* dout, float dout_scale,
                         float* grad_latents, float* grad_mlp, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Kernel timing for measurement (not needed for normal use).  After
+ * ntc_timing_begin(max_launches), the library records a HIP event pair on the launch
+ * stream around each of the next max_launches launches of every timed kernel
+ * ("train_fused": the fused training kernel of ntc_train_gradients / ntc_train_step /
+ * ntc_backward; "decode": the kernel of ntc_decode).  ntc_timing_read waits for the
+ * recorded events and returns their summed elapsed time and count; ntc_timing_end
+ * synchronizes the device, stops recording and frees the events.  Calls from several
+ * threads are serialized; begin resets earlier records.
+ */
+ntc_status ntc_timing_begin(int32_t max_launches);
+ntc_status ntc_timing_read(const char* kernel, double* total_ms, int32_t* launches);
+ntc_status ntc_timing_end(void);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,81 @@ __device__ inline f16x2 code_pair(uint32_t w, int s) {
   return __builtin_bit_cast(f16x2, ((w >> s) & pm) | 0x64006400u);
 }
 
+// The bit-packed code words one texel's lane group needs (its G0 neighbour cell and
+// the four G1 taps) plus what the input assembly needs from the footprint.
+template <int C0, int C1, int B0, int B1>
+struct CodeWindow {
+  static constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
+  int ix, iy;
+  float fx, fy, w[4];
+  uint32_t g0[NW0];
+  uint32_t g1[4][NW1];
+  __device__ inline void fetch(const DevMat& m, const uint32_t* __restrict__ packed, float u, float v, int lod,
+                               int g) {
+    const Footprint f = locate(m, u, v, lod, g);
+    ix = f.ix;
+    iy = f.iy;
+    fx = f.fx;
+    fy = f.fy;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = f.g1_w[k];
+    load_bits<NW0, NB0 % 32 == 0>(packed, m.g0_pk[f.j] * 8 + (long long)f.g0_cell * NB0, m.g0_pk_end[f.j], g0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      load_bits<NW1, NB1 % 32 == 0>(packed, m.g1_pk[f.j] * 8 + (long long)f.g1_cell[k] * NB1, m.g1_pk_end[f.j], g1[k]);
+  }
+};
+
+// G1 bilinear of the paired layout: pair p = d * (4/B1) + kk holds channels
+// d*32/B1 + g + 4kk and that + 16/B1.  Separable, in centred code units: the row steps
+// are exact, the column step rounds once, the power-of-two scale is exact, so the
+// result equals the FP16 rounding of the exact bilinear value.
+template <int C0, int C1, int B0, int B1>
+__device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
+                                f16x2 (&out)[CodeWindow<C0, C1, B0, B1>::NW1 * (4 / B1)]) {
+  constexpr int NW1 = CodeWindow<C0, C1, B0, B1>::NW1, KP = 4 / B1, N1 = 1 << B1;
+  const f16x2 fx = {(_Float16)R.fx, (_Float16)R.fx}, fy = {(_Float16)R.fy, (_Float16)R.fy};
+  const _Float16 o = (_Float16)(-(1024.f + N1 / 2 - 1));
+  const f16x2 of = {o, o};
+  const f16x2 sc = {(_Float16)(1.f / N1), (_Float16)(1.f / N1)};
+#pragma unroll
+  for (int d = 0; d < NW1; ++d)
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+      const int sh = B1 * (g + 4 * kk);
+      const f16x2 x0 = code_pair<B1>(R.g1[0][d], sh), x1 = code_pair<B1>(R.g1[1][d], sh);
+      const f16x2 x2 = code_pair<B1>(R.g1[2][d], sh), x3 = code_pair<B1>(R.g1[3][d], sh);
+      const f16x2 r0 = __builtin_elementwise_fma(fx, x1 - x0, x0 + of);
+      const f16x2 r1 = __builtin_elementwise_fma(fx, x3 - x2, x2 + of);
+      out[d * KP + kk] = __builtin_elementwise_fma(fy, r1 - r0, r0) * sc;
+    }
+}
+
+// Lane group g's four output channels 4g .. 4g+3 of texel s.
+template <int C>
+__device__ inline void store_out(void* __restrict__ out, int out_f16, long long s, long long n, int g, f32x4 y) {
+  if (s >= n || 4 * g >= C) return;
+  if (out_f16) {
+    _Float16* o = reinterpret_cast<_Float16*>(out) + s * C + 4 * g;
+    if constexpr (C % 4 == 0) {
+      *reinterpret_cast<f16x4*>(o) = __builtin_convertvector(y, f16x4);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < C) o[i] = (_Float16)y[i];
+    }
+  } else {
+    float* o = reinterpret_cast<float*>(out) + s * C + 4 * g;
+    if constexpr (C % 4 == 0) {
+      *reinterpret_cast<f32x4*>(o) = y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < C) o[i] = y[i];
+    }
+  }
+}
+
 // PACKED: latents come as bit-packed codes (ntc_decode); otherwise as FP32 values
 // in the canonical latent layout (ntc_forward, the differentiation path).
 // bias: b1 (HD), b2 (HD), b3 (C) at the three given addresses.
@@ -84,27 +159,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
     // layer 3 (no activation): lane group g holds channels 4g .. 4g+3
     f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
     y = mma_slots<SH>(y, w_lds + pg.L3, h, lane);
-    if (s < n && 4 * g < C) {
-      if (out_f16) {
-        _Float16* o = reinterpret_cast<_Float16*>(out) + s * C + 4 * g;
-        if constexpr (C % 4 == 0) {
-          *reinterpret_cast<f16x4*>(o) = __builtin_convertvector(y, f16x4);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (4 * g + i < C) o[i] = (_Float16)y[i];
-        }
-      } else {
-        float* o = reinterpret_cast<float*>(out) + s * C + 4 * g;
-        if constexpr (C % 4 == 0) {
-          *reinterpret_cast<f32x4*>(o) = y;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (4 * g + i < C) o[i] = y[i];
-        }
-      }
-    }
+    store_out<C>(out, out_f16, s, n, g, y);
   };
   auto pe_slots = [&](T (&xs)[S1], int ix, int iy) {
     float pv[3];
@@ -129,27 +184,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
   if constexpr (PACKED) {
     // Software pipeline over the wave's tiles: queries two tiles ahead, latent words
     // one tile ahead, so both gathers are in flight while the matrix cores run.
-    constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
-    struct Raw {
-      int ix, iy;
-      float fx, fy, w[4];
-      uint32_t g0[NW0];
-      uint32_t g1[4][NW1];
-    };
-    auto fetch = [&](float u, float v, int lod, Raw& R) {
-      const Footprint f = locate(m, u, v, lod, g);
-      R.ix = f.ix;
-      R.iy = f.iy;
-      R.fx = f.fx;
-      R.fy = f.fy;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) R.w[k] = f.g1_w[k];
-      load_bits<NW0, NB0 % 32 == 0>(packed, m.g0_pk[f.j] * 8 + (long long)f.g0_cell * NB0, m.g0_pk_end[f.j], R.g0);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        load_bits<NW1, NB1 % 32 == 0>(packed, m.g1_pk[f.j] * 8 + (long long)f.g1_cell[k] * NB1, m.g1_pk_end[f.j],
-                                      R.g1[k]);
-    };
+    using Raw = CodeWindow<C0, C1, B0, B1>;
     auto assemble = [&](const Raw& R, T (&xs)[S1]) {
       if constexpr (DL::paired) {
         {  // G0: two channels per instruction; (1024 + code) / N - (N/2 - 1 + 1024) / N is exact
@@ -158,7 +193,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
           const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
           const f16x2 of = {o, o};
 #pragma unroll
-          for (int d = 0; d < NW0; ++d)
+          for (int d = 0; d < Raw::NW0; ++d)
 #pragma unroll
             for (int c = 0; c < HALF; ++c) {
               const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
@@ -166,27 +201,12 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
               xs[2 * (d * HALF + c) + 1] = x[1];
             }
         }
-        {  // G1: separable bilinear in centred code units; the row steps are exact, the
-           // column step rounds once and the power-of-two scale is exact
-          constexpr int KP = 4 / B1, N1 = 1 << B1;
-          const f16x2 fx = {(_Float16)R.fx, (_Float16)R.fx}, fy = {(_Float16)R.fy, (_Float16)R.fy};
-          const _Float16 o = (_Float16)(-(1024.f + N1 / 2 - 1));
-          const f16x2 of = {o, o};
-          const f16x2 sc = {(_Float16)(1.f / N1), (_Float16)(1.f / N1)};
+        f16x2 v[Raw::NW1 * (4 / B1)];
+        g1_pairs(R, g, v);
 #pragma unroll
-          for (int d = 0; d < NW1; ++d)
-#pragma unroll
-            for (int kk = 0; kk < KP; ++kk) {
-              const int sh = B1 * (g + 4 * kk);
-              const f16x2 x0 = code_pair<B1>(R.g1[0][d], sh), x1 = code_pair<B1>(R.g1[1][d], sh);
-              const f16x2 x2 = code_pair<B1>(R.g1[2][d], sh), x3 = code_pair<B1>(R.g1[3][d], sh);
-              const f16x2 r0 = __builtin_elementwise_fma(fx, x1 - x0, x0 + of);
-              const f16x2 r1 = __builtin_elementwise_fma(fx, x3 - x2, x2 + of);
-              const f16x2 v = __builtin_elementwise_fma(fy, r1 - r0, r0) * sc;
-              const int t = C0 + 2 * (d * KP + kk);
-              xs[t] = v[0];
-              xs[t + 1] = v[1];
-            }
+        for (int p = 0; p < Raw::NW1 * (4 / B1); ++p) {
+          xs[C0 + 2 * p] = v[p][0];
+          xs[C0 + 2 * p + 1] = v[p][1];
         }
       } else {
 #pragma unroll
@@ -214,11 +234,11 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
     int lod;
     load_query(tile, u, v, lod);
     Raw cur;
-    fetch(u, v, lod, cur);
+    cur.fetch(m, packed, u, v, lod, g);
     load_query(tile + stride, u, v, lod);
     for (; tile < tiles; tile += stride) {
       Raw nxt;
-      if (tile + stride < tiles) fetch(u, v, lod, nxt);
+      if (tile + stride < tiles) nxt.fetch(m, packed, u, v, lod, g);
       if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
       T xs[S1];
       assemble(cur, xs);
@@ -252,6 +272,180 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
   }
 }
 
+// ------------------------------------------------------------------ FP8-e4m3 decode
+// Same pipeline as the FP16 decoder; operands are e4m3 bytes, four slots per word.
+// G0 codes go through a byte lookup (v_perm) straight to e4m3 patterns of their exact
+// dequantized values; G1 values are the paired FP16 bilinear values rounded to e4m3;
+// layer outputs are s_l * acc + b_l in FP32, the activation, then e4m3 again.
+template <int B>
+__device__ inline uint32_t codes_to_e4m3(uint32_t codes) {  // one code (< 2^B) per byte
+  constexpr uint32_t L0 = e4m3_code_lut(B, 0), L1 = e4m3_code_lut(B, 1);
+  if constexpr (B <= 3) {
+    return __builtin_amdgcn_perm(L1, L0, codes);
+  } else {
+    constexpr uint32_t L2 = e4m3_code_lut(B, 2), L3 = e4m3_code_lut(B, 3);
+    const uint32_t sel = codes & 0x07070707u;
+    const uint32_t lo = __builtin_amdgcn_perm(L1, L0, sel), hi = __builtin_amdgcn_perm(L3, L2, sel);
+    const uint32_t mask = ((codes >> 3) & 0x01010101u) * 0xFFu;
+    return (hi & mask) | (lo & ~mask);
+  }
+}
+
+template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
+__global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, const uint32_t* __restrict__ packed,
+                                                         const uint8_t* __restrict__ wpack,
+                                                         const float* __restrict__ scales,
+                                                         const float* __restrict__ bias,
+                                                         const ntc_query* __restrict__ q, long long n,
+                                                         void* __restrict__ out, int out_f16) {
+  constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
+  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT;
+  constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
+  using Raw = CodeWindow<C0, C1, B0, B1>;
+  constexpr int NP = Raw::NW1 * (4 / B1);  // G1 pairs per lane group
+  extern __shared__ __align__(16) char smem[];
+  const uint8_t* w_lds = reinterpret_cast<const uint8_t*>(smem);
+  float* pe_lds = reinterpret_cast<float*>(smem + WB);
+  float* b_lds = pe_lds + 48;
+
+  for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
+    reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
+  for (int i = threadIdx.x; i < 48; i += blockDim.x) pe_lds[i] = pe.v[i / 6][i % 6];
+  for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x) b_lds[i] = i < 2 * HD + C ? bias[i] : 0.f;
+  __syncthreads();
+  const float sc1 = scales[0], sc2 = scales[1], sc3 = scales[2];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const long long tiles = (n + 15) / 16, stride = (long long)gridDim.x * 4;
+
+  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
+    const long long s = tile * 16 + r;
+    u = v = 0.f;
+    lod = 0;
+    if (tile < tiles && s < n) {
+      u = q[s].u;
+      v = q[s].v;
+      lod = q[s].lod;
+    }
+  };
+  // A operand of MFMA kk of M-tile mo of a layer pack with S slots
+  auto a_op = [&](long long base, int S, int mo, int kk) -> long {
+    return *reinterpret_cast<const long*>(w_lds + base + (long long)mo * S * 64 + kk * 512 + lane * 8);
+  };
+  // hidden layer: act(s * acc + b) of fragment mo as 4 e4m3 bytes (slots 4mo .. 4mo+3)
+  auto hidden_word = [&](f32x4 acc, float s, const float* b, int mo) -> uint32_t {
+    const f32x4 bb = *reinterpret_cast<const f32x4*>(b + 16 * mo + 4 * g);
+    float h[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // activation, saturated to the e4m3 range (the conversion alone gives NaN)
+      const float z = __builtin_fmaf(acc[i], s, bb[i]);
+      h[i] = ACT == 0 ? __builtin_amdgcn_fmed3f(z, 0.f, 448.f) : __builtin_amdgcn_fmed3f(act_fn<ACT>(z), -448.f, 448.f);
+    }
+    return cvt_e4m3x2(h[2], h[3], cvt_e4m3x2(h[0], h[1], 0u, false), true);
+  };
+
+  long long tile = (long long)blockIdx.x * 4 + wave;
+  if (tile >= tiles) return;
+  float u, v;
+  int lod;
+  load_query(tile, u, v, lod);
+  Raw cur;
+  cur.fetch(m, packed, u, v, lod, g);
+  load_query(tile + stride, u, v, lod);
+  for (; tile < tiles; tile += stride) {
+    Raw nxt;
+    if (tile + stride < tiles) nxt.fetch(m, packed, u, v, lod, g);
+    if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
+
+    // ---- inputs: S1/4 words of e4m3 bytes
+    uint32_t xw[S1 / 4];
+#pragma unroll
+    for (int i = 0; i < S1 / 4; ++i) xw[i] = 0u;
+    constexpr uint32_t BM = ((1u << B0) - 1u) * 0x01010101u;
+#pragma unroll
+    for (int d = 0; d < Raw::NW0; ++d)
+#pragma unroll
+      for (int k = 0; k < 8 / B0; ++k) xw[(8 / B0) * d + k] = codes_to_e4m3<B0>((cur.g0[d] >> (B0 * k)) & BM);
+    {
+      f16x2 pv2[NP];
+      g1_pairs(cur, g, pv2);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int t = C0 + 2 * p;
+        xw[t / 4] = cvt_e4m3x2((float)pv2[p][0], (float)pv2[p][1], xw[t / 4], (t % 4) != 0);
+      }
+      float pv[3];
+      pe_values(pe_lds, cur.ix, cur.iy, g, pv);
+      constexpr int t0 = pg.T_lat;  // even
+      xw[t0 / 4] = cvt_e4m3x2(pv[0], pv[1], xw[t0 / 4], (t0 % 4) != 0);
+      xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], 0.f, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
+    }
+    // ---- layer 1
+    uint32_t hw[SH / 4];
+#pragma unroll
+    for (int mo = 0; mo < MT; ++mo) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < S1 / 8; ++kk) {
+        const long b = (long)((uint64_t)xw[2 * kk] | (uint64_t)xw[2 * kk + 1] << 32);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L1, S1, mo, kk), b, acc, 0, 0, 0);
+      }
+      hw[mo] = hidden_word(acc, sc1, b_lds, mo);
+    }
+    // ---- layer 2
+    uint32_t hw2[SH / 4];
+#pragma unroll
+    for (int mo = 0; mo < MT; ++mo) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < SH / 8; ++kk) {
+        const long b = (long)((uint64_t)hw[2 * kk] | (uint64_t)hw[2 * kk + 1] << 32);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L2, SH, mo, kk), b, acc, 0, 0, 0);
+      }
+      hw2[mo] = hidden_word(acc, sc2, b_lds + HD, mo);
+    }
+    // ---- layer 3 (no activation)
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < SH / 8; ++kk) {
+      const long b = (long)((uint64_t)hw2[2 * kk] | (uint64_t)hw2[2 * kk + 1] << 32);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L3, SH, 0, kk), b, acc, 0, 0, 0);
+    }
+    const f32x4 b3 = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
+    f32x4 y;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = __builtin_fmaf(acc[i], sc3, b3[i]);
+    store_out<C>(out, out_f16, tile * 16 + r, n, g, y);
+    cur = nxt;
+  }
+}
+
+template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
+static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, const void* wpack, const ntc_query* q,
+                                long long n, void* out, bool out_f16, hipStream_t s) {
+  constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
+  constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4;
+  const float* scales = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
+  auto kern = decode_fp8_kernel<C0, C1, C, HD, B0, B1, ACT>;
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds) != hipSuccess || v < 1) v = 1;
+    per_cu = v;
+  }
+  const long long tiles = (n + 15) / 16;
+  long long grid = (tiles + 3) / 4;
+  const long long cap = (long long)device_cus() * per_cu;
+  if (grid > cap) grid = cap;
+  const int slot = timing_before(TK_DECODE, s);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(),
+                     reinterpret_cast<const uint32_t*>(packed), reinterpret_cast<const uint8_t*>(wpack), scales,
+                     scales + 4, q, n, out, out_f16 ? 1 : 0);
+  timing_after(TK_DECODE, s, slot);
+  return hipGetLastError();
+}
+
 // mlp: canonical FP32 parameters supplying the biases, or nullptr when the biases
 // follow the weights in the pack (decode packs)
 template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
@@ -281,8 +475,10 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
   long long grid = (tiles + 3) / 4;
   const long long cap = (long long)device_cus() * per_cu;
   if (grid > cap) grid = cap;
+  const int slot = PACKED ? timing_before(TK_DECODE, s) : -1;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(), src,
                      reinterpret_cast<const T*>(wpack), b1, b2, b3, q, n, out, out_f16 ? 1 : 0);
+  timing_after(TK_DECODE, s, slot);
   return hipGetLastError();
 }
 
@@ -312,6 +508,18 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
   if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)      \
     return f16 ? decode_t<_Float16, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s) \
                : decode_t<float, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s);
+  NTC_DECODE_SHAPES(NTC_X)
+#undef NTC_X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_decode_fp8(const ntc_material& m, const uint8_t* packed, const void* wpack, const ntc_query* q,
+                             long long n, void* out, bool out_f16, hipStream_t s) {
+#define NTC_X(a, b, cc, h, x0, x1)                                                                   \
+  if constexpr (fp8_layout(a, b, x0, x1, h))                                                         \
+    if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)    \
+      return m.activation ? decode_fp8_t1<a, b, cc, h, x0, x1, 1>(m, packed, wpack, q, n, out, out_f16, s) \
+                          : decode_fp8_t1<a, b, cc, h, x0, x1, 0>(m, packed, wpack, q, n, out, out_f16, s);
   NTC_DECODE_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;

@@ -211,7 +211,14 @@ ntc_status ntc_dequantize_latents(const ntc_material* m, const uint8_t* packed, 
 
 static size_t round16(size_t b) { return (b + 15) / 16 * 16; }
 
+static bool fp8_supported(const ntc_material* m) {
+  return fp8_layout(m->c0, m->c1, m->b0, m->b1, m->hidden) &&
+         decode_shape_supported(m->c0, m->c1, m->channels, m->hidden, m->b0, m->b1);
+}
+
 size_t ntc_mlp_packed_bytes(const ntc_material* m, ntc_dtype precision) {
+  if (m && precision == NTC_FP8_E4M3)
+    return fp8_supported(m) ? fp8_pack_weight_bytes(*m) + 16 + round16((size_t)(2 * m->hidden + m->channels) * 4) : 0;
   if (!m || (precision != NTC_F32 && precision != NTC_F16)) return 0;
   const bool f16 = precision == NTC_F16;
   const PackGeom pg = pack_geom_decode(m->c0, m->c1, m->b0, m->b1, m->hidden, f16);
@@ -229,7 +236,14 @@ size_t ntc_train_packed_bytes(const ntc_material* m, ntc_dtype precision) {
 ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype precision, void* packed, void* stream) {
   ntc_status st = check_material(m);
   if (st != NTC_OK) return st;
-  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "pack precision must be F32 or F16");
+  if (precision == NTC_FP8_E4M3) {
+    if (!fp8_supported(m))
+      return fail(NTC_E_UNSUPPORTED, "FP8 decode needs whole-dword G0 cells, b0, b1 <= 4 and a decode shape");
+    if (!mlp || !packed) return fail(NTC_E_INVALID, "NULL buffer");
+    return hip_status(launch_pack_mlp_fp8(*m, mlp, packed, (hipStream_t)stream), "ntc_pack_mlp");
+  }
+  if (precision != NTC_F32 && precision != NTC_F16)
+    return fail(NTC_E_UNSUPPORTED, "pack precision must be F32, F16 or FP8_E4M3");
   if (!mlp || !packed) return fail(NTC_E_INVALID, "NULL buffer");
   return hip_status(launch_pack_mlp(*m, mlp, precision == NTC_F16, false, packed, (hipStream_t)stream), "ntc_pack_mlp");
 }
@@ -239,13 +253,19 @@ ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, cons
                       void* stream) {
   ntc_status st = check_material(m);
   if (st != NTC_OK) return st;
-  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "decode precision must be F32 or F16");
+  if (precision != NTC_F32 && precision != NTC_F16 && precision != NTC_FP8_E4M3)
+    return fail(NTC_E_UNSUPPORTED, "decode precision must be F32, F16 or FP8_E4M3");
   if (out_dtype != NTC_F32 && out_dtype != NTC_F16) return fail(NTC_E_UNSUPPORTED, "output dtype must be F32 or F16");
   if (n < 0) return fail(NTC_E_INVALID, "n < 0");
   if (!decode_shape_supported(m->c0, m->c1, m->channels, m->hidden, m->b0, m->b1))
     return fail(NTC_E_UNSUPPORTED, "no decode kernel for this (c0, c1, channels, hidden, b0, b1)");
+  if (precision == NTC_FP8_E4M3 && !fp8_supported(m))
+    return fail(NTC_E_UNSUPPORTED, "FP8 decode needs whole-dword G0 cells and b0, b1 <= 4");
   if (n == 0) return NTC_OK;
   if (!packed_latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  if (precision == NTC_FP8_E4M3)
+    return hip_status(launch_decode_fp8(*m, packed_latents, mlp_packed, q, n, out, out_dtype == NTC_F16,
+                                        (hipStream_t)stream), "ntc_decode");
   return hip_status(launch_decode(*m, packed_latents, mlp_packed, precision == NTC_F16, q, n, out,
                                   out_dtype == NTC_F16, (hipStream_t)stream), "ntc_decode");
 }

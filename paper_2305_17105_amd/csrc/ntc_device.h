@@ -138,6 +138,66 @@ __host__ __device__ inline void in_slot_of_paired(int k, int c0, int c1, int b0,
   }
 }
 
+// FP8-e4m3 decode layout (16x16x32 fp8 matrix cores: 8 slots of a lane group per
+// instruction, one byte each).  Same eligibility as the paired layout.  G0 codes are
+// spread into bytes four at a time: for dword d and k < 8/B0, the word
+// (w >> B0*k) & byte-mask holds in byte b the code of channel d*32/B0 + b*8/B0 + k,
+// which goes to slot d*32/B0 + 4k + b.  G1 pairs and the PE follow the paired layout;
+// slots are padded to a multiple of 8.  Element offsets are bytes.
+__host__ __device__ constexpr bool fp8_layout(int c0, int c1, int b0, int b1, int hd) {
+  return paired_layout(c0, c1, b0, b1, true) && hd % 32 == 0;
+}
+__host__ __device__ constexpr PackGeom pack_geom_fp8(int c0, int c1, int b0, int b1, int hd) {
+  PackGeom p{};
+  p.T_lat = c0 + paired_g1_slots(c1, b1);
+  p.T_used = p.T_lat + 3;
+  p.S1 = (p.T_used + 7) / 8 * 8;
+  p.SH = hd / 4;
+  p.MT = hd / 16;
+  p.ML = (p.T_lat + 3) / 4;
+  p.L1 = 0;
+  p.L2 = p.L1 + (long long)p.MT * p.S1 * 64;
+  p.L3 = p.L2 + (long long)p.MT * p.SH * 64;
+  p.B3 = p.L3 + (long long)p.SH * 64;
+  p.fwd_end = p.B2 = p.B1 = p.train_end = p.B3;
+  return p;
+}
+__host__ __device__ inline void in_slot_of_fp8(int k, int c0, int c1, int b0, int b1, int& g, int& t) {
+  if (k < 4 * c0) {
+    const int c = k % c0, per = 32 / b0, d = c / per, cc = c % per, b = cc / (8 / b0), kk = cc % (8 / b0);
+    g = k / c0;
+    t = per * d + 4 * kk + b;
+  } else {
+    in_slot_of_paired(k, c0, c1, b0, b1, g, t);
+  }
+}
+// e4m3 bit pattern of a value that the format holds exactly (dequantized codes)
+__host__ __device__ constexpr uint32_t e4m3_exact_bits(float v) {
+  uint32_t s = v < 0 ? 0x80u : 0u;
+  float a = v < 0 ? -v : v;
+  if (a == 0.f) return s;
+  int e = 0;
+  while (a >= 2.f) { a *= 0.5f; ++e; }
+  while (a < 1.f) { a *= 2.f; --e; }
+  if (e < -6) {  // subnormal: m * 2^-9
+    float m = a;
+    for (int i = e; i < -9; ++i) m *= 0.5f;
+    for (int i = -9; i < e; ++i) m *= 2.f;
+    return s | (uint32_t)m;
+  }
+  return s | (uint32_t)(e + 7) << 3 | (uint32_t)((a - 1.f) * 8.f);
+}
+// Four e4m3 patterns of dequantized codes 4i .. 4i+3 of a B-bit grid, packed in a word.
+__host__ __device__ constexpr uint32_t e4m3_code_lut(int B, int i) {
+  const int N = 1 << B;
+  uint32_t w = 0;
+  for (int b = 0; b < 4; ++b) {
+    const int k = 4 * i + b;
+    if (k < N) w |= e4m3_exact_bits((float)(k - (N / 2 - 1)) / (float)N) << (8 * b);
+  }
+  return w;
+}
+
 // Runtime inverse slot maps (used where canonical weights are scattered into packs).
 __host__ __device__ inline void in_slot_of(int k, int c0, int c1, int& g, int& t) {
   const int tl = c0 + (c1 + 3) / 4;
@@ -158,6 +218,10 @@ __host__ __device__ inline int pack_index(int S, int mo, int t, int lane);
 template <>
 __host__ __device__ inline int pack_index<float>(int S, int mo, int t, int lane) {
   return (mo * S + t) * 64 + lane;
+}
+template <>
+__host__ __device__ inline int pack_index<uint8_t>(int S, int mo, int t, int lane) {
+  return mo * S * 64 + (t / 8) * 512 + lane * 8 + (t % 8);  // S is a multiple of 8
 }
 template <>
 __host__ __device__ inline int pack_index<_Float16>(int S, int mo, int t, int lane) {
@@ -215,6 +279,12 @@ __device__ inline float act_fn(float z) {
     return z < -1.5f ? 0.f : (z > 1.5f ? z : p);
   }
 }
+// FP32 -> e4m3 (round to nearest even) of two values into the low or high half of `old`.
+__device__ inline uint32_t cvt_e4m3x2(float a, float b, uint32_t old, bool hi) {
+  return hi ? (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, (int)old, true)
+            : (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, (int)old, false);
+}
+
 // a(z) of one accumulator fragment, rounded to the operand type T; ReLU in FP16
 // rounds first (rounding commutes with max(., 0)) and clamps two values per op
 template <int ACT, typename T>
@@ -241,6 +311,14 @@ __device__ inline float act_grad(float z) {
     const float p = (2.f * z + 1.5f) * (1.f / 3.f);
     return z < -1.5f ? 0.f : (z > 1.5f ? 1.f : p);
   }
+}
+
+// a'(z) given z and the stored activation h = a(z) in the operand type: ReLU takes
+// its decision from h (h > 0 exactly when z > 0, up to underflow of the rounding)
+template <int ACT, typename T>
+__device__ inline float dact(float z, T h) {
+  if constexpr (ACT == 0) return (float)h > 0.f ? 1.f : 0.f;
+  else return act_grad<ACT>(z);
 }
 
 // ------------------------------------------------------------------ sampling (section 4.3)

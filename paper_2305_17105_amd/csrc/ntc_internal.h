@@ -9,6 +9,12 @@
 
 namespace ntc {
 
+// Optional launch timing (ntc_timing_begin / _read / _end): a slot >= 0 when a start
+// event was recorded, to be closed by timing_after on the same stream.
+enum TimedKernel { TK_TRAIN_FUSED = 0, TK_DECODE = 1, TK_COUNT = 2 };
+int timing_before(TimedKernel k, hipStream_t s);
+void timing_after(TimedKernel k, hipStream_t s, int slot);
+
 // Thread-local error message for ntc_last_error().
 void set_error(const std::string& msg);
 
@@ -25,6 +31,11 @@ hipError_t launch_dequantize(const ntc_material& m, const uint8_t* packed, float
 // Scatter canonical FP32 weights into operand packs (forward only, or forward + backward).
 hipError_t launch_pack_mlp(const ntc_material& m, const float* mlp, bool f16, bool with_backward,
                            void* packed, hipStream_t s);
+// FP8-e4m3 decode pack (weights, per-layer scales, FP32 biases) and its weight-part size.
+size_t fp8_pack_weight_bytes(const ntc_material& m);
+hipError_t launch_pack_mlp_fp8(const ntc_material& m, const float* mlp, void* packed, hipStream_t s);
+hipError_t launch_decode_fp8(const ntc_material& m, const uint8_t* packed, const void* wpack, const ntc_query* q,
+                             long long n, void* out, bool out_f16, hipStream_t s);
 hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const void* wpack, bool f16,
                          const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s);
 
@@ -34,7 +45,8 @@ struct TrainPlan {
   int nbins, ntiles, region_max, nbb, per_bin_block, grid;
   long long max_items;
   bool supported_bins;
-  size_t off_counts, off_offsets, off_total, off_base, off_tstart, off_ttotal, off_ibase, off_misc, off_list;
+  size_t off_counts, off_offsets, off_total, off_base, off_tstart, off_ttotal, off_ibase, off_itile, off_misc;
+  size_t off_list;
   size_t off_part_lat;
   size_t off_part_dw, off_part_loss, off_tmp, off_grad, total;
 };

@@ -45,10 +45,11 @@ struct TrainArgs {
   const float* targets;
   float* lat_grad;
   float* part_lat;
-  const int* list;
+  const int4* list;        // binned samples: (u bits, v bits, lod, sample index)
   const int* tile_start;   // first list position of each tile's samples
   const int* tile_total;   // number of list entries of each tile
   const int* item_base;    // first work item of each tile (ntiles + 1)
+  const int* item_tile;    // tile of each work item
   const int* nitems;
   float* part_dw;
   float* part_loss;
@@ -145,7 +146,10 @@ struct TrainCfg {
   static constexpr int OFF_RED = OFF_TAB + 32 * 8;
   static constexpr int OFF_BUF = (OFF_RED + 16 + 15) / 16 * 16;
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
-  static constexpr int kLdsCap = 160 * 1024;
+  // FP16: two blocks per CU (the second block hides the first one's memory stalls);
+  // FP32 packs are twice the size, so FP32 keeps one block with the larger staging
+  static constexpr int kBlocksPerCu = sizeof(T) == 2 ? 2 : 1;
+  static constexpr int kLdsCap = 160 * 1024 / kBlocksPerCu;
   static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
   // one-phase staging when it fits next to a tile of at least 16 x 16 cells
   static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 4 <= kLdsCap;
@@ -157,7 +161,7 @@ struct TrainCfg {
 };
 
 template <typename T, int C0, int C1, int C, int HD, int ACT>
-__global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
+__global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) void train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
   constexpr PackGeom pg = Cfg::pg;
@@ -210,13 +214,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
     bool single = true;
     bool sorted = false;
     if (a.binned) {
-      int lo = 0, hi = a.tg.ntiles;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.item_base[mid] <= item) lo = mid;
-        else hi = mid;
-      }
-      const int tile = lo;
+      const int tile = a.item_tile[item];
       const int chunk = item - a.item_base[tile];
       single = (a.item_base[tile + 1] - a.item_base[tile]) == 1;
       start = (long long)a.tile_start[tile] + (long long)chunk * kChunk;
@@ -238,18 +236,38 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       for (int k = tid; k < RG; k += 256) reg[k] = 0.f;
     __syncthreads();
 
-    for (int t0 = 0; t0 < cnt; t0 += 64) {
+    // the list entry (query + sample index) of one 64-sample step; the next step's
+    // entry is loaded before this step's gathers, so it arrives with them
+    auto load_entry = [&](int t0, float& u, float& v, int& lod, long long& s) {
       const int pos = t0 + wave * 16 + r;
-      const bool valid = pos < cnt;
-      long long s = 0;
-      if (valid) s = a.binned ? (long long)a.list[start + pos] : start + pos;
-      float u = 0.f, v = 0.f;
-      int lod = 0;
-      if (valid) {
-        u = a.q[s].u;
-        v = a.q[s].v;
-        lod = a.q[s].lod;
+      u = v = 0.f;
+      lod = 0;
+      s = 0;
+      if (pos < cnt) {
+        if (a.binned) {
+          const int4 e = a.list[start + pos];
+          u = __int_as_float(e.x);
+          v = __int_as_float(e.y);
+          lod = e.z;
+          s = e.w;
+        } else {
+          s = start + pos;
+          u = a.q[s].u;
+          v = a.q[s].v;
+          lod = a.q[s].lod;
+        }
       }
+    };
+    float nu, nv;
+    int nlod;
+    long long ns;
+    load_entry(0, nu, nv, nlod, ns);
+    for (int t0 = 0; t0 < cnt; t0 += 64) {
+      const bool valid = t0 + wave * 16 + r < cnt;
+      const float u = nu, v = nv;
+      const int lod = nlod;
+      const long long s = ns;
+      if (t0 + 64 < cnt) load_entry(t0 + 64, nu, nv, nlod, ns);
       const Footprint f = locate(m, u, v, lod, g);
       const bool primary = valid && (!a.binned || (f.ax / T_ == tx && f.ay / T_ == ty));
       const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
@@ -283,8 +301,10 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       }
 
       // ---------------- forward
+      // h1, h2: activations in the operand type; the pre-activations z are kept only
+      // where the activation's derivative needs them (ReLU reads its decision off h)
       float z1[SH], z2[SH];
-      T hs[SH];
+      T h1[SH], h2[SH];
       f32x4 acc[MT];
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo) {
@@ -295,21 +315,21 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       for (int mo = 0; mo < MT; ++mo) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) z1[4 * mo + i] = acc[mo][i];
-        act4<ACT>(acc[mo], hs + 4 * mo);
+        act4<ACT>(acc[mo], h1 + 4 * mo);
       }
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo) {
         acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
-        acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, hs, lane);
+        acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, h1, lane);
       }
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) z2[4 * mo + i] = acc[mo][i];
-        act4<ACT>(acc[mo], hs + 4 * mo);
+        act4<ACT>(acc[mo], h2 + 4 * mo);
       }
       f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
-      y = mma_slots<SH>(y, w_lds + pg.L3, hs, lane);
+      y = mma_slots<SH>(y, w_lds + pg.L3, h2, lane);
 
       // ---------------- loss and output gradient (lane group g: channels 4g..4g+3)
       T dyT[4];
@@ -342,7 +362,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         d = mma_slots<4>(d, w_lds + pg.B3 + mo * 4 * 64, dyT, lane);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          dz2[4 * mo + i] = d[i] * act_grad<ACT>(z2[4 * mo + i]);
+          dz2[4 * mo + i] = d[i] * dact<ACT>(z2[4 * mo + i], h2[4 * mo + i]);
           dT[4 * mo + i] = (T)dz2[4 * mo + i];
         }
       }
@@ -351,7 +371,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
         d = mma_slots<SH>(d, w_lds + pg.B2 + mo * SH * 64, dT, lane);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * act_grad<ACT>(z1[4 * mo + i]);
+        for (int i = 0; i < 4; ++i) dz1[4 * mo + i] = d[i] * dact<ACT>(z1[4 * mo + i], h1[4 * mo + i]);
       }
       T dz1T[SH];
 #pragma unroll
@@ -436,8 +456,8 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
 #pragma unroll
         for (int t = 0; t < SH; ++t) {
           const int h = hid_feature(g, t);
-          buf[(Cfg::RH1 + h) * RS + col] = primary ? (T)act_fn<ACT>(z1[t]) : zero;
-          buf[(Cfg::RH2 + h) * RS + col] = primary ? (T)act_fn<ACT>(z2[t]) : zero;
+          buf[(Cfg::RH1 + h) * RS + col] = primary ? h1[t] : zero;
+          buf[(Cfg::RH2 + h) * RS + col] = primary ? h2[t] : zero;
           buf[(Cfg::RDZ1 + h) * RS + col] = primary ? dz1T[t] : zero;
           buf[(Cfg::RDZ2 + h) * RS + col] = primary ? dT[t] : zero;
         }
@@ -464,7 +484,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
       } else {
         // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
 #pragma unroll
-        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn<ACT>(z2[t]) : zero;
+        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? h2[t] : zero;
 #pragma unroll
         for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
         __syncthreads();
@@ -474,7 +494,7 @@ __global__ __launch_bounds__(256) void train_fused_kernel(DevMat m, PeTable pe, 
         // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
 #pragma unroll
         for (int t = 0; t < SH; ++t) {
-          buf[hid_feature(g, t) * RS + col] = primary ? (T)act_fn<ACT>(z1[t]) : zero;
+          buf[hid_feature(g, t) * RS + col] = primary ? h1[t] : zero;
           buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
         }
         __syncthreads();
@@ -587,7 +607,7 @@ struct BinArgs {
   int* counts;         // [nbins][nbb]
   const int* offsets;  // [nbins][nbb], relative to the bin base
   const int* base;     // [nbins + 1]
-  int* list;
+  int4* list;
 };
 
 template <bool SCATTER>
@@ -606,7 +626,8 @@ __global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs
     for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
       for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
         const int b = sort_bin(tg, sb.j, tx, ty, f.ax, f.ay);
-        if (SCATTER) a.list[atomicAdd(&hist[b], 1)] = (int)s;
+        if (SCATTER)
+          a.list[atomicAdd(&hist[b], 1)] = make_int4(__float_as_int(qq.u), __float_as_int(qq.v), qq.lod, (int)s);
         else atomicAdd(&hist[b], 1);
       }
   }
@@ -668,7 +689,7 @@ __device__ inline int block_exclusive_scan(int v, int* sh) {
 __global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int* __restrict__ total,
                                                          int* __restrict__ base, int* __restrict__ tile_start,
                                                          int* __restrict__ tile_total, int* __restrict__ item_base,
-                                                         int* __restrict__ nitems) {
+                                                         int* __restrict__ item_tile, int* __restrict__ nitems) {
   __shared__ int s_base[kMaxBins + 1];
   __shared__ int s_scan[1024];
   constexpr int kPer = kMaxBins / 1024;
@@ -717,8 +738,10 @@ __global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int*
     int pi = block_exclusive_scan<kPer>(items, s_scan);
     for (int e = 0; e < per && t0 + e < nt; ++e) {
       const int tot = tile_total[t0 + e];
+      const int k = max(1, (tot + kChunk - 1) / kChunk);
       item_base[t0 + e] = pi;
-      pi += max(1, (tot + kChunk - 1) / kChunk);
+      for (int i = 0; i < k; ++i) item_tile[pi + i] = t0 + e;
+      pi += k;
     }
     if (tid == 1023) {
       item_base[nt] = s_scan[1023];
@@ -923,10 +946,11 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.targets = l.targets;
   a.lat_grad = l.lat_grad;
   a.part_lat = (float*)(ws + p.off_part_lat);
-  a.list = (const int*)(ws + p.off_list);
+  a.list = (const int4*)(ws + p.off_list);
   a.tile_start = (const int*)(ws + p.off_tstart);
   a.tile_total = (const int*)(ws + p.off_ttotal);
   a.item_base = (const int*)(ws + p.off_ibase);
+  a.item_tile = (const int*)(ws + p.off_itile);
   a.nitems = (const int*)(ws + p.off_misc);
   a.part_dw = (float*)(ws + p.off_part_dw);
   a.part_loss = (float*)(ws + p.off_part_loss);
@@ -940,8 +964,10 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.dout_scale = l.dout_scale;
   a.out_scale = l.out_scale;
   a.tg = p.tg;
+  const int slot = timing_before(TK_TRAIN_FUSED, s);
   hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
                      pe_table(), a);
+  timing_after(TK_TRAIN_FUSED, s, slot);
   return hipGetLastError();
 }
 
@@ -1016,8 +1042,9 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
   p.off_tstart = take((size_t)nt * 4);
   p.off_ttotal = take((size_t)nt * 4);
   p.off_ibase = take((size_t)(nt + 1) * 4);
+  p.off_itile = take((size_t)p.max_items * 4);
   p.off_misc = take(64);
-  p.off_list = take((size_t)4 * n * 4);
+  p.off_list = take((size_t)4 * n * 16);
   p.off_part_lat = take((size_t)p.max_items * rmax * 4);
   p.off_part_dw = take((size_t)p.grid * P * 4);
   p.off_part_loss = take((size_t)p.grid * 4);
@@ -1041,14 +1068,14 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     b.counts = (int*)(ws + p.off_counts);
     b.offsets = (const int*)(ws + p.off_offsets);
     b.base = (const int*)(ws + p.off_base);
-    b.list = (int*)(ws + p.off_list);
+    b.list = (int4*)(ws + p.off_list);
     const size_t lds = (size_t)p.nbins * 4;
     hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
     hipLaunchKernelGGL(bin_scan1_kernel, dim3((p.nbins + 3) / 4), dim3(256), 0, s, p.nbins, p.nbb,
                        (const int*)(ws + p.off_counts), (int*)(ws + p.off_offsets), (int*)(ws + p.off_total));
     hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.tg, (const int*)(ws + p.off_total),
                        (int*)(ws + p.off_base), (int*)(ws + p.off_tstart), (int*)(ws + p.off_ttotal),
-                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_misc));
+                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_itile), (int*)(ws + p.off_misc));
     hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
   }
   hipError_t e = hipGetLastError();

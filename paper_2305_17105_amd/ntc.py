@@ -84,6 +84,9 @@ _sig = {
     "ntc_backward_workspace_bytes": (C.c_size_t, [_P(Material), C.c_int64, C.c_int]),
     "ntc_backward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
                                C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_timing_begin": (C.c_int, [C.c_int32]),
+    "ntc_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "ntc_timing_end": (C.c_int, []),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -242,3 +245,19 @@ class TrainState:
         self.loss_scale = torch.full((2,), loss_scale, **f)
         self.scale_state = torch.zeros(2, dtype=torch.int32, device=device)
         self.c = TrainStateC(*[C.c_void_p(getattr(self, n).data_ptr()) for n, _ in TrainStateC._fields_])
+
+
+def timing_begin(max_launches: int):
+    """Record HIP events around the next max_launches launches of each timed kernel."""
+    _check(_lib.ntc_timing_begin(max_launches), "ntc_timing_begin")
+
+
+def timing_read(kernel: str):
+    """(total ms, launches) recorded for kernel "train_fused" or "decode"."""
+    ms, n = C.c_double(0.0), C.c_int32(0)
+    _check(_lib.ntc_timing_read(kernel.encode(), C.byref(ms), C.byref(n)), "ntc_timing_read")
+    return ms.value, n.value
+
+
+def timing_end():
+    _check(_lib.ntc_timing_end(), "ntc_timing_end")

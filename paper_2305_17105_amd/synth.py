@@ -54,6 +54,56 @@ def value_noise(seed: int, material: int, W: int, H: int, C: int, octaves: int =
     return out
 
 
+def value_noise_torch(seed: int, material: int, W: int, H: int, C: int, device, octaves: int = 4):
+    """value_noise() evaluated with torch on `device` (same lattice values, same float64
+    operation sequence), for sizes where the numpy version is slow."""
+    import torch
+    norm = sum(0.5 ** o for o in range(octaves))
+    ys = (torch.arange(H, dtype=torch.float64, device=device) + 0.5) / H
+    xs = (torch.arange(W, dtype=torch.float64, device=device) + 0.5) / W
+    out = torch.empty((H, W, C), dtype=torch.float32, device=device)
+    for c in range(C):
+        acc = torch.zeros((H, W), dtype=torch.float64, device=device)
+        for o in range(octaves):
+            cells = 8 * 2 ** o
+            lat = torch.from_numpy(_rng(seed, material, c, o).random((cells, cells))).to(device)
+            gx, gy = xs * cells, ys * cells
+            x0, y0 = torch.floor(gx), torch.floor(gy)
+            tx, ty = gx - x0, gy - y0
+            sx = tx * tx * (3.0 - 2.0 * tx)
+            sy = ty * ty * (3.0 - 2.0 * ty)
+            x0 = x0.long() % cells
+            y0 = y0.long() % cells
+            x1, y1 = (x0 + 1) % cells, (y0 + 1) % cells
+            a = lat[y0[:, None], x0[None, :]]
+            b = lat[y0[:, None], x1[None, :]]
+            cc = lat[y1[:, None], x0[None, :]]
+            d = lat[y1[:, None], x1[None, :]]
+            top = a + (b - a) * sx[None, :]
+            bot = cc + (d - cc) * sx[None, :]
+            acc += 0.5 ** o * (top + (bot - top) * sy[:, None])
+        out[:, :, c] = (acc / norm).to(torch.float32)
+    return out
+
+
+def target_chain_torch(seed: int, material: int, W: int, H: int, C: int, num_mips: int, device):
+    """target_chain() on a torch device: flat float32 tensor, mip 0 first."""
+    import torch
+    img = value_noise_torch(seed, material, W, H, C, device)
+    mips = [img]
+    for _ in range(1, num_mips):
+        m = mips[-1].double()
+        h, w = m.shape[0], m.shape[1]
+        h2, w2 = max(1, h // 2), max(1, w // 2)
+        if h == 1:
+            m = torch.cat([m, m], dim=0)
+        if w == 1:
+            m = torch.cat([m, m], dim=1)
+        m = 0.25 * (m[0::2, 0::2] + m[1::2, 0::2] + m[0::2, 1::2] + m[1::2, 1::2])
+        mips.append(m[:h2, :w2].to(torch.float32).contiguous())
+    return torch.cat([m.reshape(-1) for m in mips])
+
+
 def box_mips(img: np.ndarray, num_mips: int):
     """Mip chain by 2x2 box averaging (float32), down to num_mips levels."""
     mips = [np.ascontiguousarray(img, dtype=np.float32)]

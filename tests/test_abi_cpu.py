@@ -91,3 +91,9 @@ def test_supported_shapes_and_sizes(ntc):
     assert ntc.train_packed_bytes(m, ntc.F16) * 2 >= ntc.train_packed_bytes(m, ntc.F32) - 16
     assert ntc.mlp_packed_bytes(m, ntc.F32) > ntc.mlp_packed_bytes(m, ntc.F16) > 0
     assert ntc.mlp_packed_bytes(m, 7) == 0
+    # FP8: 12 channels x 4 bits is not whole words -> unsupported; 16 x 2-bit is
+    assert ntc.mlp_packed_bytes(m, ntc.FP8_E4M3) == 0
+    m3 = ntc.material_init(4096, 4096, 16, 16, 16, 2, 4, 64)
+    # e4m3 weights (96 + 64 + 16 slots x 64 lanes, one byte each) + 16 B scales + FP32 biases
+    assert ntc.mlp_packed_bytes(m3, ntc.FP8_E4M3) == 4 * 24 * 64 + 4 * 16 * 64 + 16 * 64 + 16 + (2 * 64 + 16) * 4
+    assert ntc.mlp_packed_bytes(m3, ntc.F16) > ntc.mlp_packed_bytes(m3, ntc.FP8_E4M3)

@@ -207,7 +207,6 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
     log(f"[bench] decode material: targets + {steps} FP32 training steps in {time.time() - t0:.1f}s")
 
     q_rand = torch.from_numpy(synth.random_queries(seed + 5, nq, m.num_mips).view(np.uint8).copy()).cuda()
-    q_tile = torch.from_numpy(synth.tile_queries(d["W"], d["W"], 0).view(np.uint8).copy()).cuda()
     n_tile = d["W"] * d["W"]
     out = torch.empty(max(nq, n_tile) * d["C"], dtype=torch.float16, device="cuda")
     out32 = torch.empty(n_tile * d["C"], dtype=torch.float32, device="cuda")
@@ -217,15 +216,19 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
     for name, prec in (("f16", ntc.F16), ("fp8", ntc.FP8_E4M3), ("f32", ntc.F32)):
         wp = torch.zeros(ntc.mlp_packed_bytes(m, prec), dtype=torch.uint8, device="cuda")
         ntc.pack_mlp(m, mlp, prec, wp)
-        for kind, qd, nn in (("random", q_rand, nq), ("coherent", q_tile, n_tile)):
+        for kind, nn in (("random", nq), ("coherent", n_tile)):
+            if kind == "random":
+                call = lambda: ntc.decode(m, packed, wp, prec, q_rand, nq, out, ntc.F16)
+            else:  # the whole of mip 0 through the rectangle entry point, no query buffer
+                call = lambda: ntc.decode_tile(m, packed, wp, prec, 0, 0, 0, d["W"], d["W"], out, ntc.F16)
             for _ in range(2):
-                ntc.decode(m, packed, wp, prec, qd, nn, out, ntc.F16)
+                call()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             ntc.timing_begin(reps)
             e0.record()
             for _ in range(reps):
-                ntc.decode(m, packed, wp, prec, qd, nn, out, ntc.F16)
+                call()
             e1.record()
             torch.cuda.synchronize()
             ktot, kcnt = ntc.timing_read("decode")
@@ -236,7 +239,7 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
                                          texels_per_s=nn / (ms * 1e-3), tflops=fl_q * nn / (kms * 1e-3) / 1e12)
             log(f"[bench] decode {kind} {name}: {ms:.3f} ms for {nn} queries -> {nn / (ms * 1e-3):.3e} texels/s "
                 f"(kernel {kms:.3f} ms)")
-        ntc.decode(m, packed, wp, prec, q_tile, n_tile, out32, ntc.F32)
+        ntc.decode_tile(m, packed, wp, prec, 0, 0, 0, d["W"], d["W"], out32, ntc.F32)
         mse = float(((out32.double() - ref0) ** 2).mean())
         res[f"psnr_mip0_{name}"] = round(-10.0 * math.log10(mse), 3)
     log(f"[bench] decode PSNR of mip 0: f32 {res['psnr_mip0_f32']} dB, f16 {res['psnr_mip0_f16']} dB, "

@@ -151,6 +151,18 @@ ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, cons
                       ntc_dtype out_dtype, void* stream);
 
 /*
+ * Coherent decode (the screen-space workload of section 6): every texel of the
+ * rectangle [x0, x0 + width) x [y0, y0 + height) of mip `lod`, without a query array.
+ * out: width * height * C values, row-major over the rectangle then channel.  Same
+ * results, bit for bit, as ntc_decode on the texel-centre queries of the rectangle.
+ * The rectangle must lie inside the mip (NTC_E_INVALID otherwise); an empty one is
+ * a no-op.  Other arguments as for ntc_decode.
+ */
+ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                           ntc_dtype precision, int32_t lod, int32_t x0, int32_t y0, int32_t width,
+                           int32_t height, void* out, ntc_dtype out_dtype, void* stream);
+
+/*
  * Training (autodecoder, section 4; optimiser section 4.5 and section 5.1).
  * State buffers (all caller-owned device memory):
  *   latents      latent_count  FP32 masters

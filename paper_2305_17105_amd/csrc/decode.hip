@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
                                                      const float* __restrict__ bias2,
                                                      const float* __restrict__ bias3,
                                                      const ntc_query* __restrict__ q, long long n,
-                                                     void* __restrict__ out, int out_f16) {
+                                                     TexelRect rect, void* __restrict__ out, int out_f16) {
   const uint32_t* __restrict__ packed = reinterpret_cast<const uint32_t*>(src);
   const float* __restrict__ lat = reinterpret_cast<const float*>(src);
   using IS = InSlots<C0, C1>;
@@ -175,9 +175,13 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
     u = v = 0.f;
     lod = 0;
     if (tile < tiles && s < n) {
-      u = q[s].u;
-      v = q[s].v;
-      lod = q[s].lod;
+      if (rect.w > 0) {
+        rect_query(rect, s, u, v, lod);
+      } else {
+        u = q[s].u;
+        v = q[s].v;
+        lod = q[s].lod;
+      }
     }
   };
 
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, c
                                                          const float* __restrict__ scales,
                                                          const float* __restrict__ bias,
                                                          const ntc_query* __restrict__ q, long long n,
-                                                         void* __restrict__ out, int out_f16) {
+                                                         TexelRect rect, void* __restrict__ out, int out_f16) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT;
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
@@ -323,9 +327,13 @@ __global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, c
     u = v = 0.f;
     lod = 0;
     if (tile < tiles && s < n) {
-      u = q[s].u;
-      v = q[s].v;
-      lod = q[s].lod;
+      if (rect.w > 0) {
+        rect_query(rect, s, u, v, lod);
+      } else {
+        u = q[s].u;
+        v = q[s].v;
+        lod = q[s].lod;
+      }
     }
   };
   // A operand of MFMA kk of M-tile mo of a layer pack with S slots
@@ -422,7 +430,7 @@ __global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, c
 
 template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
 static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, const void* wpack, const ntc_query* q,
-                                long long n, void* out, bool out_f16, hipStream_t s) {
+                                long long n, const TexelRect& rect, void* out, bool out_f16, hipStream_t s) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4;
@@ -441,7 +449,7 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
   const int slot = timing_before(TK_DECODE, s);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(),
                      reinterpret_cast<const uint32_t*>(packed), reinterpret_cast<const uint8_t*>(wpack), scales,
-                     scales + 4, q, n, out, out_f16 ? 1 : 0);
+                     scales + 4, q, n, rect, out, out_f16 ? 1 : 0);
   timing_after(TK_DECODE, s, slot);
   return hipGetLastError();
 }
@@ -450,7 +458,8 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
 // follow the weights in the pack (decode packs)
 template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
 static hipError_t decode_t1(const ntc_material& mm, const void* src, const void* wpack, const float* mlp,
-                           const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s) {
+                           const ntc_query* q, long long n, const TexelRect& rect, void* out, bool out_f16,
+                           hipStream_t s) {
   constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>::WB;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4;
   const float *b1, *b2, *b3;
@@ -477,16 +486,18 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
   if (grid > cap) grid = cap;
   const int slot = PACKED ? timing_before(TK_DECODE, s) : -1;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(), src,
-                     reinterpret_cast<const T*>(wpack), b1, b2, b3, q, n, out, out_f16 ? 1 : 0);
+                     reinterpret_cast<const T*>(wpack), b1, b2, b3, q, n, rect, out, out_f16 ? 1 : 0);
   timing_after(TK_DECODE, s, slot);
   return hipGetLastError();
 }
 
 template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED>
 static hipError_t decode_t(const ntc_material& mm, const void* src, const void* wpack, const float* mlp,
-                           const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s) {
-  return mm.activation ? decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 1>(mm, src, wpack, mlp, q, n, out, out_f16, s)
-                       : decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 0>(mm, src, wpack, mlp, q, n, out, out_f16, s);
+                           const ntc_query* q, long long n, const TexelRect& rect, void* out, bool out_f16,
+                           hipStream_t s) {
+  return mm.activation
+             ? decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 1>(mm, src, wpack, mlp, q, n, rect, out, out_f16, s)
+             : decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 0>(mm, src, wpack, mlp, q, n, rect, out, out_f16, s);
 }
 
 #define NTC_DECODE_SHAPES(X)                                                                     \
@@ -502,24 +513,33 @@ bool decode_shape_supported(int c0, int c1, int c, int hd, int b0, int b1) {
   return false;
 }
 
+// rect: nullptr for query-array decode, else the texel rectangle to decode (q unused)
+static TexelRect make_rect(const ntc_material& m, const TexelRect* rect) {
+  if (rect) return *rect;
+  TexelRect r{};
+  return r;
+}
+
 hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const void* wpack, bool f16, const ntc_query* q,
-                         long long n, void* out, bool out_f16, hipStream_t s) {
-#define NTC_X(a, b, cc, h, x0, x1)                                                                   \
-  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)      \
-    return f16 ? decode_t<_Float16, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s) \
-               : decode_t<float, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, out, out_f16, s);
+                         long long n, const TexelRect* rect, void* out, bool out_f16, hipStream_t s) {
+  const TexelRect r = make_rect(m, rect);
+#define NTC_X(a, b, cc, h, x0, x1)                                                                             \
+  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)                \
+    return f16 ? decode_t<_Float16, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, r, out, out_f16, s) \
+               : decode_t<float, a, b, cc, h, x0, x1, true>(m, packed, wpack, nullptr, q, n, r, out, out_f16, s);
   NTC_DECODE_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_decode_fp8(const ntc_material& m, const uint8_t* packed, const void* wpack, const ntc_query* q,
-                             long long n, void* out, bool out_f16, hipStream_t s) {
-#define NTC_X(a, b, cc, h, x0, x1)                                                                   \
-  if constexpr (fp8_layout(a, b, x0, x1, h))                                                         \
-    if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)    \
-      return m.activation ? decode_fp8_t1<a, b, cc, h, x0, x1, 1>(m, packed, wpack, q, n, out, out_f16, s) \
-                          : decode_fp8_t1<a, b, cc, h, x0, x1, 0>(m, packed, wpack, q, n, out, out_f16, s);
+                             long long n, const TexelRect* rect, void* out, bool out_f16, hipStream_t s) {
+  const TexelRect r = make_rect(m, rect);
+#define NTC_X(a, b, cc, h, x0, x1)                                                                      \
+  if constexpr (fp8_layout(a, b, x0, x1, h))                                                            \
+    if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)       \
+      return m.activation ? decode_fp8_t1<a, b, cc, h, x0, x1, 1>(m, packed, wpack, q, n, r, out, out_f16, s) \
+                          : decode_fp8_t1<a, b, cc, h, x0, x1, 0>(m, packed, wpack, q, n, r, out, out_f16, s);
   NTC_DECODE_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;
@@ -535,8 +555,9 @@ hipError_t launch_forward(const ntc_material& m, const float* latents, const flo
                           const ntc_query* q, long long n, float* out, hipStream_t s) {
 #define NTC_X(a, b, cc, h)                                                                                   \
   if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h)                                           \
-    return f16 ? decode_t<_Float16, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, out, false, s)   \
-               : decode_t<float, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, out, false, s);
+    return f16 ? decode_t<_Float16, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, TexelRect{}, out,  \
+                                                                 false, s)                                     \
+               : decode_t<float, a, b, cc, h, 4, 4, false>(m, latents, wpack, mlp, q, n, TexelRect{}, out, false, s);
   NTC_FORWARD_SHAPES(NTC_X)
 #undef NTC_X
   return hipErrorInvalidValue;

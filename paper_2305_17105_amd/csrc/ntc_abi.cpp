@@ -248,26 +248,62 @@ ntc_status ntc_pack_mlp(const ntc_material* m, const float* mlp, ntc_dtype preci
   return hip_status(launch_pack_mlp(*m, mlp, precision == NTC_F16, false, packed, (hipStream_t)stream), "ntc_pack_mlp");
 }
 
-ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
-                      ntc_dtype precision, const ntc_query* q, int64_t n, void* out, ntc_dtype out_dtype,
-                      void* stream) {
+static ntc_status check_decode(const ntc_material* m, ntc_dtype precision, ntc_dtype out_dtype) {
   ntc_status st = check_material(m);
   if (st != NTC_OK) return st;
   if (precision != NTC_F32 && precision != NTC_F16 && precision != NTC_FP8_E4M3)
     return fail(NTC_E_UNSUPPORTED, "decode precision must be F32, F16 or FP8_E4M3");
   if (out_dtype != NTC_F32 && out_dtype != NTC_F16) return fail(NTC_E_UNSUPPORTED, "output dtype must be F32 or F16");
-  if (n < 0) return fail(NTC_E_INVALID, "n < 0");
   if (!decode_shape_supported(m->c0, m->c1, m->channels, m->hidden, m->b0, m->b1))
     return fail(NTC_E_UNSUPPORTED, "no decode kernel for this (c0, c1, channels, hidden, b0, b1)");
   if (precision == NTC_FP8_E4M3 && !fp8_supported(m))
     return fail(NTC_E_UNSUPPORTED, "FP8 decode needs whole-dword G0 cells and b0, b1 <= 4");
+  return NTC_OK;
+}
+
+static ntc_status run_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                             ntc_dtype precision, const ntc_query* q, int64_t n, const TexelRect* rect, void* out,
+                             ntc_dtype out_dtype, void* stream, const char* where) {
+  if (precision == NTC_FP8_E4M3)
+    return hip_status(launch_decode_fp8(*m, packed_latents, mlp_packed, q, n, rect, out, out_dtype == NTC_F16,
+                                        (hipStream_t)stream), where);
+  return hip_status(launch_decode(*m, packed_latents, mlp_packed, precision == NTC_F16, q, n, rect, out,
+                                  out_dtype == NTC_F16, (hipStream_t)stream), where);
+}
+
+ntc_status ntc_decode(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                      ntc_dtype precision, const ntc_query* q, int64_t n, void* out, ntc_dtype out_dtype,
+                      void* stream) {
+  ntc_status st = check_decode(m, precision, out_dtype);
+  if (st != NTC_OK) return st;
+  if (n < 0) return fail(NTC_E_INVALID, "n < 0");
   if (n == 0) return NTC_OK;
   if (!packed_latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
-  if (precision == NTC_FP8_E4M3)
-    return hip_status(launch_decode_fp8(*m, packed_latents, mlp_packed, q, n, out, out_dtype == NTC_F16,
-                                        (hipStream_t)stream), "ntc_decode");
-  return hip_status(launch_decode(*m, packed_latents, mlp_packed, precision == NTC_F16, q, n, out,
-                                  out_dtype == NTC_F16, (hipStream_t)stream), "ntc_decode");
+  return run_decode(m, packed_latents, mlp_packed, precision, q, n, nullptr, out, out_dtype, stream, "ntc_decode");
+}
+
+ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                           ntc_dtype precision, int32_t lod, int32_t x0, int32_t y0, int32_t width, int32_t height,
+                           void* out, ntc_dtype out_dtype, void* stream) {
+  ntc_status st = check_decode(m, precision, out_dtype);
+  if (st != NTC_OK) return st;
+  if (lod < 0 || lod >= m->num_mips) return fail(NTC_E_INVALID, "lod outside the mip chain");
+  const int wl = m->mip_w[lod], hl = m->mip_h[lod];
+  if (width < 0 || height < 0 || x0 < 0 || y0 < 0 || (int64_t)x0 + width > wl || (int64_t)y0 + height > hl)
+    return fail(NTC_E_INVALID, "rectangle outside the mip");
+  const int64_t n = (int64_t)width * height;
+  if (n == 0) return NTC_OK;
+  if (!packed_latents || !mlp_packed || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  TexelRect r;
+  r.lod = lod;
+  r.x0 = x0;
+  r.y0 = y0;
+  r.w = width;
+  r.h = height;
+  r.inv_w = 1.f / (float)wl;  // powers of two: exact
+  r.inv_h = 1.f / (float)hl;
+  return run_decode(m, packed_latents, mlp_packed, precision, nullptr, n, &r, out, out_dtype, stream,
+                    "ntc_decode_tile");
 }
 
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {

@@ -37,6 +37,20 @@ struct DevMat {
   long long latent_count;
 };
 
+// Coherent decode source: the texels of rectangle [x0, x0+w) x [y0, y0+h) of mip lod,
+// row-major (w == 0: queries come from a query array instead).  inv_w, inv_h = 1 / mip
+// size, so (x + 1/2) * inv_w is the exact texel centre.
+struct TexelRect {
+  int lod, x0, y0, w, h;
+  float inv_w, inv_h;
+};
+__device__ inline void rect_query(const TexelRect& r, long long s, float& u, float& v, int& lod) {
+  const int i = (int)s, yy = i / r.w, xx = i - yy * r.w;
+  u = ((float)(r.x0 + xx) + 0.5f) * r.inv_w;
+  v = ((float)(r.y0 + yy) + 0.5f) * r.inv_h;
+  lod = r.lod;
+}
+
 // Positional-encoding table: pe[m][q] for texel position m = i mod 8 inside the
 // 8-texel tile and value q = (sin, cos) x (1, 2, 4 cycles per tile) (section 4.3.2).
 struct PeTable {

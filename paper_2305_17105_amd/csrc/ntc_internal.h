@@ -34,10 +34,13 @@ hipError_t launch_pack_mlp(const ntc_material& m, const float* mlp, bool f16, bo
 // FP8-e4m3 decode pack (weights, per-layer scales, FP32 biases) and its weight-part size.
 size_t fp8_pack_weight_bytes(const ntc_material& m);
 hipError_t launch_pack_mlp_fp8(const ntc_material& m, const float* mlp, void* packed, hipStream_t s);
+// Decode launchers: rect == nullptr decodes the n queries of q; otherwise the n texels
+// of the rectangle, row-major (q unused).
 hipError_t launch_decode_fp8(const ntc_material& m, const uint8_t* packed, const void* wpack, const ntc_query* q,
-                             long long n, void* out, bool out_f16, hipStream_t s);
+                             long long n, const TexelRect* rect, void* out, bool out_f16, hipStream_t s);
 hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const void* wpack, bool f16,
-                         const ntc_query* q, long long n, void* out, bool out_f16, hipStream_t s);
+                         const ntc_query* q, long long n, const TexelRect* rect, void* out, bool out_f16,
+                         hipStream_t s);
 
 // Launch plan of a training step: tile geometry, grids and workspace layout (bytes).
 struct TrainPlan {

@@ -84,6 +84,8 @@ _sig = {
     "ntc_backward_workspace_bytes": (C.c_size_t, [_P(Material), C.c_int64, C.c_int]),
     "ntc_backward": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
                                C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_decode_tile": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_timing_begin": (C.c_int, [C.c_int32]),
     "ntc_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "ntc_timing_end": (C.c_int, []),
@@ -170,6 +172,12 @@ def pack_mlp(m: Material, mlp, precision, packed, stream=None):
 def decode(m: Material, packed_latents, mlp_packed, precision, queries, n, out, out_dtype, stream=None):
     _check(_lib.ntc_decode(C.byref(m), _ptr(packed_latents), _ptr(mlp_packed), precision, _ptr(queries), n,
                            _ptr(out), out_dtype, _stream(stream)), "ntc_decode")
+
+
+def decode_tile(m: Material, packed_latents, mlp_packed, precision, lod, x0, y0, width, height, out, out_dtype,
+                stream=None):
+    _check(_lib.ntc_decode_tile(C.byref(m), _ptr(packed_latents), _ptr(mlp_packed), precision, lod, x0, y0, width,
+                                height, _ptr(out), out_dtype, _stream(stream)), "ntc_decode_tile")
 
 
 def train_prepare(m: Material, state: "TrainState", hp: HParams, stream=None):

@@ -1,5 +1,6 @@
 """C-ABI checks that need no GPU: the library loads, exports every entry point the
 header declares, and its host-side geometry agrees with the oracle's independent one."""
+import ctypes
 import os
 import re
 
@@ -97,3 +98,20 @@ def test_supported_shapes_and_sizes(ntc):
     # e4m3 weights (96 + 64 + 16 slots x 64 lanes, one byte each) + 16 B scales + FP32 biases
     assert ntc.mlp_packed_bytes(m3, ntc.FP8_E4M3) == 4 * 24 * 64 + 4 * 16 * 64 + 16 * 64 + 16 + (2 * 64 + 16) * 4
     assert ntc.mlp_packed_bytes(m3, ntc.F16) > ntc.mlp_packed_bytes(m3, ntc.FP8_E4M3)
+
+
+def test_decode_tile_rejects_bad_rectangles(ntc):
+    """Rectangle checks happen before any launch: no GPU needed."""
+    m = ntc.material_init(512, 512, 16, 16, 16, 2, 4, 64)
+    fake = ctypes.c_void_p(16)
+    lib = ntc._lib
+    def call(lod, x0, y0, w, h, out=fake):
+        return lib.ntc_decode_tile(ctypes.byref(m), fake, fake, ntc.F16, lod, x0, y0, w, h, out, ntc.F16, None)
+    assert call(-1, 0, 0, 1, 1) == ntc.E_INVALID
+    assert call(int(m.num_mips), 0, 0, 1, 1) == ntc.E_INVALID
+    assert call(1, 200, 0, 57, 1) == ntc.E_INVALID        # mip 1 is 256 wide
+    assert call(0, 0, 0, -1, 1) == ntc.E_INVALID
+    assert call(0, 0, 0, 0, 7) == ntc.OK                   # empty: no-op
+    assert call(0, 0, 0, 4, 4, out=None) == ntc.E_INVALID  # NULL output
+    assert lib.ntc_decode_tile(ctypes.byref(m), fake, fake, 9, 0, 0, 0, 1, 1, fake, ntc.F16, None) == \
+        ntc.E_UNSUPPORTED

@@ -140,7 +140,7 @@ def test_decode_fp8_parity(lib, shape):
     # The e4m3 oracle rounds the same values; a value within FP32 rounding of an e4m3
     # midpoint may round the other way (one e4m3 step of one hidden unit), so a few
     # outputs differ by up to ~1e-2 while almost all agree to FP32 accumulation order.
-    assert np.quantile(e8, 0.999) <= 1e-3 and e8.max() <= 2e-2
+    assert e8.mean() <= 2e-5 and np.quantile(e8, 0.99) <= 1e-3 and e8.max() <= 2e-2
     # Against float64 the e4m3 rounding of weights and hidden activations itself costs
     # up to ~2.5e-2 on these outputs (measured error budget in the design notes)
     assert e64.max() <= 3e-2 and e64.mean() <= 5e-3
@@ -154,6 +154,38 @@ def test_fp8_unsupported_shapes_rejected(lib):
     with pytest.raises(lib.NtcError):
         lib.pack_mlp(m, torch.zeros(int(m.mlp_params), device="cuda"), lib.FP8_E4M3,
                      torch.zeros(64, dtype=torch.uint8, device="cuda"))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "fp8"])
+def test_decode_tile_equals_query_decode(lib, prec):
+    """ntc_decode_tile over a ragged rectangle of mip 1 equals ntc_decode on the
+    rectangle's texel-centre queries bit for bit, and the oracle within tolerance."""
+    import torch
+    P = {"f32": lib.F32, "f16": lib.F16, "fp8": lib.FP8_E4M3}[prec]
+    m = lib.material_init(512, 512, 16, 16, 16, 2, 4, 64)
+    g = geometry(m)
+    raw = synth.uniform_latents(13, int(m.latent_count))
+    mlp = mlp_in_unit_range(13, g.K, 64, 16)
+    packed = _packed(lib, m, raw)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    lod, x0, y0, w, h = 1, 3, 5, 37, 19
+    wl = int(m.mip_w[lod])
+    ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+    q = np.zeros(w * h, dtype=synth.QUERY_DTYPE)
+    q["u"] = ((xs.ravel() + 0.5) / wl).astype(np.float32)
+    q["v"] = ((ys.ravel() + 0.5) / wl).astype(np.float32)
+    q["lod"] = lod
+    a = torch.full((w * h * 16,), float("nan"), dtype=torch.float32, device="cuda")
+    b = torch.full((w * h * 16,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode_tile(m, packed, wp, P, lod, x0, y0, w, h, a, lib.F32)
+    lib.decode(m, packed, wp, P, queries_dev(q), w * h, b, lib.F32)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q).ravel()
+    err = np.max(np.abs(a.cpu().numpy() - ref))
+    print(f"decode_tile {prec}: max-abs err {err:.3e} vs float64")
+    assert err <= {"f32": 1e-5, "f16": 2e-3, "fp8": 3e-2}[prec]
 
 
 def test_decode_edge_coordinates(lib):

@@ -438,13 +438,14 @@ struct SampleBins {
 __device__ inline SampleBins sample_bins(const Footprint& f, const TileGeom& tg) {
   SampleBins b;
   b.j = f.j;
-  const int T = tg.T[f.j], T1 = T >> 1;
-  b.tx0 = min(f.ax / T, f.g1x[0] / T1);
-  b.tx1 = max(f.bx / T, f.g1x[1] / T1);
-  b.ty0 = min(f.ay / T, f.g1y[0] / T1);
-  b.ty1 = max(f.by / T, f.g1y[1] / T1);
-  b.ptx = f.ax / T;
-  b.pty = f.ay / T;
+  // tile sides are powers of two (>= 2): shifts instead of divisions
+  const int ts = __builtin_ctz(tg.T[f.j]), t1s = ts - 1;
+  b.tx0 = min(f.ax >> ts, f.g1x[0] >> t1s);
+  b.tx1 = max(f.bx >> ts, f.g1x[1] >> t1s);
+  b.ty0 = min(f.ay >> ts, f.g1y[0] >> t1s);
+  b.ty1 = max(f.by >> ts, f.g1y[1] >> t1s);
+  b.ptx = f.ax >> ts;
+  b.pty = f.ay >> ts;
   return b;
 }
 

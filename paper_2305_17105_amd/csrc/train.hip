@@ -8,8 +8,8 @@
 //     whose latents its footprint (2x2 G0 cells, 4 G1 taps) touches (at most 4),
 //     a counting sort with per-block LDS histograms.  A tile's list is cut into
 //     work items of at most kChunk samples.
-//  2. train_fused_kernel: a persistent block takes work items; for each 64-texel
-//     block tile it gathers latents + PE, runs the MLP forward on matrix cores, the
+//  2. train_fused_kernel: a persistent block takes work items; for each step of
+//     16 texels per wavefront it gathers latents + PE, runs the MLP forward on matrix cores, the
 //     L2 loss and dY, the backward through the three layers (transposed-weight
 //     packs, activations in registers), accumulates the gradients of the latents
 //     the tile owns in LDS (LDS atomics), and adds dW += A^T dZ through an LDS
@@ -65,29 +65,29 @@ struct TrainArgs {
   TileGeom tg;
 };
 
-template <typename T>
-constexpr int lds_row_stride() { return sizeof(T) == 4 ? 68 : 72; }
+// LDS row stride (elements) of the staging buffer for NCOL texel columns: the padding
+// shifts consecutive rows by 4 banks
+template <typename T, int NCOL>
+constexpr int lds_row_stride() { return sizeof(T) == 4 ? NCOL + 4 : NCOL + 8; }
 
-// dW tile += A rows [rowA, rowA+16) x B rows [rowB, rowB+16) summed over the 64
-// texel columns of the block tile.  Lane group g covers texels 16g .. 16g+15.
-template <typename T>
+// dW tile += A rows [rowA, rowA+16) x B rows [rowB, rowB+16) summed over the NCOL
+// texel columns of the block step.  Lane group g covers texels g*NCOL/4 .. (g+1)*NCOL/4 - 1.
+template <typename T, int NCOL>
 __device__ inline f32x4 dw_tile(f32x4 acc, const T* buf, int rowA, int rowB, int g, int r) {
-  constexpr int RS = lds_row_stride<T>();
-  const T* a = buf + (rowA + r) * RS + 16 * g;
-  const T* b = buf + (rowB + r) * RS + 16 * g;
+  constexpr int RS = lds_row_stride<T, NCOL>(), GC = NCOL / 4;
+  const T* a = buf + (rowA + r) * RS + GC * g;
+  const T* b = buf + (rowB + r) * RS + GC * g;
   if constexpr (sizeof(T) == 4) {
-    f32x4 av[4], bv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      av[k] = reinterpret_cast<const f32x4*>(a)[k];
-      bv[k] = reinterpret_cast<const f32x4*>(b)[k];
+    for (int k = 0; k < GC / 4; ++k) {
+      const f32x4 av = reinterpret_cast<const f32x4*>(a)[k];
+      const f32x4 bv = reinterpret_cast<const f32x4*>(b)[k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k / 4][k % 4], bv[k / 4][k % 4], acc, 0, 0, 0);
   } else {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < GC / 8; ++k) {
       const f16x8 av = reinterpret_cast<const f16x8*>(a)[k];
       const f16x8 bv = reinterpret_cast<const f16x8*>(b)[k];
       acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
@@ -98,10 +98,10 @@ __device__ inline f32x4 dw_tile(f32x4 acc, const T* buf, int rowA, int rowB, int
 
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
 
-// Sum of columns 16q .. 16q+15 of LDS row `row` (a quarter of the 64 texels).
-template <typename T>
-__device__ inline float row_quarter_sum(const T* buf, int row, int q) {
-  constexpr int RS = lds_row_stride<T>();
+// Sum of columns 16q .. 16q+15 of LDS row `row`.
+template <typename T, int NCOL>
+__device__ inline float row_part_sum(const T* buf, int row, int q) {
+  constexpr int RS = lds_row_stride<T, NCOL>();
   const T* p = buf + row * RS + 16 * q;
   float s = 0.f;
   if constexpr (sizeof(T) == 4) {
@@ -128,13 +128,27 @@ struct TrainCfg {
   static constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT, ML = pg.ML;
   static constexpr int MT1 = (S1 + 3) / 4;         // dW1 M-tiles (X slot rows 4t+g)
   static constexpr int RX = 16 * MT1;               // X rows in the transpose buffer
-  static constexpr int RS = lds_row_stride<T>();
+  // Wavefronts per block (16 samples each per step) and blocks per CU.  FP16: one
+  // block of 8 (2 per SIMD) with three-phase staging and 16 x 16 tiles; measured
+  // faster than two blocks of 4 once the latent accumulators are FP64 (which two
+  // blocks cannot fit next to a 16 x 16 tile).  FP32: one block of 4 (its packs and
+  // staging are twice the size).
+#ifndef NTC_TRAIN_NW16
+#define NTC_TRAIN_NW16 8
+#endif
+#ifndef NTC_TRAIN_BPC16
+#define NTC_TRAIN_BPC16 1
+#endif
+  static constexpr int NW = sizeof(T) == 2 ? NTC_TRAIN_NW16 : 4;
+  static constexpr int BPC = sizeof(T) == 2 ? NTC_TRAIN_BPC16 : 1;
+  static constexpr int NTHR = 64 * NW, NCOL = 16 * NW;
+  static constexpr int RS = lds_row_stride<T, NCOL>();
   // one-phase weight-gradient staging: rows X | H1 | H2 | dZ1 | dZ2 | dY
   static constexpr int RH1 = RX, RH2 = RX + HD, RDZ1 = RX + 2 * HD, RDZ2 = RX + 3 * HD, RDY = RX + 4 * HD;
   static constexpr int TR1 = RX + 4 * HD + 16;
   static constexpr int TR3 = cmax(cmax(RX + HD, 2 * HD), HD + 16);  // three-phase staging
-  static constexpr int NT2 = (MT * MT + 3) / 4;     // dW2 tiles per wavefront
-  static constexpr int NT1 = (MT1 * MT + 3) / 4;    // dW1 tiles per wavefront
+  static constexpr int NT2 = (MT * MT + NW - 1) / NW;     // dW2 tiles per wavefront
+  static constexpr int NT1 = (MT1 * MT + NW - 1) / NW;    // dW1 tiles per wavefront
   static constexpr long long K = 4 * C0 + C1 + 12;
   static constexpr long long P = K * HD + HD + (long long)HD * HD + HD + (long long)HD * C + C;
   static constexpr long long W1o = 0, b1o = K * HD, W2o = b1o + HD, b2o = W2o + (long long)HD * HD;
@@ -144,29 +158,28 @@ struct TrainCfg {
   static constexpr int OFF_BIAS = OFF_PE + 48 * 4;
   static constexpr int OFF_TAB = OFF_BIAS + (2 * HD + 16) * 4;  // g0_off[8], g1_off[8], mip_off[16]
   static constexpr int OFF_RED = OFF_TAB + 32 * 8;
-  static constexpr int OFF_BUF = (OFF_RED + 16 + 15) / 16 * 16;
+  static constexpr int OFF_BUF = (OFF_RED + 4 * NW + 15) / 16 * 16;
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
-  // FP16: two blocks per CU (the second block hides the first one's memory stalls);
-  // FP32 packs are twice the size, so FP32 keeps one block with the larger staging
-  static constexpr int kBlocksPerCu = sizeof(T) == 2 ? 2 : 1;
-  static constexpr int kLdsCap = 160 * 1024 / kBlocksPerCu;
+  static constexpr int kLdsCap = 160 * 1024 / BPC;
   static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
   // one-phase staging when it fits next to a tile of at least 16 x 16 cells
-  static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 4 <= kLdsCap;
+  static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
   // largest tile side whose owned-latent gradient fits next to the rest
-  static constexpr int TMAX = OFF_REG + region(32) * 4 <= kLdsCap ? 32 : OFF_REG + region(16) * 4 <= kLdsCap ? 16 : 8;
-  static constexpr int LDS = OFF_REG + region(TMAX) * 4;
+  static constexpr int TMAX = OFF_REG + region(32) * 8 <= kLdsCap ? 32 : OFF_REG + region(16) * 8 <= kLdsCap ? 16 : 8;
+  static constexpr int LDS = OFF_REG + region(TMAX) * 8;
 };
 
 template <typename T, int C0, int C1, int C, int HD, int ACT>
-__global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) void train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
+__global__ __launch_bounds__((TrainCfg<T, C0, C1, C, HD>::NTHR),
+                             (TrainCfg<T, C0, C1, C, HD>::NW * TrainCfg<T, C0, C1, C, HD>::BPC / 4)) void
+train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
   constexpr PackGeom pg = Cfg::pg;
   constexpr int S1 = Cfg::S1, SH = Cfg::SH, MT = Cfg::MT, ML = Cfg::ML, MT1 = Cfg::MT1, RX = Cfg::RX;
-  constexpr int RS = Cfg::RS;
+  constexpr int RS = Cfg::RS, NW = Cfg::NW, NTHR = Cfg::NTHR, NCOL = Cfg::NCOL;
   extern __shared__ __align__(16) char smem[];
   T* w_lds = reinterpret_cast<T*>(smem);
   float* pe_lds = reinterpret_cast<float*>(smem + Cfg::OFF_PE);
@@ -174,13 +187,15 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
   long long* tab = reinterpret_cast<long long*>(smem + Cfg::OFF_TAB);
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
-  float* reg = reinterpret_cast<float*>(smem + Cfg::OFF_REG);
+  // owned-latent gradient accumulators: FP64, because LDS FP32 atomic adds run ~8x
+  // slower than FP64 ones on this GPU (and ~25x slower than integer ones)
+  double* reg = reinterpret_cast<double*>(smem + Cfg::OFF_REG);
 
   const int tid = threadIdx.x;
-  for (int i = tid; i < Cfg::WB / 16; i += 256)
+  for (int i = tid; i < Cfg::WB / 16; i += NTHR)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.wpack)[i];
-  for (int i = tid; i < 48; i += 256) pe_lds[i] = pe.v[i / 6][i % 6];
-  for (int i = tid; i < 2 * HD + 16; i += 256) {
+  for (int i = tid; i < 48; i += NTHR) pe_lds[i] = pe.v[i / 6][i % 6];
+  for (int i = tid; i < 2 * HD + 16; i += NTHR) {
     float v = 0.f;
     if (i < HD) v = a.mlp[Cfg::b1o + i];
     else if (i < 2 * HD) v = a.mlp[Cfg::b2o + i - HD];
@@ -230,13 +245,14 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
       cnt = (int)min((long long)kChunk, a.n - start);
     }
     const int T1 = T_ >> 1;
+    const int ts = __builtin_ctz(T_), t1s = ts - 1;  // tile sides are powers of two >= 2
     const int R0 = T_ * T_ * C0;
     const int RG = R0 + T1 * T1 * C1;
     if (a.binned)
-      for (int k = tid; k < RG; k += 256) reg[k] = 0.f;
+      for (int k = tid; k < RG; k += NTHR) reg[k] = 0.0;
     __syncthreads();
 
-    // the list entry (query + sample index) of one 64-sample step; the next step's
+    // the list entry (query + sample index) of one NCOL-sample step; the next step's
     // entry is loaded before this step's gathers, so it arrives with them
     auto load_entry = [&](int t0, float& u, float& v, int& lod, long long& s) {
       const int pos = t0 + wave * 16 + r;
@@ -262,14 +278,14 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
     int nlod;
     long long ns;
     load_entry(0, nu, nv, nlod, ns);
-    for (int t0 = 0; t0 < cnt; t0 += 64) {
+    for (int t0 = 0; t0 < cnt; t0 += NCOL) {
       const bool valid = t0 + wave * 16 + r < cnt;
       const float u = nu, v = nv;
       const int lod = nlod;
       const long long s = ns;
-      if (t0 + 64 < cnt) load_entry(t0 + 64, nu, nv, nlod, ns);
+      if (t0 + NCOL < cnt) load_entry(t0 + NCOL, nu, nv, nlod, ns);
       const Footprint f = locate(m, u, v, lod, g);
-      const bool primary = valid && (!a.binned || (f.ax / T_ == tx && f.ay / T_ == ty));
+      const bool primary = valid && (!a.binned || ((f.ax >> ts) == tx && (f.ay >> ts) == ty));
       const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
       const long long g1base = tab[8 + f.j];
 
@@ -390,9 +406,9 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
         // samples are sorted by anchor cell, a row (16 samples of one lane group) that
         // targets a single cell is summed across lanes first (one atomic per channel).
         const int rr = lane & 15;
-        const bool own0 = valid && f.g0x / T_ == tx && f.g0y / T_ == ty;
+        const bool own0 = valid && (f.g0x >> ts) == tx && (f.g0y >> ts) == ty;
         const int key0 = own0 ? ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) : -1;
-        float* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
+        double* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
         if (sorted) {
           const int rk = __shfl(key0, lane & ~15);
           const unsigned long long bal = __ballot(key0 == rk || !valid);
@@ -401,21 +417,21 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
           for (int t = 0; t < C0; ++t) {
             const float sv = row_sum16(own0 ? dx[t] : 0.f);
             if (uni) {
-              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, sv);
+              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, (double)sv);
             } else if (own0) {
-              atomicAdd(dst0 + t, dx[t]);
+              atomicAdd(dst0 + t, (double)dx[t]);
             }
           }
         } else if (own0) {
 #pragma unroll
-          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, dx[t]);
+          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, (double)dx[t]);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
-          const bool own1 = valid && x1 / T1 == tx && y1 / T1 == ty && f.g1_w[k] != 0.f;
+          const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
           const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
-          float* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
+          double* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
           if (sorted) {
             const int rk = __shfl(key1, lane & ~15);
             const unsigned long long bal = __ballot(key1 == rk || !valid);
@@ -427,9 +443,9 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
               const float sv = row_sum16(v1);
               if (ch < C1) {
                 if (uni) {
-                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, sv);
+                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, (double)sv);
                 } else if (own1) {
-                  atomicAdd(dst1 + ch, v1);
+                  atomicAdd(dst1 + ch, (double)v1);
                 }
               }
             }
@@ -437,18 +453,20 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
 #pragma unroll
             for (int i = 0; i < IS::n1max; ++i) {
               const int ch = g + 4 * i;
-              if (ch < C1) atomicAdd(dst1 + ch, f.g1_w[k] * dx[C0 + i]);
+              if (ch < C1) atomicAdd(dst1 + ch, (double)(f.g1_w[k] * dx[C0 + i]));
             }
           }
         }
       }
 
       // ---------------- weight gradients through LDS (texels become the K axis);
-      // only a sample's primary copy contributes.  Bias gradients are row sums of the
-      // deltas: thread (row = tid/4, quarter q = tid%4) adds 16 columns per row.
+      // only a sample's primary copy contributes.  Column wave*16 + r holds texel r of
+      // wave `wave`.  Bias gradients are row sums of the deltas: thread (row = tid / PARTS,
+      // part = tid % PARTS) adds the 16 columns of its part of the row.
       const int col = wave * 16 + r;
       const T zero = (T)0.f;
-      const int brow = tid >> 2, bq = tid & 3;
+      constexpr int PARTS = NCOL / 16;
+      const int brow = tid / PARTS, bq = tid % PARTS;
       if constexpr (Cfg::ONE_PHASE) {
         // all operands at once: X | H1 | H2 | dZ1 | dZ2 | dY
 #pragma unroll
@@ -464,22 +482,22 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
 #pragma unroll
         for (int i = 0; i < 4; ++i) buf[(Cfg::RDY + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
         __syncthreads();
-        if (wave < MT) acc3 = dw_tile<T>(acc3, buf, Cfg::RH2 + 16 * wave, Cfg::RDY, g, r);
+        if (wave < MT) acc3 = dw_tile<T, NCOL>(acc3, buf, Cfg::RH2 + 16 * wave, Cfg::RDY, g, r);
 #pragma unroll
         for (int k = 0; k < Cfg::NT2; ++k) {
-          const int id = wave + 4 * k;
-          if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, Cfg::RH1 + 16 * (id / MT), Cfg::RDZ2 + 16 * (id % MT), g, r);
+          const int id = wave + NW * k;
+          if (id < MT * MT) acc2[k] = dw_tile<T, NCOL>(acc2[k], buf, Cfg::RH1 + 16 * (id / MT), Cfg::RDZ2 + 16 * (id % MT), g, r);
         }
 #pragma unroll
         for (int k = 0; k < Cfg::NT1; ++k) {
-          const int id = wave + 4 * k;
-          if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), Cfg::RDZ1 + 16 * (id % MT), g, r);
+          const int id = wave + NW * k;
+          if (id < MT1 * MT) acc1[k] = dw_tile<T, NCOL>(acc1[k], buf, 16 * (id / MT), Cfg::RDZ1 + 16 * (id % MT), g, r);
         }
         if (brow < HD) {
-          db1 += row_quarter_sum<T>(buf, Cfg::RDZ1 + brow, bq);
-          db2 += row_quarter_sum<T>(buf, Cfg::RDZ2 + brow, bq);
+          db1 += row_part_sum<T, NCOL>(buf, Cfg::RDZ1 + brow, bq);
+          db2 += row_part_sum<T, NCOL>(buf, Cfg::RDZ2 + brow, bq);
         }
-        if (brow < 16) db3 += row_quarter_sum<T>(buf, Cfg::RDY + brow, bq);
+        if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, Cfg::RDY + brow, bq);
         __syncthreads();
       } else {
         // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
@@ -488,8 +506,8 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
 #pragma unroll
         for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
         __syncthreads();
-        if (wave < MT) acc3 = dw_tile<T>(acc3, buf, 16 * wave, HD, g, r);
-        if (brow < 16) db3 += row_quarter_sum<T>(buf, HD + brow, bq);
+        if (wave < MT) acc3 = dw_tile<T, NCOL>(acc3, buf, 16 * wave, HD, g, r);
+        if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
         __syncthreads();
         // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
 #pragma unroll
@@ -500,10 +518,10 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < Cfg::NT2; ++k) {
-          const int id = wave + 4 * k;
-          if (id < MT * MT) acc2[k] = dw_tile<T>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
+          const int id = wave + NW * k;
+          if (id < MT * MT) acc2[k] = dw_tile<T, NCOL>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
         }
-        if (brow < HD) db2 += row_quarter_sum<T>(buf, HD + brow, bq);
+        if (brow < HD) db2 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
         __syncthreads();
         // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
 #pragma unroll
@@ -513,10 +531,10 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < Cfg::NT1; ++k) {
-          const int id = wave + 4 * k;
-          if (id < MT1 * MT) acc1[k] = dw_tile<T>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
+          const int id = wave + NW * k;
+          if (id < MT1 * MT) acc1[k] = dw_tile<T, NCOL>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
         }
-        if (brow < HD) db1 += row_quarter_sum<T>(buf, RX + brow, bq);
+        if (brow < HD) db1 += row_part_sum<T, NCOL>(buf, RX + brow, bq);
         __syncthreads();
       }
     }
@@ -525,7 +543,7 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
     if (a.binned) {
       if (single) {
         const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
-        for (int k = tid; k < RG; k += 256) {
+        for (int k = tid; k < RG; k += NTHR) {
           long long gi;
           if (k < R0) {
             const int c = k % C0, cell = k / C0, cx = cell % T_, cy = cell / T_;
@@ -534,11 +552,11 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
             const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
             gi = tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
           }
-          a.lat_grad[gi] = reg[k] * a.out_scale;
+          a.lat_grad[gi] = (float)reg[k] * a.out_scale;
         }
       } else {
         float* dst = a.part_lat + (long long)item * a.region_max;
-        for (int k = tid; k < RG; k += 256) dst[k] = reg[k];
+        for (int k = tid; k < RG; k += NTHR) dst[k] = (float)reg[k];
       }
       __syncthreads();
     }
@@ -555,7 +573,7 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
   }
 #pragma unroll
   for (int k = 0; k < Cfg::NT2; ++k) {
-    const int id = wave + 4 * k;
+    const int id = wave + NW * k;
     if (id < MT * MT) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -566,7 +584,7 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
   }
 #pragma unroll
   for (int k = 0; k < Cfg::NT1; ++k) {
-    const int id = wave + 4 * k;
+    const int id = wave + NW * k;
     if (id < MT1 * MT) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -577,15 +595,16 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
       }
     }
   }
-  // bias gradients: the four quarter sums of each row are in lanes 4*row .. 4*row+3
-  db1 += __shfl_xor(db1, 1);
-  db1 += __shfl_xor(db1, 2);
-  db2 += __shfl_xor(db2, 1);
-  db2 += __shfl_xor(db2, 2);
-  db3 += __shfl_xor(db3, 1);
-  db3 += __shfl_xor(db3, 2);
-  if ((tid & 3) == 0) {
-    const int row = tid >> 2;
+  // bias gradients: the PARTS part sums of each row are in consecutive lanes
+  constexpr int PARTS = NCOL / 16;
+#pragma unroll
+  for (int o = 1; o < PARTS; o <<= 1) {
+    db1 += __shfl_xor(db1, o);
+    db2 += __shfl_xor(db2, o);
+    db3 += __shfl_xor(db3, o);
+  }
+  if (tid % PARTS == 0) {
+    const int row = tid / PARTS;
     if (row < HD) {
       part[Cfg::b1o + row] = db1;
       part[Cfg::b2o + row] = db2;
@@ -595,7 +614,11 @@ __global__ __launch_bounds__(256, (TrainCfg<T, C0, C1, C, HD>::kBlocksPerCu)) vo
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
   if (lane == 0) red[wave] = loss;
   __syncthreads();
-  if (tid == 0) a.part_loss[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) {
+    float l = 0.f;
+    for (int w = 0; w < NW; ++w) l += red[w];
+    a.part_loss[blockIdx.x] = l;
+  }
 }
 
 // ------------------------------------------------------------------ binning (counting sort)
@@ -917,7 +940,7 @@ static int fused_per_cu() {
   static int cached = 0;
   if (cached == 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD, ACT>, 256,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD, ACT>, Cfg::NTHR,
                                                      Cfg::LDS) !=
             hipSuccess ||
         per_cu < 1)
@@ -965,7 +988,7 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.out_scale = l.out_scale;
   a.tg = p.tg;
   const int slot = timing_before(TK_TRAIN_FUSED, s);
-  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(256), Cfg::LDS, s, dev_mat(mm),
+  hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(Cfg::NTHR), Cfg::LDS, s, dev_mat(mm),
                      pe_table(), a);
   timing_after(TK_TRAIN_FUSED, s, slot);
   return hipGetLastError();

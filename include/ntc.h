@@ -197,7 +197,12 @@ typedef struct {
  * (noise_seed, s, latent index)).  precision: NTC_F32 or NTC_F16.  noise: add
  * U(-Q/2, Q/2) to the forward latents.  freeze_latents: the quantize-and-freeze
  * phase (latents neither noised nor updated).  scale_growth_interval: NTC_F16
- * doubles the loss scale after this many good steps (halves it on overflow). */
+ * doubles the loss scale after this many good steps (halves it on overflow).
+ * Graph replay: with step_dev (device int32, optional) the kernels read the step
+ * index from device memory instead of `step`, and ntc_train_update (ntc_train_step)
+ * increments it after the update, so one captured step can be replayed; with lr_dev
+ * (device float[2] = latent, MLP learning rate, optional) the learning rates are read
+ * on the device as well.  NULL: the host values are used. */
 typedef struct {
   float lr_latent, lr_mlp, beta1, beta2, eps;
   uint64_t noise_seed;
@@ -206,11 +211,31 @@ typedef struct {
   int32_t noise;
   int32_t freeze_latents;
   int32_t scale_growth_interval;
+  int32_t* step_dev;
+  const float* lr_dev;
 } ntc_hparams;
 
 size_t ntc_train_packed_bytes(const ntc_material* m, ntc_dtype precision);
 /* Workspace for a training step of n samples on the current device. */
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision);
+
+/*
+ * Tuning of the training step (tile shapes): times ntc_train_gradients of this
+ * material and sample count for each candidate (samples per work item, latent-tile
+ * side) and keeps the fastest for the material's shape (c0, c1, channels, hidden,
+ * activation) and precision; later plans of that shape use it.  Writes lat_grad and
+ * the workspace but not the masters or the optimiser state; synchronizes the stream.
+ * Thread-safe (the table is mutex-guarded).  chosen (host, optional) receives the
+ * choice and its time per gradient pass.
+ */
+typedef struct {
+  int32_t chunk;        /* samples per work item */
+  int32_t tile;         /* latent-tile side (G0 cells) */
+  double microseconds;  /* measured time of one gradient pass */
+} ntc_train_tuning;
+ntc_status ntc_train_autotune(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
+                              const float* targets, const ntc_hparams* hp, void* workspace, size_t ws_bytes,
+                              void* stream, ntc_train_tuning* chosen);
 
 /*
  * Make the state consistent for step hp->step: latents_fwd = latents (+ that
@@ -279,6 +304,31 @@ size_t ntc_backward_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype 
 ntc_status ntc_backward(const ntc_material* m, const float* latents, const float* mlp, const void* mlp_train_packed,
                         ntc_dtype precision, const ntc_query* q, int64_t n, const float* dout, float dout_scale,
                         float* grad_latents, float* grad_mlp, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Many materials (uneven sizes, channel counts and MLP widths, each with its own
+ * weights and state) in one call.  Queries are grouped per material: material i
+ * owns q[offsets[i] .. offsets[i+1]) (offsets: host, nmat + 1 entries, offsets[0] = 0,
+ * non-decreasing; an empty group skips the material).  Every argument of every
+ * material is validated before anything is enqueued; the calls enqueue only kernel
+ * launches on `stream`, so a whole batched step can be captured in a HIP graph (with
+ * hp->step_dev, one captured step replays as the next step).
+ *   ntc_train_step_batched: one training step (ntc_train_step) of every material;
+ *     states[i], targets[i] (device pointer) per material, hp shared; with
+ *     hp->step_dev the step index advances once per batched step.  workspace:
+ *     ntc_train_workspace_bytes_batched bytes.
+ *   ntc_decode_batched: decode of every group (ntc_decode); packed_latents[i] and
+ *     mlp_packed[i] per material (mlp_packed from ntc_pack_mlp with `precision`);
+ *     out holds the groups one after another, n_i x C_i values each.
+ */
+size_t ntc_train_workspace_bytes_batched(const ntc_material* mats, int32_t nmat, const int64_t* offsets,
+                                         ntc_dtype precision);
+ntc_status ntc_train_step_batched(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                  const ntc_query* q, const int64_t* offsets, const float* const* targets,
+                                  const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream);
+ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
+                              const void* const* mlp_packed, ntc_dtype precision, const ntc_query* q,
+                              const int64_t* offsets, void* out, ntc_dtype out_dtype, void* stream);
 
 /*
  * Kernel timing for measurement (not needed for normal use).  After

@@ -2,6 +2,7 @@
 // launch sequence of each entry point.  No entry point allocates device memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -309,7 +310,13 @@ ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents,
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
   if (!m || n <= 0 || (precision != NTC_F32 && precision != NTC_F16)) return 0;
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden)) return 0;
-  return train_plan(*m, precision == NTC_F16, n).total;
+  // large enough for every tuning candidate, so a tuned plan always fits
+  const bool f16 = precision == NTC_F16;
+  size_t total = train_plan(*m, f16, n).total;
+  int nc = 0;
+  const TrainTune* c = train_tune_candidates(&nc);
+  for (int i = 0; i < nc; ++i) total = std::max(total, train_plan(*m, f16, n, &c[i]).total);
+  return total;
 }
 
 static ntc_status check_state(const ntc_train_state* s, bool f16) {
@@ -381,6 +388,7 @@ ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, 
   a.workspace = workspace;
   a.loss_scale = f16 ? s->loss_scale : nullptr;
   a.scale_slot = hp->step & 1;
+  a.step_dev = hp->step_dev;
   a.overflow_flag = s->scale_state + 1;
   a.scatter_latents = !hp->freeze_latents;
   a.dout = nullptr;
@@ -389,8 +397,86 @@ ntc_status ntc_train_gradients(const ntc_material* m, const ntc_train_state* s, 
   return hip_status(launch_train_gradients(*m, f16, plan, a, (hipStream_t)stream), "ntc_train_gradients");
 }
 
+ntc_status ntc_train_autotune(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
+                              const float* targets, const ntc_hparams* hp, void* workspace, size_t ws_bytes,
+                              void* stream, ntc_train_tuning* chosen) {
+  ntc_status st = check_train(m, s, hp, n);
+  if (st != NTC_OK) return st;
+  if (!q || !targets) return fail(NTC_E_INVALID, "NULL queries or targets");
+  if (hp->freeze_latents) return fail(NTC_E_INVALID, "tuning needs the latent scatter (freeze_latents = 0)");
+  const bool f16 = hp->precision == NTC_F16;
+  if (!workspace || ws_bytes < ntc_train_workspace_bytes(m, n, (ntc_dtype)hp->precision))
+    return fail(NTC_E_WORKSPACE, "workspace too small");
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError(), "ntc_train_autotune");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_status(hipGetLastError(), "ntc_train_autotune");
+  }
+  TrainLaunch a;
+  a.lat_fwd = s->latents_fwd;
+  a.wpack = s->mlp_packed;
+  a.mlp = s->mlp;
+  a.q = q;
+  a.n = n;
+  a.targets = targets;
+  a.lat_grad = s->lat_grad;
+  a.workspace = workspace;
+  a.loss_scale = f16 ? s->loss_scale : nullptr;
+  a.scale_slot = hp->step & 1;
+  a.step_dev = hp->step_dev;
+  a.overflow_flag = s->scale_state + 1;
+  a.scatter_latents = true;
+  a.dout = nullptr;
+  a.dout_scale = 1.f;
+  a.out_scale = 1.f;
+  int nc = 0;
+  const TrainTune* cand = train_tune_candidates(&nc);
+  float best = 1e30f;
+  TrainTune best_t{0, 0};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < nc && e == hipSuccess; ++i) {
+    const TrainPlan plan = train_plan(*m, f16, n, &cand[i]);
+    if (!plan.supported_bins || plan.total > ws_bytes) continue;
+    if (i > 0 && plan.tune.chunk == best_t.chunk && plan.tune.tile == best_t.tile) continue;
+    e = launch_train_gradients(*m, f16, plan, a, hs);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, hs);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_train_gradients(*m, f16, plan, a, hs);
+    if (e == hipSuccess) e = hipEventRecord(e1, hs);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_t = plan.tune;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_status(e, "ntc_train_autotune");
+  if (best_t.chunk == 0) return fail(NTC_E_UNSUPPORTED, "no tuning candidate fits this material");
+  set_train_tune(*m, f16, best_t);
+  if (chosen) {
+    chosen->chunk = best_t.chunk;
+    chosen->tile = best_t.tile;
+    chosen->microseconds = best * 1000.0 / 3.0;
+  }
+  return NTC_OK;
+}
+
+static ntc_status train_update_impl(const ntc_material* m, const ntc_train_state* s, int64_t n,
+                                    const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream,
+                                    bool advance_step);
+
 ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int64_t n, const ntc_hparams* hp,
                             void* workspace, size_t ws_bytes, void* stream) {
+  return train_update_impl(m, s, n, hp, workspace, ws_bytes, stream, true);
+}
+
+static ntc_status train_update_impl(const ntc_material* m, const ntc_train_state* s, int64_t n,
+                                    const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream,
+                                    bool advance_step) {
   ntc_status st = check_train(m, s, hp, n);
   if (st != NTC_OK) return st;
   const bool f16 = hp->precision == NTC_F16;
@@ -428,6 +514,10 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
     ad.freeze = hp->freeze_latents ? 1 : 0;
     ad.growth = hp->scale_growth_interval > 0 ? hp->scale_growth_interval : 2000;
     ad.f16 = f16 ? 1 : 0;
+    ad.step_dev = hp->step_dev;
+    ad.lr_dev = hp->lr_dev;
+    ad.seed = hp->noise_seed;
+    ad.advance = advance_step;
     e = launch_adam(*m, ad, hs);
   }
   return hip_status(e, "ntc_train_update");
@@ -491,6 +581,7 @@ ntc_status ntc_backward(const ntc_material* m, const float* latents, const float
   a.workspace = workspace;
   a.loss_scale = nullptr;
   a.scale_slot = 0;
+  a.step_dev = nullptr;
   a.overflow_flag = (int32_t*)(ws + plan.off_misc + 16);
   a.scatter_latents = true;
   a.dout = dout;
@@ -508,6 +599,91 @@ ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const
   ntc_status st = ntc_train_gradients(m, s, q, n, targets, hp, workspace, ws_bytes, stream);
   if (st != NTC_OK) return st;
   return ntc_train_update(m, s, n, hp, workspace, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------ many materials
+static ntc_status check_batch(const ntc_material* mats, int32_t nmat, const int64_t* offsets) {
+  if (!mats || !offsets) return fail(NTC_E_INVALID, "NULL materials or offsets");
+  if (nmat < 1) return fail(NTC_E_INVALID, "nmat must be positive");
+  if (offsets[0] != 0) return fail(NTC_E_INVALID, "offsets[0] must be 0");
+  for (int i = 0; i < nmat; ++i) {
+    ntc_status st = check_material(mats + i);
+    if (st != NTC_OK) return st;
+    if (offsets[i + 1] < offsets[i]) return fail(NTC_E_INVALID, "offsets must be non-decreasing");
+  }
+  return NTC_OK;
+}
+
+size_t ntc_train_workspace_bytes_batched(const ntc_material* mats, int32_t nmat, const int64_t* offsets,
+                                         ntc_dtype precision) {
+  if (check_batch(mats, nmat, offsets) != NTC_OK) return 0;
+  size_t total = 0;
+  for (int i = 0; i < nmat; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n <= 0) continue;
+    const size_t b = ntc_train_workspace_bytes(mats + i, n, precision);
+    if (b == 0) return 0;
+    total += (b + 255) / 256 * 256;
+  }
+  return total;
+}
+
+ntc_status ntc_train_step_batched(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                  const ntc_query* q, const int64_t* offsets, const float* const* targets,
+                                  const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream) {
+  ntc_status st = check_batch(mats, nmat, offsets);
+  if (st != NTC_OK) return st;
+  if (!states || !q || !targets) return fail(NTC_E_INVALID, "NULL states, queries or targets");
+  for (int i = 0; i < nmat; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n <= 0) continue;
+    if ((st = check_train(mats + i, states + i, hp, n)) != NTC_OK) return st;
+    if (!targets[i]) return fail(NTC_E_INVALID, "NULL targets");
+    if (!train_plan(mats[i], hp->precision == NTC_F16, n).supported_bins)
+      return fail(NTC_E_UNSUPPORTED, "too many latent tiles for a material");
+  }
+  const size_t need = ntc_train_workspace_bytes_batched(mats, nmat, offsets, (ntc_dtype)hp->precision);
+  if (!workspace || need == 0 || ws_bytes < need) return fail(NTC_E_WORKSPACE, "workspace too small");
+  char* ws = (char*)workspace;
+  size_t off = 0;
+  for (int i = 0; i < nmat; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n <= 0) continue;
+    const size_t b = (ntc_train_workspace_bytes(mats + i, n, (ntc_dtype)hp->precision) + 255) / 256 * 256;
+    st = ntc_train_gradients(mats + i, states + i, q + offsets[i], n, targets[i], hp, ws + off, b, stream);
+    if (st == NTC_OK)
+      st = train_update_impl(mats + i, states + i, n, hp, ws + off, b, stream, /*advance_step=*/false);
+    if (st != NTC_OK) return st;
+    off += b;
+  }
+  if (hp->step_dev)  // one step for the whole batch
+    return hip_status(launch_step_advance(hp->step_dev, (hipStream_t)stream), "ntc_train_step_batched");
+  return NTC_OK;
+}
+
+ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
+                              const void* const* mlp_packed, ntc_dtype precision, const ntc_query* q,
+                              const int64_t* offsets, void* out, ntc_dtype out_dtype, void* stream) {
+  ntc_status st = check_batch(mats, nmat, offsets);
+  if (st != NTC_OK) return st;
+  if (!packed_latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  for (int i = 0; i < nmat; ++i) {
+    if ((st = check_decode(mats + i, precision, out_dtype)) != NTC_OK) return st;
+    if (offsets[i + 1] > offsets[i] && (!packed_latents[i] || !mlp_packed[i]))
+      return fail(NTC_E_INVALID, "NULL latents or weights");
+  }
+  const size_t esz = out_dtype == NTC_F16 ? 2 : 4;
+  size_t o = 0;
+  for (int i = 0; i < nmat; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n > 0) {
+      st = run_decode(mats + i, packed_latents[i], mlp_packed[i], precision, q + offsets[i], n, nullptr,
+                      (char*)out + o * esz, out_dtype, stream, "ntc_decode_batched");
+      if (st != NTC_OK) return st;
+    }
+    o += (size_t)n * mats[i].channels;
+  }
+  return NTC_OK;
 }
 
 }  // extern "C"

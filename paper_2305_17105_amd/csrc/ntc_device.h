@@ -418,6 +418,7 @@ struct TileGeom {
   int bin_base[kMaxLevels + 1];   // first sort bin of each level
   int region[kMaxLevels];
   int ntiles, nbins, region_max;
+  int chunk;                       // samples per work item
 };
 
 __host__ __device__ inline int sort_bin(const TileGeom& tg, int j, int tx, int ty, int ax, int ay) {

@@ -42,9 +42,19 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
                          const ntc_query* q, long long n, const TexelRect* rect, void* out, bool out_f16,
                          hipStream_t s);
 
+// Tunable plan parameters: samples per work item and largest latent-tile side
+// (0: the kernel's capacity).
+struct TrainTune {
+  int chunk, tile;
+};
+void set_train_tune(const ntc_material& m, bool f16, const TrainTune& t);
+TrainTune get_train_tune(const ntc_material& m, bool f16);
+const TrainTune* train_tune_candidates(int* count);
+
 // Launch plan of a training step: tile geometry, grids and workspace layout (bytes).
 struct TrainPlan {
   TileGeom tg;
+  TrainTune tune;  // the parameters in effect
   int nbins, ntiles, region_max, nbb, per_bin_block, grid;
   long long max_items;
   bool supported_bins;
@@ -53,7 +63,8 @@ struct TrainPlan {
   size_t off_part_lat;
   size_t off_part_dw, off_part_loss, off_tmp, off_grad, total;
 };
-TrainPlan train_plan(const ntc_material& m, bool f16, long long n);
+// tune == nullptr: the tuning table's entry for the material's shape (or the defaults)
+TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTune* tune = nullptr);
 
 struct TrainLaunch {
   const float* lat_fwd;
@@ -66,6 +77,7 @@ struct TrainLaunch {
   void* workspace;
   const float* loss_scale;  // device, 2 entries, or nullptr (scale 1)
   int scale_slot;
+  const int* step_dev;      // device step index (graph replay) or nullptr: scale_slot
   int32_t* overflow_flag;   // reset by the fused kernel
   bool scatter_latents;     // false: latents frozen, samples processed in query order
   const float* dout;        // external output gradient, or nullptr (L2 loss against targets)
@@ -96,8 +108,13 @@ struct AdamLaunch {
   float lr_lat, lr_mlp, beta1, beta2, eps, bc1, bc2;
   uint64_t next_key;   // noise key of step + 1
   int step, noise, freeze, growth, f16;
+  int* step_dev;        // device step index or nullptr (then step, bc1, bc2, next_key)
+  const float* lr_dev;  // device (lr_lat, lr_mlp) or nullptr
+  uint64_t seed;        // noise seed (device-step mode derives the key on the device)
+  bool advance;         // device-step mode: advance the step index after the update
 };
 hipError_t launch_adam(const ntc_material& m, const AdamLaunch& a, hipStream_t s);
+hipError_t launch_step_advance(int* step_dev, hipStream_t s);
 hipError_t launch_prepare(const ntc_material& m, const float* latents, float* latents_fwd, float* lat_grad,
                           uint64_t key, int noise, hipStream_t s);
 

@@ -7,7 +7,7 @@
 //  1. bin_count / bin_scan / bin_scatter: each sample is listed under every tile
 //     whose latents its footprint (2x2 G0 cells, 4 G1 taps) touches (at most 4),
 //     a counting sort with per-block LDS histograms.  A tile's list is cut into
-//     work items of at most kChunk samples.
+//     work items of at most `chunk` samples (a plan parameter).
 //  2. train_fused_kernel: a persistent block takes work items; for each step of
 //     16 texels per wavefront it gathers latents + PE, runs the MLP forward on matrix cores, the
 //     L2 loss and dY, the backward through the three layers (transposed-weight
@@ -25,12 +25,14 @@
 //     step's noisy forward latents, refreshed weight packs, FP16 loss scale.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "ntc_internal.h"
 
 namespace ntc {
 
-constexpr int kChunk = 512;       // samples per work item
+constexpr int kChunkDefault = 512;  // samples per work item unless tuned
 constexpr int kBinBlockSamples = 1024;
 constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
 constexpr int kSortedCells = 4096; // levels with at most this many G0 cells are sorted by anchor cell
@@ -55,6 +57,7 @@ struct TrainArgs {
   float* part_loss;
   const float* loss_scale;
   int scale_slot;
+  const int* step_dev;
   int32_t* overflow_flag;
   int binned;
   int region_max;
@@ -210,7 +213,8 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   if (blockIdx.x == 0 && tid == 0) *a.overflow_flag = 0;
   __syncthreads();
 
-  const float scale = a.loss_scale ? a.loss_scale[a.scale_slot] : 1.f;
+  const int slot = a.step_dev ? (*a.step_dev & 1) : a.scale_slot;
+  const float scale = a.loss_scale ? a.loss_scale[slot] : 1.f;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
 
   f32x4 acc3 = {0.f, 0.f, 0.f, 0.f};
@@ -221,7 +225,8 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   for (int k = 0; k < Cfg::NT1; ++k) acc1[k] = acc3;
   float db1 = 0.f, db2 = 0.f, db3 = 0.f, loss = 0.f;
 
-  const int nitems = a.binned ? *a.nitems : (int)((a.n + kChunk - 1) / kChunk);
+  const int chunk_n = a.tg.chunk;
+  const int nitems = a.binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     // ---------------- work item -> (tile, sample range)
     int j = 0, tx = 0, ty = 0, T_ = 2, cnt;
@@ -232,8 +237,8 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
       const int tile = a.item_tile[item];
       const int chunk = item - a.item_base[tile];
       single = (a.item_base[tile + 1] - a.item_base[tile]) == 1;
-      start = (long long)a.tile_start[tile] + (long long)chunk * kChunk;
-      cnt = min(kChunk, a.tile_total[tile] - chunk * kChunk);
+      start = (long long)a.tile_start[tile] + (long long)chunk * chunk_n;
+      cnt = min(chunk_n, a.tile_total[tile] - chunk * chunk_n);
       while (j + 1 < m.J && tile >= a.tg.tile_base[j + 1]) ++j;
       const int t = tile - a.tg.tile_base[j];
       tx = t % a.tg.ntx[j];
@@ -241,8 +246,8 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
       T_ = a.tg.T[j];
       sorted = a.tg.sb[j] > 1;
     } else {
-      start = (long long)item * kChunk;
-      cnt = (int)min((long long)kChunk, a.n - start);
+      start = (long long)item * chunk_n;
+      cnt = (int)min((long long)chunk_n, a.n - start);
     }
     const int T1 = T_ >> 1;
     const int ts = __builtin_ctz(T_), t1s = ts - 1;  // tile sides are powers of two >= 2
@@ -693,7 +698,7 @@ __global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, cons
 }
 
 // One block of 1024 threads: exclusive scan over the sort bins of their totals (list
-// positions), then per tile its start, total and work items (at most kChunk samples
+// positions), then per tile its start, total and work items (at most tg.chunk samples
 // per item, at least one), and the exclusive scan of the items over the tiles.
 template <int PER>
 __device__ inline int block_exclusive_scan(int v, int* sh) {
@@ -756,12 +761,12 @@ __global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int*
       const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
       tile_start[t] = st;
       tile_total[t] = tot;
-      items += max(1, (tot + kChunk - 1) / kChunk);
+      items += max(1, (tot + tg.chunk - 1) / tg.chunk);
     }
     int pi = block_exclusive_scan<kPer>(items, s_scan);
     for (int e = 0; e < per && t0 + e < nt; ++e) {
       const int tot = tile_total[t0 + e];
-      const int k = max(1, (tot + kChunk - 1) / kChunk);
+      const int k = max(1, (tot + tg.chunk - 1) / tg.chunk);
       item_base[t0 + e] = pi;
       for (int i = 0; i < k; ++i) item_tile[pi + i] = t0 + e;
       pi += k;
@@ -871,17 +876,32 @@ template <typename T>
 __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
   const AdamLaunch& a = args.a;
   const int ovf = a.scale_state[1];
-  const float scale = a.loss_scale ? a.loss_scale[a.step & 1] : 1.f;
+  // step-dependent values: from the host, or derived from the device step index
+  int step = a.step;
+  float bc1 = a.bc1, bc2 = a.bc2, lr_lat = a.lr_lat, lr_mlp = a.lr_mlp;
+  uint64_t next_key = a.next_key;
+  if (a.step_dev) {
+    step = *a.step_dev;
+    const double t = (double)step + 1.0;
+    bc1 = (float)(1.0 - exp(t * log((double)a.beta1)));
+    bc2 = (float)(1.0 - exp(t * log((double)a.beta2)));
+    next_key = noise_key(a.seed, step + 1);
+  }
+  if (a.lr_dev) {
+    lr_lat = a.lr_dev[0];
+    lr_mlp = a.lr_dev[1];
+  }
+  const float scale = a.loss_scale ? a.loss_scale[step & 1] : 1.f;
   const float inv_s = 1.f / scale;
   const float b1 = a.beta1, b2 = a.beta2, eps = a.eps;
-  const float ib1 = 1.f / a.bc1, ib2 = 1.f / a.bc2;
+  const float ib1 = 1.f / bc1, ib2 = 1.f / bc2;
   if ((int)blockIdx.x < args.mlp_blocks) {
     const long long p = blockIdx.x * 256ll + threadIdx.x;
     if (p < args.P && !ovf) {
       const float gr = a.mlp_grad[p] * inv_s;
       const float mm = b1 * a.mlp_m[p] + (1.f - b1) * gr;
       const float vv = b2 * a.mlp_v[p] + (1.f - b2) * gr * gr;
-      const float w = a.mlp[p] - a.lr_mlp * (mm * ib1) / (sqrtf(vv * ib2) + eps);
+      const float w = a.mlp[p] - lr_mlp * (mm * ib1) / (sqrtf(vv * ib2) + eps);
       a.mlp_m[p] = mm;
       a.mlp_v[p] = vv;
       a.mlp[p] = w;
@@ -897,7 +917,7 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
         sn = scale * 2.f;
         good = 0;
       }
-      a.loss_scale[(a.step + 1) & 1] = sn;
+      a.loss_scale[(step + 1) & 1] = sn;
       a.scale_state[0] = good;
     }
     return;
@@ -912,15 +932,20 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
       const float gr = a.lat_grad[i] * inv_s;
       const float mm = b1 * a.lat_m[i] + (1.f - b1) * gr;
       const float vv = b2 * a.lat_v[i] + (1.f - b2) * gr * gr;
-      p = p - a.lr_lat * (mm * ib1) / (sqrtf(vv * ib2) + eps);
+      p = p - lr_lat * (mm * ib1) / (sqrtf(vv * ib2) + eps);
       const float lo = -0.5f + ldexpf(1.f, -bits - 1);  // -(N-1)/(2N)
       p = fminf(fmaxf(p, lo), 0.5f);
       a.lat_m[i] = mm;
       a.lat_v[i] = vv;
       a.latents[i] = p;
     }
-    a.latents_fwd[i] = a.noise ? p + noise_at(a.next_key, i, bits) : p;
+    a.latents_fwd[i] = a.noise ? p + noise_at(next_key, i, bits) : p;
   }
+}
+
+// Device-step mode: the step index advances once the update has read it.
+__global__ void step_advance_kernel(int* step) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
 }
 
 __global__ void prepare_kernel(DevMat m, const float* __restrict__ lat, float* __restrict__ fwd, float* __restrict__ grad,
@@ -979,6 +1004,7 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.part_loss = (float*)(ws + p.off_part_loss);
   a.loss_scale = l.loss_scale;
   a.scale_slot = l.scale_slot;
+  a.step_dev = l.step_dev;
   a.overflow_flag = l.overflow_flag;
   a.binned = l.scatter_latents ? 1 : 0;
   a.region_max = p.region_max;
@@ -1008,8 +1034,60 @@ bool train_shape_supported(int c0, int c1, int c, int hd) {
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
+// ------------------------------------------------------------------ tuning table
+// Work-item size and tile side per (shape, precision, activation), chosen by
+// ntc_train_autotune; plans without an entry use the defaults.
+namespace {
+struct TuneKey {
+  int c0, c1, c, hd, f16, act;
+  bool operator==(const TuneKey& o) const {
+    return c0 == o.c0 && c1 == o.c1 && c == o.c && hd == o.hd && f16 == o.f16 && act == o.act;
+  }
+};
+struct TuneTable {
+  std::mutex mu;
+  std::vector<std::pair<TuneKey, TrainTune>> rows;
+};
+TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
+}
+TuneKey tune_key(const ntc_material& m, bool f16) {
+  return TuneKey{m.c0, m.c1, m.channels, m.hidden, f16 ? 1 : 0, m.activation};
+}
+}  // namespace
+
+void set_train_tune(const ntc_material& m, bool f16, const TrainTune& t) {
+  TuneTable& tb = tune_table();
+  std::lock_guard<std::mutex> lock(tb.mu);
+  const TuneKey k = tune_key(m, f16);
+  for (auto& r : tb.rows)
+    if (r.first == k) {
+      r.second = t;
+      return;
+    }
+  tb.rows.push_back({k, t});
+}
+
+TrainTune get_train_tune(const ntc_material& m, bool f16) {
+  TuneTable& tb = tune_table();
+  std::lock_guard<std::mutex> lock(tb.mu);
+  const TuneKey k = tune_key(m, f16);
+  for (auto& r : tb.rows)
+    if (r.first == k) return r.second;
+  return TrainTune{kChunkDefault, 0};
+}
+
+const TrainTune* train_tune_candidates(int* count) {
+  static const TrainTune c[] = {{256, 8}, {512, 8}, {256, 16}, {512, 16}, {1024, 16}, {512, 32}, {1024, 32}};
+  *count = (int)(sizeof c / sizeof c[0]);
+  return c;
+}
+
+TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTune* tune) {
   TrainPlan p{};
+  const TrainTune tn = tune ? *tune : get_train_tune(m, f16);
+  const int chunk = tn.chunk > 0 ? tn.chunk : kChunkDefault;
   int tmax = 8, per_cu = 1;
 #define NTC_X(a_, b, cc, h)                                                                          \
   if (m.c0 == a_ && m.c1 == b && m.channels == cc && m.hidden == h) {                                \
@@ -1018,8 +1096,11 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
   }
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
+  if (tn.tile > 0) tmax = std::min(tmax, tn.tile);  // tile sides at most the kernel's capacity
   TileGeom& tg = p.tg;
   std::memset(&tg, 0, sizeof tg);
+  tg.chunk = chunk;
+  p.tune = TrainTune{chunk, tmax};
   int nb = 0, nt = 0, rmax = 0;
   for (int j = 0; j < m.num_levels; ++j) {
     const int T = std::min(tmax, std::min(m.g0_w[j], m.g0_h[j]));
@@ -1048,8 +1129,8 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n) {
   p.ntiles = nt;
   p.nbb = (int)std::max<long long>(1, std::min<long long>(256, (n + kBinBlockSamples - 1) / kBinBlockSamples));
   p.per_bin_block = (int)((n + p.nbb - 1) / p.nbb);
-  p.max_items = nt + (4 * n + kChunk - 1) / kChunk;
-  const long long work_items = std::max<long long>(p.max_items, (n + kChunk - 1) / kChunk);
+  p.max_items = nt + (4 * n + chunk - 1) / chunk;
+  const long long work_items = std::max<long long>(p.max_items, (n + chunk - 1) / chunk);
   p.grid = (int)std::max<long long>(1, std::min<long long>(work_items, (long long)device_cus() * per_cu));
   const size_t P = (size_t)m.mlp_params;
   size_t o = 0;
@@ -1149,6 +1230,12 @@ hipError_t launch_adam(const ntc_material& m, const AdamLaunch& a, hipStream_t s
     hipLaunchKernelGGL(adam_kernel<_Float16>, dim3(grid), dim3(256), 0, s, dev_mat(m), args);
   else
     hipLaunchKernelGGL(adam_kernel<float>, dim3(grid), dim3(256), 0, s, dev_mat(m), args);
+  if (a.step_dev && a.advance) hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, s, a.step_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int* step_dev, hipStream_t s) {
+  hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, s, step_dev);
   return hipGetLastError();
 }
 

@@ -54,7 +54,12 @@ class HParams(C.Structure):
         ("lr_latent", C.c_float), ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
         ("eps", C.c_float), ("noise_seed", C.c_uint64), ("step", C.c_int32), ("precision", C.c_int32),
         ("noise", C.c_int32), ("freeze_latents", C.c_int32), ("scale_growth_interval", C.c_int32),
+        ("step_dev", C.c_void_p), ("lr_dev", C.c_void_p),
     ]
+
+
+class TrainTuning(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("tile", C.c_int32), ("microseconds", C.c_double)]
 
 
 _P = C.POINTER
@@ -86,6 +91,13 @@ _sig = {
                                C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "ntc_decode_tile": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]),
+    "ntc_train_autotune": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p, _P(HParams),
+                                     C.c_void_p, C.c_size_t, C.c_void_p, _P(TrainTuning)]),
+    "ntc_train_workspace_bytes_batched": (C.c_size_t, [_P(Material), C.c_int32, _P(C.c_int64), C.c_int]),
+    "ntc_train_step_batched": (C.c_int, [_P(Material), C.c_int32, _P(TrainStateC), C.c_void_p, _P(C.c_int64),
+                                         _P(C.c_void_p), _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_decode_batched": (C.c_int, [_P(Material), C.c_int32, _P(C.c_void_p), _P(C.c_void_p), C.c_int, C.c_void_p,
+                                     _P(C.c_int64), C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_timing_begin": (C.c_int, [C.c_int32]),
     "ntc_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "ntc_timing_end": (C.c_int, []),
@@ -223,12 +235,63 @@ def backward(m: Material, latents, mlp, mlp_train_packed, precision, queries, n,
 
 
 def hparams(lr_latent=0.01, lr_mlp=0.005, step=0, precision=F32, noise=True, freeze=False, seed=0,
-            beta1=0.9, beta2=0.999, eps=1e-8, growth=2000) -> HParams:
+            beta1=0.9, beta2=0.999, eps=1e-8, growth=2000, step_dev=None, lr_dev=None) -> HParams:
+    """step_dev: int32 device tensor (1 element) holding the step index for graph
+    replay; lr_dev: float32 device tensor (latent lr, MLP lr).  Both optional."""
     hp = HParams()
     hp.lr_latent, hp.lr_mlp, hp.beta1, hp.beta2, hp.eps = lr_latent, lr_mlp, beta1, beta2, eps
     hp.noise_seed, hp.step, hp.precision = seed, step, precision
     hp.noise, hp.freeze_latents, hp.scale_growth_interval = int(noise), int(freeze), growth
+    hp.step_dev = _ptr(step_dev) if step_dev is not None else None
+    hp.lr_dev = _ptr(lr_dev) if lr_dev is not None else None
     return hp
+
+
+def train_autotune(m: Material, state: "TrainState", queries, n, targets, hp: HParams, workspace, stream=None):
+    """Pick the fastest (samples per work item, tile side) for this material's shape; returns
+    (chunk, tile, microseconds per gradient pass)."""
+    t = TrainTuning()
+    _check(_lib.ntc_train_autotune(C.byref(m), C.byref(state.c), _ptr(queries), n, _ptr(targets), C.byref(hp),
+                                   _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream),
+                                   C.byref(t)), "ntc_train_autotune")
+    return t.chunk, t.tile, t.microseconds
+
+
+def _materials(mats):
+    arr = (Material * len(mats))()
+    for i, m in enumerate(mats):
+        arr[i] = m
+    return arr
+
+
+def train_workspace_bytes_batched(mats, offsets, precision=F32) -> int:
+    off = (C.c_int64 * len(offsets))(*[int(o) for o in offsets])
+    return int(_lib.ntc_train_workspace_bytes_batched(_materials(mats), len(mats), off, precision))
+
+
+def train_step_batched(mats, states, queries, offsets, targets, hp: HParams, workspace, stream=None):
+    """One training step of every material; queries grouped per material by offsets
+    (len(mats) + 1, host); targets: one device tensor per material."""
+    n = len(mats)
+    st = (TrainStateC * n)()
+    for i, s in enumerate(states):
+        st[i] = s.c
+    off = (C.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    tg = (C.c_void_p * n)(*[_ptr(t) for t in targets])
+    _check(_lib.ntc_train_step_batched(_materials(mats), n, st, _ptr(queries), off, tg, C.byref(hp), _ptr(workspace),
+                                       workspace.numel() * workspace.element_size(), _stream(stream)),
+           "ntc_train_step_batched")
+
+
+def decode_batched(mats, packed, wpacks, precision, queries, offsets, out, out_dtype, stream=None):
+    """Decode the query groups of every material into one output buffer: material i's
+    n_i x C_i values follow those of materials < i."""
+    n = len(mats)
+    off = (C.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    pk = (C.c_void_p * n)(*[_ptr(p) for p in packed])
+    wp = (C.c_void_p * n)(*[_ptr(w) for w in wpacks])
+    _check(_lib.ntc_decode_batched(_materials(mats), n, pk, wp, precision, _ptr(queries), off, _ptr(out), out_dtype,
+                                   _stream(stream)), "ntc_decode_batched")
 
 
 class TrainState:

@@ -1,0 +1,205 @@
+"""Many materials in one call (uneven sizes, channel counts, MLP widths), HIP-graph
+replay of a training step, and the training-step tuner.  The per-material path these
+calls run is pinned to the FP64 oracle by test_gpu_train / test_gpu_decode; here the
+batched and replayed results are compared with that per-material path, and one
+material's loss with the oracle."""
+import numpy as np
+import pytest
+
+from _helpers import geometry, mlp_in_unit_range, queries_dev, quantized_latents_oracle, to_dev
+from oracle import ntc_oracle as O
+from paper_2305_17105_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # W, C (= c0 = c1), hidden, samples
+    (256, 8, 32, 3000),
+    (512, 12, 64, 9001),
+    (256, 16, 64, 4097),
+]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_17105_amd import ntc
+    return ntc
+
+
+def _material(lib, W, C, hd, seed):
+    import torch
+    m = lib.material_init(W, W, C, C, C, 4, 4, hd)
+    raw = synth.uniform_latents(seed, int(m.latent_count))
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    lib.quantize_latents(m, to_dev(raw), packed)
+    lat = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+    lib.dequantize_latents(m, packed, lat)
+    mlp = synth.xavier_mlp(seed, int(m.input_width), hd, C)
+    _, tflat = synth.target_chain(seed, 0, W, W, C, int(m.num_mips))
+    return m, raw, lat, mlp, to_dev(tflat), tflat
+
+
+def _states(lib, mats, prec):
+    out = []
+    for m, raw, lat, mlp, td, _ in mats:
+        out.append(lib.TrainState(m, lat, to_dev(mlp), prec))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_batched_train_equals_per_material(lib, prec):
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    mats = [_material(lib, W, C, hd, 40 + i) for i, (W, C, hd, _) in enumerate(SHAPES)]
+    ns = [n for (_, _, _, n) in SHAPES]
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    qs = [synth.random_queries(50 + i, n, int(mats[i][0].num_mips)) for i, n in enumerate(ns)]
+    qall = queries_dev(np.concatenate(qs))
+    ms = [x[0] for x in mats]
+    # batched: two steps
+    sb = _states(lib, mats, P)
+    wsb = torch.zeros(lib.train_workspace_bytes_batched(ms, offsets, P), dtype=torch.uint8, device="cuda")
+    for step in range(2):
+        hp = lib.hparams(precision=P, step=step, lr_latent=0.01, lr_mlp=0.005, seed=3)
+        if step == 0:
+            for m, s in zip(ms, sb):
+                lib.train_prepare(m, s, hp)
+        lib.train_step_batched(ms, sb, qall, offsets, [x[4] for x in mats], hp, wsb)
+    # one material at a time
+    si = _states(lib, mats, P)
+    for i, (m, s) in enumerate(zip(ms, si)):
+        ws = torch.zeros(lib.train_workspace_bytes(m, ns[i], P), dtype=torch.uint8, device="cuda")
+        qd = queries_dev(qs[i])
+        for step in range(2):
+            hp = lib.hparams(precision=P, step=step, lr_latent=0.01, lr_mlp=0.005, seed=3)
+            if step == 0:
+                lib.train_prepare(m, s, hp)
+            lib.train_step(m, s, qd, ns[i], mats[i][4], hp, ws)
+    torch.cuda.synchronize()
+    for i in range(len(ms)):
+        for name in ("latents", "mlp", "lat_m", "mlp_v", "loss"):
+            a = getattr(sb[i], name).cpu().numpy().astype(np.float64)
+            b = getattr(si[i], name).cpu().numpy().astype(np.float64)
+            err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30)
+            assert err <= 1e-5, (i, name, err)
+    # the first step's loss of one material against the oracle (masters at step 0)
+    m0, raw0, _, mlp0, _, tflat0 = mats[1]
+    g = geometry(m0)
+    lat_fwd = quantized_latents_oracle(g, raw0) + O.noise_values(g, 3, 0)
+    L, _, _, _ = O.loss_and_grads(g, lat_fwd, mlp0.astype(np.float64), qs[1], tflat0)
+    si2 = _states(lib, [mats[1]], P)[0]
+    ws = torch.zeros(lib.train_workspace_bytes(m0, ns[1], P), dtype=torch.uint8, device="cuda")
+    hp = lib.hparams(precision=P, step=0, lr_latent=0.0, lr_mlp=0.0, seed=3)
+    lib.train_prepare(m0, si2, hp)
+    lib.train_step_batched([m0], [si2], queries_dev(qs[1]), [0, ns[1]], [mats[1][4]], hp, ws)
+    torch.cuda.synchronize()
+    got = float(si2.loss.cpu()[0])
+    print(f"batched {prec}: loss {got:.7e} vs oracle {L:.7e}")
+    assert abs(got - L) / L <= (1e-5 if prec == "f32" else 2e-3)
+
+
+@pytest.mark.parametrize("prec", ["f16", "fp8", "f32"])
+def test_batched_decode_equals_per_material(lib, prec):
+    import torch
+    P = {"f32": lib.F32, "f16": lib.F16, "fp8": lib.FP8_E4M3}[prec]
+    shapes = [(256, 8, 8, 4, 4, 64, 1000), (512, 16, 16, 2, 4, 64, 3001), (256, 16, 16, 4, 4, 32, 77)]
+    ms, pk, wp, qs, ns = [], [], [], [], []
+    for i, (W, C, c0, b0, b1, hd, n) in enumerate(shapes):
+        m = lib.material_init(W, W, C, c0, c0, b0, b1, hd)
+        raw = synth.uniform_latents(60 + i, int(m.latent_count))
+        p = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        lib.quantize_latents(m, to_dev(raw), p)
+        mlp = mlp_in_unit_range(60 + i, int(m.input_width), hd, C)
+        w = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+        lib.pack_mlp(m, to_dev(mlp), P, w)
+        ms.append(m); pk.append(p); wp.append(w); ns.append(n)
+        qs.append(synth.random_queries(70 + i, n, int(m.num_mips)))
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    total = sum(n * m.channels for n, m in zip(ns, ms))
+    out = torch.full((total,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode_batched(ms, pk, wp, P, queries_dev(np.concatenate(qs)), offsets, out, lib.F32)
+    o = 0
+    for i, m in enumerate(ms):
+        ref = torch.full((ns[i] * m.channels,), float("nan"), dtype=torch.float32, device="cuda")
+        lib.decode(m, pk[i], wp[i], P, queries_dev(qs[i]), ns[i], ref, lib.F32)
+        torch.cuda.synchronize()
+        assert torch.equal(out[o:o + ns[i] * m.channels], ref), i
+        o += ns[i] * m.channels
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_graph_replay_matches_eager(lib, prec):
+    """One captured training step (device step index and learning rates) replayed four
+    times, with eager work and synchronization between replays; every replay matches
+    the eager step with the same index."""
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    W, C, hd, n = 512, 12, 64, 9001
+    mat = _material(lib, W, C, hd, 81)
+    m, _, lat, mlp, td, _ = mat
+    q = queries_dev(synth.random_queries(82, n, int(m.num_mips)))
+    lr = [(0.01 * (1 - 0.1 * s), 0.005 * (1 - 0.1 * s)) for s in range(4)]
+    # eager reference
+    se = lib.TrainState(m, lat, to_dev(mlp), P)
+    wse = torch.zeros(lib.train_workspace_bytes(m, n, P), dtype=torch.uint8, device="cuda")
+    ref = []
+    for s in range(4):
+        hp = lib.hparams(precision=P, step=s, lr_latent=lr[s][0], lr_mlp=lr[s][1], seed=5)
+        if s == 0:
+            lib.train_prepare(m, se, hp)
+        lib.train_step(m, se, q, n, td, hp, wse)
+        torch.cuda.synchronize()
+        ref.append({k: getattr(se, k).clone() for k in ("latents", "latents_fwd", "mlp", "loss")})
+    # captured step
+    sg = lib.TrainState(m, lat, to_dev(mlp), P)
+    wsg = torch.zeros_like(wse)
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr_dev = torch.tensor(lr[0], dtype=torch.float32, device="cuda")
+    hp = lib.hparams(precision=P, step=0, seed=5, step_dev=step_dev, lr_dev=lr_dev)
+    lib.train_prepare(m, sg, hp)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            lib.train_step(m, sg, q, n, td, hp, wsg)
+    torch.cuda.synchronize()
+    assert int(step_dev.item()) == 0  # capture does not run the step
+    for s in range(4):
+        lr_dev.copy_(torch.tensor(lr[s], dtype=torch.float32))
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1024, device="cuda").sum().item()  # eager work between replays
+        assert int(step_dev.item()) == s + 1
+        for k, v in ref[s].items():
+            a = getattr(sg, k).double()
+            err = float((a - v.double()).abs().max()) / max(float(v.double().abs().max()), 1e-30)
+            assert err <= 1e-5, (s, k, err)
+
+
+def test_autotune_picks_a_candidate_and_training_still_matches(lib):
+    import torch
+    W, C, hd, n = 512, 12, 64, 20011
+    m, _, lat, mlp, td, _ = _material(lib, W, C, hd, 91)
+    q = queries_dev(synth.random_queries(92, n, int(m.num_mips)))
+    s0 = lib.TrainState(m, lat, to_dev(mlp), lib.F16)
+    ws = torch.zeros(lib.train_workspace_bytes(m, n, lib.F16), dtype=torch.uint8, device="cuda")
+    hp = lib.hparams(precision=lib.F16, step=0, seed=7)
+    lib.train_prepare(m, s0, hp)
+    lib.train_step(m, s0, q, n, td, hp, ws)  # default plan
+    torch.cuda.synchronize()
+    s1 = lib.TrainState(m, lat, to_dev(mlp), lib.F16)
+    lib.train_prepare(m, s1, hp)
+    chunk, tile, us = lib.train_autotune(m, s1, q, n, td, hp, ws)
+    print(f"tuned: chunk {chunk}, tile {tile}, {us:.1f} us per gradient pass")
+    assert chunk in (256, 512, 1024) and tile in (8, 16, 32) and us > 0
+    lib.train_prepare(m, s1, hp)
+    lib.train_step(m, s1, q, n, td, hp, ws)  # tuned plan
+    torch.cuda.synchronize()
+    # another work split sums the FP32 weight-gradient partials in another order; Adam's
+    # normalised step turns that rounding into up to ~lr * 1e-2 on near-zero gradients
+    for k in ("latents", "mlp", "loss"):
+        a, b = getattr(s1, k).double(), getattr(s0, k).double()
+        err = float((a - b).abs().max()) / max(float(b.abs().max()), 1e-30)
+        assert err <= 1e-4, (k, err)

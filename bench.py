@@ -247,6 +247,148 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
     return res
 
 
+BATCH = dict(materials=64, samples=4 * 2 ** 20, steps=20, warmup=3, decode_queries=4 * 2 ** 20)
+
+
+def batched_materials(seed=7, count=64):
+    """Seeded uneven material set: side 2^9..2^12 (log-uniform), C in {8, 10, 12, 16}
+    with C0 = C1 = C at 4 bits, hidden width 32 or 64."""
+    r = np.random.Generator(np.random.PCG64([seed, 505]))
+    sides = 2 ** r.integers(9, 13, count)
+    chans = r.choice([8, 10, 12, 16], count)
+    widths = r.choice([32, 64], count)
+    return [(int(w), int(c), int(h)) for w, c, h in zip(sides, chans, widths)]
+
+
+def run_batched(ntc, synth, torch, steps, warmup, seed=7):
+    """Many-material workload: every material trained (FP16 matrix cores) in one batched
+    step captured in a HIP graph and replayed, samples per material proportional to its
+    area; then decoded in one batched call (queries proportional to area) and through
+    the coherent rectangle entry point (all of mip 0).  Tile shapes per (hidden width,
+    channels) come from the step tuner."""
+    b = BATCH
+    spec = batched_materials(seed, b["materials"])
+    t0 = time.time()
+    mats, states, targets, nsamp = [], [], [], []
+    area = np.array([w * w for w, _, _ in spec], dtype=np.float64)
+    shares = np.maximum(1, np.floor(b["samples"] * area / area.sum())).astype(np.int64)
+    for i, (w, c, hd) in enumerate(spec):
+        m = ntc.material_init(w, w, c, c, c, 4, 4, hd)
+        raw = torch.from_numpy(synth.uniform_latents(seed * 1000 + i, int(m.latent_count))).cuda()
+        packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        ntc.quantize_latents(m, raw, packed)
+        lat = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+        ntc.dequantize_latents(m, packed, lat)
+        mlp = torch.from_numpy(synth.xavier_mlp(seed * 1000 + i, m.input_width, hd, c)).cuda()
+        mats.append(m)
+        states.append(ntc.TrainState(m, lat, mlp, ntc.F16))
+        targets.append(synth.target_chain_torch(seed, 100 + i, w, w, c, int(m.num_mips), "cuda"))
+        nsamp.append(int(shares[i]))
+    offsets = np.concatenate([[0], np.cumsum(nsamp)])
+    ntot = int(offsets[-1])
+    qpool = []
+    for k in range(2):
+        qs = [synth.random_queries(seed * 7919 + 31 * i + k, n, int(m.num_mips)) for i, (m, n) in
+              enumerate(zip(mats, nsamp))]
+        qpool.append(torch.from_numpy(np.concatenate(qs).view(np.uint8).copy()).cuda())
+    ws = torch.zeros(ntc.train_workspace_bytes_batched(mats, offsets, ntc.F16), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench] batched: {len(mats)} materials, {int(area.sum())} mip-0 texels, "
+        f"{sum(int(m.latent_count) for m in mats)} latents, {ntot} samples/step, set-up {time.time() - t0:.1f}s")
+
+    # tuner: one representative (the largest) material per (hidden width, channels)
+    tuned = {}
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr_dev = torch.tensor([TRAIN["lr_lat"], TRAIN["lr_mlp"]], dtype=torch.float32, device="cuda")
+    hp = ntc.hparams(precision=ntc.F16, step=0, seed=11, noise=True, step_dev=step_dev, lr_dev=lr_dev)
+    hp_host = ntc.hparams(precision=ntc.F16, step=0, seed=11, noise=True)
+    for m, st in zip(mats, states):
+        ntc.train_prepare(m, st, hp_host)
+    for key in sorted({(m.hidden, m.channels) for m in mats}):
+        i = max((j for j, m in enumerate(mats) if (m.hidden, m.channels) == key), key=lambda j: mats[j].width)
+        n = nsamp[i]
+        wsi = torch.zeros(ntc.train_workspace_bytes(mats[i], n, ntc.F16), dtype=torch.uint8, device="cuda")
+        qi = qpool[0][offsets[i] * 12:offsets[i + 1] * 12]
+        chunk, tile, us = ntc.train_autotune(mats[i], states[i], qi, n, targets[i], hp_host, wsi)
+        tuned[f"hidden{key[0]}_c{key[1]}"] = dict(chunk=chunk, tile=tile, us_per_gradient_pass=round(us, 1),
+                                                  tuned_on=f"{mats[i].width}^2, {n} samples")
+        del wsi
+    for m, st in zip(mats, states):
+        ntc.train_prepare(m, st, hp_host)
+    log(f"[bench] batched: tuned tiles {tuned}")
+
+    # eager batched steps, then one captured step replayed
+    for s in range(warmup):
+        ntc.train_step_batched(mats, states, qpool[s % 2], offsets, targets, hp, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(steps):
+        ntc.train_step_batched(mats, states, qpool[s % 2], offsets, targets, hp, ws)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t1) / steps * 1e3
+    graphs = []
+    stream = torch.cuda.Stream()
+    for k in range(2):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            with torch.cuda.graph(g, stream=stream):
+                ntc.train_step_batched(mats, states, qpool[k], offsets, targets, hp, ws)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    graphs[0].replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(steps):
+        graphs[s % 2].replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t1) / steps * 1e3
+    loss = float(np.mean([float(st.loss.cpu()[0]) for st in states]))
+    log(f"[bench] batched train: eager {eager_ms:.3f} ms/step, graph replay {graph_ms:.3f} ms/step -> "
+        f"{ntot / (graph_ms * 1e-3):.3e} samples/s, mean loss {loss:.5f}, step index {int(step_dev.item())}")
+    del graphs, ws
+
+    # decode: random queries proportional to area in one batched call; coherent mip 0
+    packed, wpacks = [], []
+    for m, st in zip(mats, states):
+        p = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        ntc.quantize_latents(m, st.latents, p)
+        w = torch.zeros(ntc.mlp_packed_bytes(m, ntc.F16), dtype=torch.uint8, device="cuda")
+        ntc.pack_mlp(m, st.mlp, ntc.F16, w)
+        packed.append(p)
+        wpacks.append(w)
+    dq = np.maximum(1, np.floor(b["decode_queries"] * area / area.sum())).astype(np.int64)
+    doff = np.concatenate([[0], np.cumsum(dq)])
+    qd = torch.from_numpy(np.concatenate([synth.random_queries(seed * 31 + i, int(n), int(m.num_mips)) for i, (m, n)
+                                          in enumerate(zip(mats, dq))]).view(np.uint8).copy()).cuda()
+    out = torch.empty(int(sum(int(n) * m.channels for n, m in zip(dq, mats))), dtype=torch.float16, device="cuda")
+    for _ in range(2):
+        ntc.decode_batched(mats, packed, wpacks, ntc.F16, qd, doff, out, ntc.F16)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        ntc.decode_batched(mats, packed, wpacks, ntc.F16, qd, doff, out, ntc.F16)
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - t1) / 5 * 1e3
+    nd = int(doff[-1])
+    big = max(int(m.width) ** 2 * m.channels for m in mats)
+    tile_out = torch.empty(big, dtype=torch.float16, device="cuda")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for m, p, w in zip(mats, packed, wpacks):
+        ntc.decode_tile(m, p, w, ntc.F16, 0, 0, 0, m.width, m.height, tile_out, ntc.F16)
+    torch.cuda.synchronize()
+    coh_ms = (time.perf_counter() - t1) * 1e3
+    log(f"[bench] batched decode: {nd} random queries {dec_ms:.3f} ms -> {nd / (dec_ms * 1e-3):.3e} texels/s; "
+        f"coherent mip 0 of all materials ({int(area.sum())} texels) {coh_ms:.3f} ms -> "
+        f"{area.sum() / (coh_ms * 1e-3):.3e} texels/s")
+    return dict(materials=len(mats), mip0_texels=int(area.sum()), samples_per_step=ntot,
+                train_ms_per_step_graph=round(graph_ms, 4), train_ms_per_step_eager=round(eager_ms, 4),
+                train_samples_per_s=ntot / (graph_ms * 1e-3), mean_loss=loss, tuned_tiles=tuned,
+                decode_random=dict(queries=nd, ms=round(dec_ms, 4), texels_per_s=nd / (dec_ms * 1e-3)),
+                decode_coherent_mip0=dict(texels=int(area.sum()), ms=round(coh_ms, 4),
+                                          texels_per_s=float(area.sum() / (coh_ms * 1e-3))))
+
+
 def cpu_baseline():
     """FP64 oracle on the host: one training step of the same material, gradient part
     on 32,768 of the 262,144 samples, dense per-latent part (noise, Adam, clamp) on all
@@ -302,6 +444,7 @@ def main():
     ap.add_argument("--decode-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -337,6 +480,10 @@ def main():
     if not args.no_decode:
         decode = run_decode(ntc, synth, torch, args.decode_queries, args.decode_reps)
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(ntc, synth, torch, BATCH["steps"], BATCH["warmup"])
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
@@ -359,6 +506,7 @@ def main():
                  "fused_tflops": round(ach32, 2), "fused_frac_of_fp32_peak": round(ach32 / PEAK_F32_TFLOPS, 4)},
         "fused_ms_f16": round(r16["fused_ms"], 4),
         "decode": decode,
+        "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

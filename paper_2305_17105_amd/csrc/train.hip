@@ -32,7 +32,7 @@
 
 namespace ntc {
 
-constexpr int kChunkDefault = 512;  // samples per work item unless tuned
+constexpr int kChunkDefault = 256;  // samples per work item unless tuned (the tuner picked 256 on every shape)
 constexpr int kBinBlockSamples = 1024;
 constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
 constexpr int kSortedCells = 4096; // levels with at most this many G0 cells are sorted by anchor cell

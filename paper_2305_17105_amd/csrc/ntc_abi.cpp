@@ -312,7 +312,9 @@ size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype pre
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden)) return 0;
   // large enough for every tuning candidate, so a tuned plan always fits
   const bool f16 = precision == NTC_F16;
-  size_t total = train_plan(*m, f16, n).total;
+  const TrainPlan base = train_plan(*m, f16, n);
+  if (!base.supported_bins) return 0;  // more latent tiles than the binning kernels hold
+  size_t total = base.total;
   int nc = 0;
   const TrainTune* c = train_tune_candidates(&nc);
   for (int i = 0; i < nc; ++i) total = std::max(total, train_plan(*m, f16, n, &c[i]).total);

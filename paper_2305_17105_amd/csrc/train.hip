@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ntc_internal.h"
@@ -165,13 +166,19 @@ struct TrainCfg {
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
   static constexpr int kLdsCap = 160 * 1024 / BPC;
   static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
-  // one-phase staging when it fits next to a tile of at least 16 x 16 cells
+  // one-phase staging only when it fits next to a 16 x 16 tile of FP64 accumulators:
+  // fast accumulators matter more than fewer barriers
   static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
+  // owned-latent accumulators in FP64 when a 16 x 16 tile of them fits (LDS FP32
+  // atomic adds run ~8x slower than FP64 ones on this GPU), else FP32
+  static constexpr bool REG64 = OFF_REG + region(16) * 8 <= kLdsCap;
+  using RegT = typename std::conditional<REG64, double, float>::type;
+  static constexpr int RB = REG64 ? 8 : 4;
   // largest tile side whose owned-latent gradient fits next to the rest
-  static constexpr int TMAX = OFF_REG + region(32) * 8 <= kLdsCap ? 32 : OFF_REG + region(16) * 8 <= kLdsCap ? 16 : 8;
-  static constexpr int LDS = OFF_REG + region(TMAX) * 8;
+  static constexpr int TMAX = OFF_REG + region(32) * RB <= kLdsCap ? 32 : OFF_REG + region(16) * RB <= kLdsCap ? 16 : 8;
+  static constexpr int LDS = OFF_REG + region(TMAX) * RB;
 };
 
 template <typename T, int C0, int C1, int C, int HD, int ACT>
@@ -190,9 +197,8 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   long long* tab = reinterpret_cast<long long*>(smem + Cfg::OFF_TAB);
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
-  // owned-latent gradient accumulators: FP64, because LDS FP32 atomic adds run ~8x
-  // slower than FP64 ones on this GPU (and ~25x slower than integer ones)
-  double* reg = reinterpret_cast<double*>(smem + Cfg::OFF_REG);
+  using RegT = typename Cfg::RegT;
+  RegT* reg = reinterpret_cast<RegT*>(smem + Cfg::OFF_REG);
 
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
@@ -254,7 +260,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
     const int R0 = T_ * T_ * C0;
     const int RG = R0 + T1 * T1 * C1;
     if (a.binned)
-      for (int k = tid; k < RG; k += NTHR) reg[k] = 0.0;
+      for (int k = tid; k < RG; k += NTHR) reg[k] = (RegT)0;
     __syncthreads();
 
     // the list entry (query + sample index) of one NCOL-sample step; the next step's
@@ -413,7 +419,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
         const int rr = lane & 15;
         const bool own0 = valid && (f.g0x >> ts) == tx && (f.g0y >> ts) == ty;
         const int key0 = own0 ? ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) : -1;
-        double* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
+        RegT* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
         if (sorted) {
           const int rk = __shfl(key0, lane & ~15);
           const unsigned long long bal = __ballot(key0 == rk || !valid);
@@ -422,21 +428,21 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
           for (int t = 0; t < C0; ++t) {
             const float sv = row_sum16(own0 ? dx[t] : 0.f);
             if (uni) {
-              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, (double)sv);
+              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, (RegT)sv);
             } else if (own0) {
-              atomicAdd(dst0 + t, (double)dx[t]);
+              atomicAdd(dst0 + t, (RegT)dx[t]);
             }
           }
         } else if (own0) {
 #pragma unroll
-          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, (double)dx[t]);
+          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, (RegT)dx[t]);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
           const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
           const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
-          double* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
+          RegT* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
           if (sorted) {
             const int rk = __shfl(key1, lane & ~15);
             const unsigned long long bal = __ballot(key1 == rk || !valid);
@@ -448,9 +454,9 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
               const float sv = row_sum16(v1);
               if (ch < C1) {
                 if (uni) {
-                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, (double)sv);
+                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, (RegT)sv);
                 } else if (own1) {
-                  atomicAdd(dst1 + ch, (double)v1);
+                  atomicAdd(dst1 + ch, (RegT)v1);
                 }
               }
             }
@@ -458,7 +464,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
 #pragma unroll
             for (int i = 0; i < IS::n1max; ++i) {
               const int ch = g + 4 * i;
-              if (ch < C1) atomicAdd(dst1 + ch, (double)(f.g1_w[k] * dx[C0 + i]));
+              if (ch < C1) atomicAdd(dst1 + ch, (RegT)(f.g1_w[k] * dx[C0 + i]));
             }
           }
         }

@@ -115,3 +115,11 @@ def test_decode_tile_rejects_bad_rectangles(ntc):
     assert call(0, 0, 0, 4, 4, out=None) == ntc.E_INVALID  # NULL output
     assert lib.ntc_decode_tile(ctypes.byref(m), fake, fake, 9, 0, 0, 0, 1, 1, fake, ntc.F16, None) == \
         ntc.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("W,C,hd", [(4096, 16, 64), (4096, 12, 64), (4096, 8, 32), (2048, 12, 64)])
+def test_training_plans_fit_large_materials(ntc, W, C, hd):
+    """Plans (tile sizes, bin counts, workspace) exist for 4096^2 materials in both precisions."""
+    m = ntc.material_init(W, W, C, C, C, 4, 4, hd)
+    for prec in (ntc.F32, ntc.F16):
+        assert ntc.train_workspace_bytes(m, 262144, prec) > 0

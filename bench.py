@@ -142,6 +142,41 @@ class TrainBench:
         return dict(seconds=dt, ms_per_step=dt / steps * 1e3, samples_per_s=n * steps / dt, fused_ms=fused_ms,
                     loss=loss, state=st)
 
+    def run_paper_schedule(self, precision, steps, seed=3):
+        """The paper's optimiser schedule (section 5.1) on this material: batches of eight
+        256^2 crops from one LOD (exponential LOD distribution, 5% uniform) generated on
+        the device, cosine-annealed learning rates 0.01 / 0.005, noise on; at 95% of the
+        steps the latents are quantized and frozen and the network alone trains on."""
+        ntc, torch = self.ntc, self.torch
+        m = self.m
+        n = 8 * 256 * 256
+        st = ntc.TrainState(m, self.lat0, self.mlp0, precision)
+        ws = torch.zeros(ntc.train_workspace_bytes(m, n, precision), dtype=torch.uint8, device="cuda")
+        qbuf = torch.zeros(n * 12, dtype=torch.uint8, device="cuda")
+        freeze_at = int(0.95 * steps)
+        packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+
+        def hp(step, frozen):
+            c = 0.5 * (1.0 + math.cos(math.pi * step / steps))
+            return ntc.hparams(lr_latent=TRAIN["lr_lat"] * c, lr_mlp=TRAIN["lr_mlp"] * c, step=step,
+                               precision=precision, noise=not frozen, freeze=frozen, seed=seed)
+
+        ntc.train_prepare(m, st, hp(0, False))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            frozen = s >= freeze_at
+            if s == freeze_at:  # quantize-and-freeze: masters become the dequantized codes
+                ntc.quantize_latents(m, st.latents, packed)
+                ntc.dequantize_latents(m, packed, st.latents)
+                ntc.train_prepare(m, st, hp(s, True))
+            ntc.crop_queries(m, seed, s, qbuf)
+            ntc.train_step(m, st, qbuf, n, self.targets, hp(s, frozen), ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dict(steps=steps, frozen_from=freeze_at, samples_per_step=n, ms_per_step=dt / steps * 1e3,
+                    samples_per_s=n * steps / dt, psnr_db=self.psnr(st), loss=float(st.loss.cpu()[0]))
+
     def psnr(self, st):
         """Eq. 1 over the full mip chain, decoding the quantized latents in FP32."""
         ntc, torch = self.ntc, self.torch
@@ -445,6 +480,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-paper-schedule", action="store_true")
+    ap.add_argument("--paper-steps", type=int, default=1000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -467,6 +504,13 @@ def main():
     log(f"[bench] f16: {r16['ms_per_step']:.3f} ms/step, fused {r16['fused_ms']:.3f} ms, loss {r16['loss']:.5f}")
     psnr16 = tb.psnr(r16.pop("state"))
     log(f"[bench] PSNR after {args.warmup + args.steps} steps: f16 {psnr16:.2f} dB, f32 {psnr32:.2f} dB")
+
+    paper = None
+    if not args.no_paper_schedule:
+        paper = tb.run_paper_schedule(ntc.F16, args.paper_steps)
+        log(f"[bench] paper schedule f16 ({paper['steps']} steps of 8 x 256^2 crops, frozen from "
+            f"{paper['frozen_from']}): {paper['ms_per_step']:.3f} ms/step -> {paper['samples_per_s']:.3e} samples/s, "
+            f"PSNR {paper['psnr_db']:.2f} dB")
 
     m = tb.m
     fps = train_flops_per_sample(m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1)
@@ -505,6 +549,7 @@ def main():
                  "ms_per_step": round(r32["ms_per_step"], 4), "fused_ms": round(r32["fused_ms"], 4),
                  "fused_tflops": round(ach32, 2), "fused_frac_of_fp32_peak": round(ach32 / PEAK_F32_TFLOPS, 4)},
         "fused_ms_f16": round(r16["fused_ms"], 4),
+        "paper_schedule_f16": paper,
         "decode": decode,
         "batched": batched,
         "roofline": roof,

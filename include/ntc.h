@@ -306,6 +306,21 @@ ntc_status ntc_backward(const ntc_material* m, const float* latents, const float
                         float* grad_latents, float* grad_mlp, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * One training batch as in section 5.1: `crops` crops of side x side texels, all from
+ * one level of detail, LOD = floor(-log4 X) with X ~ U(0, 1] (clamped to the chain),
+ * or uniform over the chain for a `uniform_fraction` of the batches.  The random
+ * numbers are SplitMix64 outputs of counters derived from (seed, step): key =
+ * mix(mix(seed ^ 0x63726F70) + gamma (step + 1)), r_i = mix(key + gamma (i + 1));
+ * X = 1 - (r_0 >> 11) 2^-53; uniform batch when (r_1 >> 11) 2^-53 < uniform_fraction,
+ * LOD = r_2 mod num_mips; crop c starts at (r_(3+2c) mod (W_l - side + 1),
+ * r_(4+2c) mod (H_l - side + 1)); on mips smaller than the crop it starts at 0 and
+ * wraps around.  out: crops * side^2 queries at texel centres, crop-major, row-major
+ * within a crop (caller-owned device memory).
+ */
+ntc_status ntc_crop_queries(const ntc_material* m, uint64_t seed, int32_t step, int32_t crops, int32_t side,
+                            double uniform_fraction, ntc_query* out, void* stream);
+
+/*
  * Many materials (uneven sizes, channel counts and MLP widths, each with its own
  * weights and state) in one call.  Queries are grouped per material: material i
  * owns q[offsets[i] .. offsets[i+1]) (offsets: host, nmat + 1 entries, offsets[0] = 0,

@@ -22,7 +22,7 @@ __all__ = [
     "mlp_param_count", "activation", "activation_grad", "mlp_forward", "decode",
     "loss_and_grads", "adam_update", "train_step", "loss_scale_update", "psnr",
     "storage_bytes_paper", "hard_gelu", "E4M3_MAX", "e4m3_value", "round_e4m3", "fp8_layer_scales",
-    "mlp_forward_fp8", "decode_fp8",
+    "mlp_forward_fp8", "decode_fp8", "crop_lod", "crop_queries",
 ]
 
 GAMMA = 0x9E3779B97F4A7C15
@@ -234,6 +234,58 @@ def noise_values(geom: Geometry, seed: int, step: int):
     r24 = (r >> np.uint64(40)).astype(np.int64)
     q = 1.0 / (2.0 ** latent_bits(geom))
     return (r24 - 2 ** 23).astype(np.float64) * 2.0 ** -24 * q
+
+
+# --------------------------------------------------------------------------------------
+# Training batches (section 5.1): eight random 256 x 256 texel crops from one level of
+# detail per batch; LOD = floor(-log4 X), X ~ U(0, 1], clamped to the chain, except for
+# 5% of the batches, whose LOD is uniform over the chain.  Readings taken: the random
+# numbers are SplitMix64 outputs of counters (key = mix(mix(seed ^ CROP_TAG) + gamma *
+# (step + 1)), r_i = mix(key + gamma * (i + 1))); X = 1 - (r_0 >> 11) * 2^-53; the batch
+# is uniform when (r_1 >> 11) * 2^-53 < fraction, its LOD then r_2 mod M; crop c has
+# origin r_(3+2c) mod (W_l - s + 1), r_(4+2c) mod (H_l - s + 1) for a crop side s <= the
+# mip side; on mips smaller than the crop, the crop starts at 0 and wraps around the
+# mip (the mip is tiled).  Samples are crop-major, row-major within a crop, at texel
+# centres.
+# --------------------------------------------------------------------------------------
+CROP_TAG = 0x63726F70
+
+
+def crop_lod(X, M):
+    """Largest k with X <= 4^-k (that is floor(-log4 X) for X in (0, 1]), at most M - 1;
+    by comparisons with exact powers of four, no logarithm."""
+    k = 0
+    while k + 1 < M and X <= 4.0 ** -(k + 1):
+        k += 1
+    return k
+
+
+def crop_queries(geom: Geometry, seed: int, step: int, crops: int = 8, side: int = 256, fraction: float = 0.05):
+    """Query records of one training batch (QUERY layout: u, v float32; lod int32)."""
+    a = int(splitmix64_mix(np.uint64((seed ^ CROP_TAG) & MASK64)))
+    key = int(splitmix64_mix(np.uint64((a + GAMMA * (step + 1)) & MASK64)))
+
+    def r(i):
+        return int(splitmix64_mix(np.uint64((key + GAMMA * (i + 1)) & MASK64)))
+
+    X = 1.0 - (r(0) >> 11) * 2.0 ** -53
+    if (r(1) >> 11) * 2.0 ** -53 < fraction:
+        lod = r(2) % geom.M
+    else:
+        lod = crop_lod(X, geom.M)
+    Wl, Hl = geom.mip_w[lod], geom.mip_h[lod]
+    q = np.zeros(crops * side * side, dtype=[("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
+    jj, ii = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+    for c in range(crops):
+        x0 = r(3 + 2 * c) % (Wl - side + 1) if Wl >= side else 0
+        y0 = r(4 + 2 * c) % (Hl - side + 1) if Hl >= side else 0
+        x = (x0 + ii.ravel()) % Wl
+        y = (y0 + jj.ravel()) % Hl
+        sl = slice(c * side * side, (c + 1) * side * side)
+        q["u"][sl] = ((x + 0.5) / Wl).astype(np.float32)
+        q["v"][sl] = ((y + 0.5) / Hl).astype(np.float32)
+        q["lod"][sl] = lod
+    return q
 
 
 # --------------------------------------------------------------------------------------

@@ -603,6 +603,19 @@ ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const
   return ntc_train_update(m, s, n, hp, workspace, ws_bytes, stream);
 }
 
+ntc_status ntc_crop_queries(const ntc_material* m, uint64_t seed, int32_t step, int32_t crops, int32_t side,
+                            double uniform_fraction, ntc_query* out, void* stream) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (crops < 1 || side < 1 || side > 32768 || (int64_t)crops * side * side > ((int64_t)1 << 31))
+    return fail(NTC_E_INVALID, "crops and side must be positive, crops * side^2 < 2^31");
+  if (!(uniform_fraction >= 0.0 && uniform_fraction <= 1.0)) return fail(NTC_E_INVALID, "fraction outside [0, 1]");
+  if (step < 0) return fail(NTC_E_INVALID, "step < 0");
+  if (!out) return fail(NTC_E_INVALID, "NULL output");
+  return hip_status(launch_crop_queries(*m, seed, step, crops, side, uniform_fraction, out, (hipStream_t)stream),
+                    "ntc_crop_queries");
+}
+
 // ------------------------------------------------------------------ many materials
 static ntc_status check_batch(const ntc_material* mats, int32_t nmat, const int64_t* offsets) {
   if (!mats || !offsets) return fail(NTC_E_INVALID, "NULL materials or offsets");

@@ -113,6 +113,8 @@ struct AdamLaunch {
   uint64_t seed;        // noise seed (device-step mode derives the key on the device)
   bool advance;         // device-step mode: advance the step index after the update
 };
+hipError_t launch_crop_queries(const ntc_material& m, uint64_t seed, int step, int crops, int side, double fraction,
+                               ntc_query* out, hipStream_t s);
 hipError_t launch_adam(const ntc_material& m, const AdamLaunch& a, hipStream_t s);
 hipError_t launch_step_advance(int* step_dev, hipStream_t s);
 hipError_t launch_prepare(const ntc_material& m, const float* latents, float* latents_fwd, float* lat_grad,

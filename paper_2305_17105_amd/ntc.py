@@ -98,6 +98,8 @@ _sig = {
                                          _P(C.c_void_p), _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
     "ntc_decode_batched": (C.c_int, [_P(Material), C.c_int32, _P(C.c_void_p), _P(C.c_void_p), C.c_int, C.c_void_p,
                                      _P(C.c_int64), C.c_void_p, C.c_int, C.c_void_p]),
+    "ntc_crop_queries": (C.c_int, [_P(Material), C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
+                                   C.c_void_p]),
     "ntc_timing_begin": (C.c_int, [C.c_int32]),
     "ntc_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "ntc_timing_end": (C.c_int, []),
@@ -245,6 +247,12 @@ def hparams(lr_latent=0.01, lr_mlp=0.005, step=0, precision=F32, noise=True, fre
     hp.step_dev = _ptr(step_dev) if step_dev is not None else None
     hp.lr_dev = _ptr(lr_dev) if lr_dev is not None else None
     return hp
+
+
+def crop_queries(m: Material, seed, step, out, crops=8, side=256, uniform_fraction=0.05, stream=None):
+    """Fill `out` (uint8 device tensor of crops*side^2*12 bytes) with one training batch."""
+    _check(_lib.ntc_crop_queries(C.byref(m), seed, step, crops, side, uniform_fraction, _ptr(out), _stream(stream)),
+           "ntc_crop_queries")
 
 
 def train_autotune(m: Material, state: "TrainState", queries, n, targets, hp: HParams, workspace, stream=None):

@@ -261,3 +261,18 @@ def test_full_size_gradients(lib, prec):
     assert abs(loss - L) <= (1e-5 if prec == "f32" else 2e-3) * L
     for k, v in errs.items():
         assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("W,side,crops", [(2048, 256, 8), (64, 32, 3), (256, 100, 2)])
+def test_crop_queries_bit_exact(lib, W, side, crops):
+    """The device batch sampler reproduces the oracle's batches bit for bit, over steps
+    that hit exponential and uniform LODs and mips smaller than the crop."""
+    import torch
+    m = lib.material_init(W, W, 4, 4, 4, 4, 4, 64)
+    g = geometry(m)
+    out = torch.zeros(crops * side * side * 12, dtype=torch.uint8, device="cuda")
+    for step in range(12):
+        lib.crop_queries(m, 77, step, out, crops=crops, side=side, uniform_fraction=0.3)
+        torch.cuda.synchronize()
+        want = O.crop_queries(g, 77, step, crops=crops, side=side, fraction=0.3)
+        assert np.array_equal(out.cpu().numpy(), want.view(np.uint8)), step

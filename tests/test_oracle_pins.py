@@ -319,6 +319,56 @@ def test_fp8_forward_exact_case():
     assert np.max(np.abs(y8b - O.mlp_forward(p2, x, K, Hd, C)[0])) > 0
 
 
+# ---------------------------------------------------------------- training batches (sec 5.1)
+def test_crop_lod_closed_form():
+    """floor(-log4 X) at and around the powers of four, clamped to the chain."""
+    M = 12
+    assert O.crop_lod(1.0, M) == 0
+    assert O.crop_lod(0.25, M) == 1 and O.crop_lod(0.25 + 1e-12, M) == 0
+    assert O.crop_lod(1 / 16, M) == 2 and O.crop_lod(1 / 16 + 1e-12, M) == 1
+    assert O.crop_lod(1e-300, M) == M - 1
+    for X in np.random.default_rng(3).uniform(1e-6, 1, 1000):
+        assert O.crop_lod(X, 40) == int(np.floor(-np.log(X) / np.log(4)))
+
+
+def test_crop_lod_distribution():
+    """Without the uniform batches, P(LOD = k) = 3/4 * 4^-k (the last mip takes the tail)."""
+    g = O.make_geometry(256, 256, 4, 4, 4, 4, 4)          # 9 mips
+    steps = 4000
+    lods = np.array([O.crop_queries(g, 5, s, crops=1, side=1, fraction=0.0)["lod"][0] for s in range(steps)])
+    k = np.arange(g.M)
+    p = 0.75 * 4.0 ** -k
+    p[-1] = 4.0 ** -(g.M - 1)
+    counts = np.bincount(lods, minlength=g.M)
+    big = p * steps >= 5
+    chi2 = float(np.sum((counts[big] - steps * p[big]) ** 2 / (steps * p[big])))
+    assert chi2 < 20.0, (counts, chi2)                   # 5 dof at the 0.1% level ~ 20.5
+    # with fraction 1 every LOD is equally likely
+    lods = np.array([O.crop_queries(g, 6, s, crops=1, side=1, fraction=1.0)["lod"][0] for s in range(2000)])
+    c = np.bincount(lods, minlength=g.M)
+    assert np.all(np.abs(c - 2000 / g.M) < 5 * np.sqrt(2000 / g.M))
+
+
+def test_crop_geometry():
+    g = O.make_geometry(512, 512, 4, 4, 4, 4, 4)
+    for step in range(20):
+        q = O.crop_queries(g, 9, step, crops=3, side=64)
+        lod = int(q["lod"][0])
+        assert np.all(q["lod"] == lod)
+        W = g.mip_w[lod]
+        x = q["u"].astype(np.float64) * W - 0.5
+        y = q["v"].astype(np.float64) * W - 0.5
+        assert np.all(x == np.round(x)) and np.all(y == np.round(y))   # texel centres
+        for c in range(3):
+            xc = x[c * 4096:(c + 1) * 4096].reshape(64, 64)
+            yc = y[c * 4096:(c + 1) * 4096].reshape(64, 64)
+            if W >= 64:    # a contiguous window inside the mip, row-major
+                assert np.all(np.diff(xc, axis=1) == 1) and np.all(np.diff(yc, axis=0) == 1)
+                assert xc.min() >= 0 and xc.max() <= W - 1
+            else:          # the mip tiled from its origin
+                assert np.array_equal(xc[0], np.arange(64) % W)
+
+
 # ---------------------------------------------------------------- optimiser (sec 4.5, 5.1)
 def test_adam_step1_closed_form():
     g = np.array([0.3, -2.0, 1e-3, 0.0])

@@ -31,6 +31,51 @@ __device__ inline f16x2 code_pair(uint32_t w, int s) {
   return __builtin_bit_cast(f16x2, ((w >> s) & pm) | 0x64006400u);
 }
 
+// Byte offsets of one feature level's packed grids and of their last dwords (the
+// packed latents of a decodable material are below 4 GiB, see ntc_decode), kept in
+// LDS so a per-lane level index reads them directly.
+struct LevelBytes {
+  uint32_t g0, g1, g0_last, g1_last;
+};
+__device__ inline void fill_level_bytes(const DevMat& m, LevelBytes* lb, int tid, int nthreads) {
+  for (int j = tid; j < kMaxLevels; j += nthreads) {
+    LevelBytes b;
+    b.g0 = (uint32_t)m.g0_pk[j];
+    b.g1 = (uint32_t)m.g1_pk[j];
+    b.g0_last = (uint32_t)(m.g0_pk_end[j] * 4);
+    b.g1_last = (uint32_t)(m.g1_pk_end[j] * 4);
+    lb[j] = b;
+  }
+}
+
+// NW dwords of the code window of `cell` (NB bits per cell) in a grid at byte `base`,
+// with 32-bit byte offsets from the packed-latent pointer (loads through a scalar base).
+template <int NW, int NB>
+__device__ inline void load_window(const char* __restrict__ packed, uint32_t base, uint32_t cell, uint32_t last,
+                                   uint32_t (&out)[NW]) {
+  if constexpr (NB % 64 == 0) {  // whole 8-byte units (grid bases are 16-byte aligned)
+    const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
+#pragma unroll
+    for (int k = 0; k < NW / 2; ++k) {
+      const uint2 w = *reinterpret_cast<const uint2*>(packed + (b0 + 8u * k));
+      out[2 * k] = w.x;
+      out[2 * k + 1] = w.y;
+    }
+  } else if constexpr (NB % 32 == 0) {
+    const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) out[k] = *reinterpret_cast<const uint32_t*>(packed + (b0 + 4u * k));
+  } else {
+    const uint64_t bit = (uint64_t)cell * NB;
+    const uint32_t b0 = base + (uint32_t)(bit >> 5) * 4u, s = (uint32_t)bit & 31u;
+    uint32_t w[NW + 1];
+#pragma unroll
+    for (int k = 0; k <= NW; ++k) w[k] = *reinterpret_cast<const uint32_t*>(packed + min(b0 + 4u * k, last));
+#pragma unroll
+    for (int k = 0; k < NW; ++k) out[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
+  }
+}
+
 // The bit-packed code words one texel's lane group needs (its G0 neighbour cell and
 // the four G1 taps) plus what the input assembly needs from the footprint.
 template <int C0, int C1, int B0, int B1>
@@ -40,8 +85,8 @@ struct CodeWindow {
   float fx, fy, w[4];
   uint32_t g0[NW0];
   uint32_t g1[4][NW1];
-  __device__ inline void fetch(const DevMat& m, const uint32_t* __restrict__ packed, float u, float v, int lod,
-                               int g) {
+  __device__ inline void fetch(const DevMat& m, const LevelBytes* __restrict__ lb, const uint32_t* __restrict__ packed,
+                               float u, float v, int lod, int g) {
     const Footprint f = locate(m, u, v, lod, g);
     ix = f.ix;
     iy = f.iy;
@@ -49,10 +94,11 @@ struct CodeWindow {
     fy = f.fy;
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = f.g1_w[k];
-    load_bits<NW0, NB0 % 32 == 0>(packed, m.g0_pk[f.j] * 8 + (long long)f.g0_cell * NB0, m.g0_pk_end[f.j], g0);
+    const LevelBytes b = lb[f.j];
+    const char* pk = reinterpret_cast<const char*>(packed);
+    load_window<NW0, NB0>(pk, b.g0, (uint32_t)f.g0_cell, b.g0_last, g0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      load_bits<NW1, NB1 % 32 == 0>(packed, m.g1_pk[f.j] * 8 + (long long)f.g1_cell[k] * NB1, m.g1_pk_end[f.j], g1[k]);
+    for (int k = 0; k < 4; ++k) load_window<NW1, NB1>(pk, b.g1, (uint32_t)f.g1_cell[k], b.g1_last, g1[k]);
   }
 };
 
@@ -126,6 +172,8 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
   T* w_lds = reinterpret_cast<T*>(smem);
   float* pe_lds = reinterpret_cast<float*>(smem + WB);
   float* b_lds = pe_lds + 48;  // b1 (HD), b2 (HD), b3 (C, zero-padded to 16)
+  LevelBytes* lb = reinterpret_cast<LevelBytes*>(b_lds + 2 * HD + 16);
+  fill_level_bytes(m, lb, threadIdx.x, blockDim.x);
 
   for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
@@ -238,11 +286,11 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
     int lod;
     load_query(tile, u, v, lod);
     Raw cur;
-    cur.fetch(m, packed, u, v, lod, g);
+    cur.fetch(m, lb, packed, u, v, lod, g);
     load_query(tile + stride, u, v, lod);
     for (; tile < tiles; tile += stride) {
       Raw nxt;
-      if (tile + stride < tiles) nxt.fetch(m, packed, u, v, lod, g);
+      if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
       if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
       T xs[S1];
       assemble(cur, xs);
@@ -311,6 +359,8 @@ __global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, c
   const uint8_t* w_lds = reinterpret_cast<const uint8_t*>(smem);
   float* pe_lds = reinterpret_cast<float*>(smem + WB);
   float* b_lds = pe_lds + 48;
+  LevelBytes* lb = reinterpret_cast<LevelBytes*>(b_lds + 2 * HD + 16);
+  fill_level_bytes(m, lb, threadIdx.x, blockDim.x);
 
   for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
@@ -358,11 +408,11 @@ __global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, c
   int lod;
   load_query(tile, u, v, lod);
   Raw cur;
-  cur.fetch(m, packed, u, v, lod, g);
+  cur.fetch(m, lb, packed, u, v, lod, g);
   load_query(tile + stride, u, v, lod);
   for (; tile < tiles; tile += stride) {
     Raw nxt;
-    if (tile + stride < tiles) nxt.fetch(m, packed, u, v, lod, g);
+    if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
     if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
 
     // ---- inputs: S1/4 words of e4m3 bytes
@@ -433,7 +483,7 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
                                 long long n, const TexelRect& rect, void* out, bool out_f16, hipStream_t s) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4;
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   const float* scales = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
   auto kern = decode_fp8_kernel<C0, C1, C, HD, B0, B1, ACT>;
   static int per_cu = 0;
@@ -461,7 +511,7 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
                            const ntc_query* q, long long n, const TexelRect& rect, void* out, bool out_f16,
                            hipStream_t s) {
   constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>::WB;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4;
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   const float *b1, *b2, *b3;
   if (mlp) {
     const long long K = 4 * C0 + C1 + 12;

@@ -259,6 +259,7 @@ static ntc_status check_decode(const ntc_material* m, ntc_dtype precision, ntc_d
     return fail(NTC_E_UNSUPPORTED, "no decode kernel for this (c0, c1, channels, hidden, b0, b1)");
   if (precision == NTC_FP8_E4M3 && !fp8_supported(m))
     return fail(NTC_E_UNSUPPORTED, "FP8 decode needs whole-dword G0 cells and b0, b1 <= 4");
+  if (m->packed_bytes >= ((int64_t)1 << 32)) return fail(NTC_E_UNSUPPORTED, "packed latents of 4 GiB or more");
   return NTC_OK;
 }
 

@@ -405,6 +405,24 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
     torch.cuda.synchronize()
     dec_ms = (time.perf_counter() - t1) / 5 * 1e3
     nd = int(doff[-1])
+    # the same batch grouped: one launch per kernel shape
+    table = ntc.DecodeTable(mats, packed, wpacks, ntc.F16)
+    out_g = torch.empty_like(out)
+    for _ in range(2):
+        ntc.decode_grouped(table, qd, doff, out_g, ntc.F16)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        ntc.decode_grouped(table, qd, doff, out_g, ntc.F16)
+    torch.cuda.synchronize()
+    grp_ms = (time.perf_counter() - t1) / 5 * 1e3
+    grp_same = bool(torch.equal(out_g, out))
+    per_shape = {}
+    for m, n in zip(mats, dq):
+        if n > 0:
+            k = (m.c0, m.c1, m.channels, m.hidden, m.b0, m.b1, m.activation)
+            per_shape[k] = per_shape.get(k, 0) + 1
+    classes = sum((c + 31) // 32 for c in per_shape.values())  # launches: at most 32 materials each
     big = max(int(m.width) ** 2 * m.channels for m in mats)
     tile_out = torch.empty(big, dtype=torch.float16, device="cuda")
     torch.cuda.synchronize()
@@ -413,13 +431,18 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
         ntc.decode_tile(m, p, w, ntc.F16, 0, 0, 0, m.width, m.height, tile_out, ntc.F16)
     torch.cuda.synchronize()
     coh_ms = (time.perf_counter() - t1) * 1e3
+    log(f"[bench] grouped decode: {nd} random queries in {classes} launches {grp_ms:.3f} ms -> "
+        f"{nd / (grp_ms * 1e-3):.3e} texels/s (equal to per-material launches: {grp_same})")
     log(f"[bench] batched decode: {nd} random queries {dec_ms:.3f} ms -> {nd / (dec_ms * 1e-3):.3e} texels/s; "
         f"coherent mip 0 of all materials ({int(area.sum())} texels) {coh_ms:.3f} ms -> "
         f"{area.sum() / (coh_ms * 1e-3):.3e} texels/s")
     return dict(materials=len(mats), mip0_texels=int(area.sum()), samples_per_step=ntot,
                 train_ms_per_step_graph=round(graph_ms, 4), train_ms_per_step_eager=round(eager_ms, 4),
                 train_samples_per_s=ntot / (graph_ms * 1e-3), mean_loss=loss, tuned_tiles=tuned,
-                decode_random=dict(queries=nd, ms=round(dec_ms, 4), texels_per_s=nd / (dec_ms * 1e-3)),
+                decode_random=dict(queries=nd, ms=round(dec_ms, 4), texels_per_s=nd / (dec_ms * 1e-3),
+                                   launches=sum(1 for n in dq if n > 0)),
+                decode_random_grouped=dict(queries=nd, ms=round(grp_ms, 4), texels_per_s=nd / (grp_ms * 1e-3),
+                                           launches=classes, equal_to_per_material=grp_same),
                 decode_coherent_mip0=dict(texels=int(area.sum()), ms=round(coh_ms, 4),
                                           texels_per_s=float(area.sum() / (coh_ms * 1e-3))))
 

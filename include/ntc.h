@@ -346,6 +346,32 @@ ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint
                               const int64_t* offsets, void* out, ntc_dtype out_dtype, void* stream);
 
 /*
+ * Grouped decode: the batch of ntc_decode_batched decoded with one launch per kernel
+ * shape (c0, c1, channels, hidden, b0, b1, activation) instead of one per material;
+ * each launch shares its blocks out over its materials (at most 32 per launch) in
+ * proportion to their queries, and every block decodes with its own material's weights.
+ *   ntc_decode_table_bytes: size of the device table for nmat materials.
+ *   ntc_decode_table_init: validates the batch (as ntc_decode_batched, for the given
+ *     precision) and writes the table into `table` (caller device memory): per
+ *     material its geometry and the device pointers packed_latents[i], mlp_packed[i]
+ *     (host arrays).  Synchronous (returns after the copy); a set-up call, not for
+ *     stream capture.  Those buffers must stay allocated while the table is used; their
+ *     contents may change (re-quantized latents, re-packed weights).
+ *   ntc_decode_grouped: decodes group i (queries offsets[i] .. offsets[i+1]-1, host
+ *     offsets) of material i into out as ntc_decode_batched does.  mats and nmat must be
+ *     those the table was built for: the launches carry a hash of them and decode nothing
+ *     when it differs from the table's.  precision must match the packs.  Only kernel
+ *     launches are enqueued, so the call can be captured in a HIP graph.
+ */
+size_t ntc_decode_table_bytes(int32_t nmat);
+ntc_status ntc_decode_table_init(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
+                                 const void* const* mlp_packed, ntc_dtype precision, void* table,
+                                 size_t table_bytes);
+ntc_status ntc_decode_grouped(const ntc_material* mats, int32_t nmat, const void* table, ntc_dtype precision,
+                              const ntc_query* q, const int64_t* offsets, void* out, ntc_dtype out_dtype,
+                              void* stream);
+
+/*
  * Kernel timing for measurement (not needed for normal use).  After
  * ntc_timing_begin(max_launches), the library records a HIP event pair on the launch
  * stream around each of the next max_launches launches of every timed kernel

@@ -1,482 +1,10 @@
-// Random-access decode (sections 4.3-4.4): packed latents -> all C channels per texel.
-//
-// Persistent kernel, 4 wavefronts per block, one 16-texel tile per wavefront
-// iteration.  Each of the 4 lane groups of a texel fetches one G0 neighbour cell
-// (a contiguous C0*B0-bit window), a quarter of the G1 bilinear channels and 3 of
-// the 12 positional-encoding values, so the MLP input is assembled directly in the
-// B-operand layout of the matrix cores.  The three layers chain through registers;
-// weights are staged once per block in LDS.
+// Single-material decode launchers: random queries (ntc_decode), texel rectangles
+// (ntc_decode_tile) and the FP32-latent forward of the differentiation path.
 #include <algorithm>
 
-#include "ntc_internal.h"
+#include "decode_impl.h"
 
 namespace ntc {
-
-// Input layout of the decoder for a material: packed codes in FP16 use the paired
-// layout where it applies; everything else (and the forward of the differentiation
-// path, which shares the training pack) the plain one.
-template <typename T, int C0, int C1, int HD, int B0, int B1, bool PACKED>
-struct DecodeLayout {
-  static constexpr bool paired = PACKED && paired_layout(C0, C1, B0, B1, sizeof(T) == 2);
-  static constexpr PackGeom pg = PACKED ? pack_geom_decode(C0, C1, B0, B1, HD, sizeof(T) == 2)
-                                        : pack_geom(C0, C1, HD, sizeof(T) == 2);
-  static constexpr int WB = ((int)pg.fwd_end * (int)sizeof(T) + 15) / 16 * 16;
-};
-
-// Two codes of one 32-bit word (bit offsets s and s + 16) as FP16 values 1024 + code:
-// OR-ing the exponent of 1024 over a code of at most 10 bits is the exact conversion.
-template <int B>
-__device__ inline f16x2 code_pair(uint32_t w, int s) {
-  constexpr uint32_t cm = (1u << B) - 1u, pm = cm | (cm << 16);
-  return __builtin_bit_cast(f16x2, ((w >> s) & pm) | 0x64006400u);
-}
-
-// Byte offsets of one feature level's packed grids and of their last dwords (the
-// packed latents of a decodable material are below 4 GiB, see ntc_decode), kept in
-// LDS so a per-lane level index reads them directly.
-struct LevelBytes {
-  uint32_t g0, g1, g0_last, g1_last;
-};
-__device__ inline void fill_level_bytes(const DevMat& m, LevelBytes* lb, int tid, int nthreads) {
-  for (int j = tid; j < kMaxLevels; j += nthreads) {
-    LevelBytes b;
-    b.g0 = (uint32_t)m.g0_pk[j];
-    b.g1 = (uint32_t)m.g1_pk[j];
-    b.g0_last = (uint32_t)(m.g0_pk_end[j] * 4);
-    b.g1_last = (uint32_t)(m.g1_pk_end[j] * 4);
-    lb[j] = b;
-  }
-}
-
-// NW dwords of the code window of `cell` (NB bits per cell) in a grid at byte `base`,
-// with 32-bit byte offsets from the packed-latent pointer (loads through a scalar base).
-template <int NW, int NB>
-__device__ inline void load_window(const char* __restrict__ packed, uint32_t base, uint32_t cell, uint32_t last,
-                                   uint32_t (&out)[NW]) {
-  if constexpr (NB % 64 == 0) {  // whole 8-byte units (grid bases are 16-byte aligned)
-    const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
-#pragma unroll
-    for (int k = 0; k < NW / 2; ++k) {
-      const uint2 w = *reinterpret_cast<const uint2*>(packed + (b0 + 8u * k));
-      out[2 * k] = w.x;
-      out[2 * k + 1] = w.y;
-    }
-  } else if constexpr (NB % 32 == 0) {
-    const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) out[k] = *reinterpret_cast<const uint32_t*>(packed + (b0 + 4u * k));
-  } else {
-    const uint64_t bit = (uint64_t)cell * NB;
-    const uint32_t b0 = base + (uint32_t)(bit >> 5) * 4u, s = (uint32_t)bit & 31u;
-    uint32_t w[NW + 1];
-#pragma unroll
-    for (int k = 0; k <= NW; ++k) w[k] = *reinterpret_cast<const uint32_t*>(packed + min(b0 + 4u * k, last));
-#pragma unroll
-    for (int k = 0; k < NW; ++k) out[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
-  }
-}
-
-// The bit-packed code words one texel's lane group needs (its G0 neighbour cell and
-// the four G1 taps) plus what the input assembly needs from the footprint.
-template <int C0, int C1, int B0, int B1>
-struct CodeWindow {
-  static constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
-  int ix, iy;
-  float fx, fy, w[4];
-  uint32_t g0[NW0];
-  uint32_t g1[4][NW1];
-  __device__ inline void fetch(const DevMat& m, const LevelBytes* __restrict__ lb, const uint32_t* __restrict__ packed,
-                               float u, float v, int lod, int g) {
-    const Footprint f = locate(m, u, v, lod, g);
-    ix = f.ix;
-    iy = f.iy;
-    fx = f.fx;
-    fy = f.fy;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = f.g1_w[k];
-    const LevelBytes b = lb[f.j];
-    const char* pk = reinterpret_cast<const char*>(packed);
-    load_window<NW0, NB0>(pk, b.g0, (uint32_t)f.g0_cell, b.g0_last, g0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) load_window<NW1, NB1>(pk, b.g1, (uint32_t)f.g1_cell[k], b.g1_last, g1[k]);
-  }
-};
-
-// G1 bilinear of the paired layout: pair p = d * (4/B1) + kk holds channels
-// d*32/B1 + g + 4kk and that + 16/B1.  Separable, in centred code units: the row steps
-// are exact, the column step rounds once, the power-of-two scale is exact, so the
-// result equals the FP16 rounding of the exact bilinear value.
-template <int C0, int C1, int B0, int B1>
-__device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
-                                f16x2 (&out)[CodeWindow<C0, C1, B0, B1>::NW1 * (4 / B1)]) {
-  constexpr int NW1 = CodeWindow<C0, C1, B0, B1>::NW1, KP = 4 / B1, N1 = 1 << B1;
-  const f16x2 fx = {(_Float16)R.fx, (_Float16)R.fx}, fy = {(_Float16)R.fy, (_Float16)R.fy};
-  const _Float16 o = (_Float16)(-(1024.f + N1 / 2 - 1));
-  const f16x2 of = {o, o};
-  const f16x2 sc = {(_Float16)(1.f / N1), (_Float16)(1.f / N1)};
-#pragma unroll
-  for (int d = 0; d < NW1; ++d)
-#pragma unroll
-    for (int kk = 0; kk < KP; ++kk) {
-      const int sh = B1 * (g + 4 * kk);
-      const f16x2 x0 = code_pair<B1>(R.g1[0][d], sh), x1 = code_pair<B1>(R.g1[1][d], sh);
-      const f16x2 x2 = code_pair<B1>(R.g1[2][d], sh), x3 = code_pair<B1>(R.g1[3][d], sh);
-      const f16x2 r0 = __builtin_elementwise_fma(fx, x1 - x0, x0 + of);
-      const f16x2 r1 = __builtin_elementwise_fma(fx, x3 - x2, x2 + of);
-      out[d * KP + kk] = __builtin_elementwise_fma(fy, r1 - r0, r0) * sc;
-    }
-}
-
-// Lane group g's four output channels 4g .. 4g+3 of texel s.
-template <int C>
-__device__ inline void store_out(void* __restrict__ out, int out_f16, long long s, long long n, int g, f32x4 y) {
-  if (s >= n || 4 * g >= C) return;
-  if (out_f16) {
-    _Float16* o = reinterpret_cast<_Float16*>(out) + s * C + 4 * g;
-    if constexpr (C % 4 == 0) {
-      *reinterpret_cast<f16x4*>(o) = __builtin_convertvector(y, f16x4);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (4 * g + i < C) o[i] = (_Float16)y[i];
-    }
-  } else {
-    float* o = reinterpret_cast<float*>(out) + s * C + 4 * g;
-    if constexpr (C % 4 == 0) {
-      *reinterpret_cast<f32x4*>(o) = y;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (4 * g + i < C) o[i] = y[i];
-    }
-  }
-}
-
-// PACKED: latents come as bit-packed codes (ntc_decode); otherwise as FP32 values
-// in the canonical latent layout (ntc_forward, the differentiation path).
-// bias: b1 (HD), b2 (HD), b3 (C) at the three given addresses.
-template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
-__global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const void* __restrict__ src,
-                                                     const T* __restrict__ wpack, const float* __restrict__ bias1,
-                                                     const float* __restrict__ bias2,
-                                                     const float* __restrict__ bias3,
-                                                     const ntc_query* __restrict__ q, long long n,
-                                                     TexelRect rect, void* __restrict__ out, int out_f16) {
-  const uint32_t* __restrict__ packed = reinterpret_cast<const uint32_t*>(src);
-  const float* __restrict__ lat = reinterpret_cast<const float*>(src);
-  using IS = InSlots<C0, C1>;
-  using DL = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>;
-  constexpr PackGeom pg = DL::pg;
-  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT, WB = DL::WB;
-  extern __shared__ __align__(16) char smem[];
-  T* w_lds = reinterpret_cast<T*>(smem);
-  float* pe_lds = reinterpret_cast<float*>(smem + WB);
-  float* b_lds = pe_lds + 48;  // b1 (HD), b2 (HD), b3 (C, zero-padded to 16)
-  LevelBytes* lb = reinterpret_cast<LevelBytes*>(b_lds + 2 * HD + 16);
-  fill_level_bytes(m, lb, threadIdx.x, blockDim.x);
-
-  for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
-    reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
-  for (int i = threadIdx.x; i < 48; i += blockDim.x) pe_lds[i] = pe.v[i / 6][i % 6];
-  for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x)
-    b_lds[i] = i < HD ? bias1[i] : i < 2 * HD ? bias2[i - HD] : i < 2 * HD + C ? bias3[i - 2 * HD] : 0.f;
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const long long tiles = (n + 15) / 16, stride = (long long)gridDim.x * 4;
-
-  // three layers on one tile's assembled inputs, then the store
-  auto mlp_store = [&](T (&xs)[S1], long long tile) {
-    const long long s = tile * 16 + r;
-    f32x4 acc[MT];
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + 16 * mo + 4 * g);
-      acc[mo] = mma_slots<S1>(acc[mo], w_lds + pg.L1 + mo * S1 * 64, xs, lane);
-    }
-    T h[SH];
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
-      acc[mo] = mma_slots<SH>(acc[mo], w_lds + pg.L2 + mo * SH * 64, h, lane);
-    }
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
-    // layer 3 (no activation): lane group g holds channels 4g .. 4g+3
-    f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
-    y = mma_slots<SH>(y, w_lds + pg.L3, h, lane);
-    store_out<C>(out, out_f16, s, n, g, y);
-  };
-  auto pe_slots = [&](T (&xs)[S1], int ix, int iy) {
-    float pv[3];
-    pe_values(pe_lds, ix, iy, g, pv);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) xs[pg.T_lat + k] = (T)pv[k];
-#pragma unroll
-    for (int t = pg.T_used; t < S1; ++t) xs[t] = (T)0.f;
-  };
-  // query record of this lane's texel of a tile (zeros past the end)
-  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
-    const long long s = tile * 16 + r;
-    u = v = 0.f;
-    lod = 0;
-    if (tile < tiles && s < n) {
-      if (rect.w > 0) {
-        rect_query(rect, s, u, v, lod);
-      } else {
-        u = q[s].u;
-        v = q[s].v;
-        lod = q[s].lod;
-      }
-    }
-  };
-
-  if constexpr (PACKED) {
-    // Software pipeline over the wave's tiles: queries two tiles ahead, latent words
-    // one tile ahead, so both gathers are in flight while the matrix cores run.
-    using Raw = CodeWindow<C0, C1, B0, B1>;
-    auto assemble = [&](const Raw& R, T (&xs)[S1]) {
-      if constexpr (DL::paired) {
-        {  // G0: two channels per instruction; (1024 + code) / N - (N/2 - 1 + 1024) / N is exact
-          constexpr int HALF = 16 / B0, N0 = 1 << B0;
-          const f16x2 sc = {(_Float16)(1.f / N0), (_Float16)(1.f / N0)};
-          const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
-          const f16x2 of = {o, o};
-#pragma unroll
-          for (int d = 0; d < Raw::NW0; ++d)
-#pragma unroll
-            for (int c = 0; c < HALF; ++c) {
-              const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
-              xs[2 * (d * HALF + c)] = x[0];
-              xs[2 * (d * HALF + c) + 1] = x[1];
-            }
-        }
-        f16x2 v[Raw::NW1 * (4 / B1)];
-        g1_pairs(R, g, v);
-#pragma unroll
-        for (int p = 0; p < Raw::NW1 * (4 / B1); ++p) {
-          xs[C0 + 2 * p] = v[p][0];
-          xs[C0 + 2 * p + 1] = v[p][1];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < C0; ++t) xs[t] = (T)dequant<B0>(code_at<B0>(R.g0, t));
-        // G1: bilinear over 4 taps, channels g, g+4, ...
-        float acc[IS::n1max];
-#pragma unroll
-        for (int i = 0; i < IS::n1max; ++i) acc[i] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int i = 0; i < IS::n1max; ++i) {
-            const int ch = min(g + 4 * i, C1 - 1);
-            acc[i] += R.w[k] * dequant<B1>(code_at_dyn<B1>(R.g1[k], ch));
-          }
-#pragma unroll
-        for (int i = 0; i < IS::n1max; ++i) xs[C0 + i] = (g + 4 * i < C1) ? (T)acc[i] : (T)0.f;
-      }
-      pe_slots(xs, R.ix, R.iy);
-    };
-
-    long long tile = (long long)blockIdx.x * 4 + wave;
-    if (tile >= tiles) return;
-    float u, v;
-    int lod;
-    load_query(tile, u, v, lod);
-    Raw cur;
-    cur.fetch(m, lb, packed, u, v, lod, g);
-    load_query(tile + stride, u, v, lod);
-    for (; tile < tiles; tile += stride) {
-      Raw nxt;
-      if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
-      if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
-      T xs[S1];
-      assemble(cur, xs);
-      mlp_store(xs, tile);
-      cur = nxt;
-    }
-  } else {
-    for (long long tile = (long long)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
-      float u, v;
-      int lod;
-      load_query(tile, u, v, lod);
-      const Footprint f = locate(m, u, v, lod, g);
-      T xs[S1];
-      const long long g0base = m.g0_off[f.j] + (long long)f.g0_cell * C0;
-      const long long g1base = m.g1_off[f.j];
-#pragma unroll
-      for (int t = 0; t < C0; ++t) xs[t] = (T)lat[g0base + t];
-#pragma unroll
-      for (int i = 0; i < IS::n1max; ++i) {
-        const int ch = g + 4 * i;
-        float acc = 0.f;
-        if (ch < C1) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc += f.g1_w[k] * lat[g1base + (long long)f.g1_cell[k] * C1 + ch];
-        }
-        xs[C0 + i] = (T)acc;
-      }
-      pe_slots(xs, f.ix, f.iy);
-      mlp_store(xs, tile);
-    }
-  }
-}
-
-// ------------------------------------------------------------------ FP8-e4m3 decode
-// Same pipeline as the FP16 decoder; operands are e4m3 bytes, four slots per word.
-// G0 codes go through a byte lookup (v_perm) straight to e4m3 patterns of their exact
-// dequantized values; G1 values are the paired FP16 bilinear values rounded to e4m3;
-// layer outputs are s_l * acc + b_l in FP32, the activation, then e4m3 again.
-template <int B>
-__device__ inline uint32_t codes_to_e4m3(uint32_t codes) {  // one code (< 2^B) per byte
-  constexpr uint32_t L0 = e4m3_code_lut(B, 0), L1 = e4m3_code_lut(B, 1);
-  if constexpr (B <= 3) {
-    return __builtin_amdgcn_perm(L1, L0, codes);
-  } else {
-    constexpr uint32_t L2 = e4m3_code_lut(B, 2), L3 = e4m3_code_lut(B, 3);
-    const uint32_t sel = codes & 0x07070707u;
-    const uint32_t lo = __builtin_amdgcn_perm(L1, L0, sel), hi = __builtin_amdgcn_perm(L3, L2, sel);
-    const uint32_t mask = ((codes >> 3) & 0x01010101u) * 0xFFu;
-    return (hi & mask) | (lo & ~mask);
-  }
-}
-
-template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
-__global__ __launch_bounds__(256) void decode_fp8_kernel(DevMat m, PeTable pe, const uint32_t* __restrict__ packed,
-                                                         const uint8_t* __restrict__ wpack,
-                                                         const float* __restrict__ scales,
-                                                         const float* __restrict__ bias,
-                                                         const ntc_query* __restrict__ q, long long n,
-                                                         TexelRect rect, void* __restrict__ out, int out_f16) {
-  constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
-  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT;
-  constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
-  using Raw = CodeWindow<C0, C1, B0, B1>;
-  constexpr int NP = Raw::NW1 * (4 / B1);  // G1 pairs per lane group
-  extern __shared__ __align__(16) char smem[];
-  const uint8_t* w_lds = reinterpret_cast<const uint8_t*>(smem);
-  float* pe_lds = reinterpret_cast<float*>(smem + WB);
-  float* b_lds = pe_lds + 48;
-  LevelBytes* lb = reinterpret_cast<LevelBytes*>(b_lds + 2 * HD + 16);
-  fill_level_bytes(m, lb, threadIdx.x, blockDim.x);
-
-  for (int i = threadIdx.x; i < WB / 16; i += blockDim.x)
-    reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(wpack)[i];
-  for (int i = threadIdx.x; i < 48; i += blockDim.x) pe_lds[i] = pe.v[i / 6][i % 6];
-  for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x) b_lds[i] = i < 2 * HD + C ? bias[i] : 0.f;
-  __syncthreads();
-  const float sc1 = scales[0], sc2 = scales[1], sc3 = scales[2];
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const long long tiles = (n + 15) / 16, stride = (long long)gridDim.x * 4;
-
-  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
-    const long long s = tile * 16 + r;
-    u = v = 0.f;
-    lod = 0;
-    if (tile < tiles && s < n) {
-      if (rect.w > 0) {
-        rect_query(rect, s, u, v, lod);
-      } else {
-        u = q[s].u;
-        v = q[s].v;
-        lod = q[s].lod;
-      }
-    }
-  };
-  // A operand of MFMA kk of M-tile mo of a layer pack with S slots
-  auto a_op = [&](long long base, int S, int mo, int kk) -> long {
-    return *reinterpret_cast<const long*>(w_lds + base + (long long)mo * S * 64 + kk * 512 + lane * 8);
-  };
-  // hidden layer: act(s * acc + b) of fragment mo as 4 e4m3 bytes (slots 4mo .. 4mo+3)
-  auto hidden_word = [&](f32x4 acc, float s, const float* b, int mo) -> uint32_t {
-    const f32x4 bb = *reinterpret_cast<const f32x4*>(b + 16 * mo + 4 * g);
-    float h[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {  // activation, saturated to the e4m3 range (the conversion alone gives NaN)
-      const float z = __builtin_fmaf(acc[i], s, bb[i]);
-      h[i] = ACT == 0 ? __builtin_amdgcn_fmed3f(z, 0.f, 448.f) : __builtin_amdgcn_fmed3f(act_fn<ACT>(z), -448.f, 448.f);
-    }
-    return cvt_e4m3x2(h[2], h[3], cvt_e4m3x2(h[0], h[1], 0u, false), true);
-  };
-
-  long long tile = (long long)blockIdx.x * 4 + wave;
-  if (tile >= tiles) return;
-  float u, v;
-  int lod;
-  load_query(tile, u, v, lod);
-  Raw cur;
-  cur.fetch(m, lb, packed, u, v, lod, g);
-  load_query(tile + stride, u, v, lod);
-  for (; tile < tiles; tile += stride) {
-    Raw nxt;
-    if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
-    if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
-
-    // ---- inputs: S1/4 words of e4m3 bytes
-    uint32_t xw[S1 / 4];
-#pragma unroll
-    for (int i = 0; i < S1 / 4; ++i) xw[i] = 0u;
-    constexpr uint32_t BM = ((1u << B0) - 1u) * 0x01010101u;
-#pragma unroll
-    for (int d = 0; d < Raw::NW0; ++d)
-#pragma unroll
-      for (int k = 0; k < 8 / B0; ++k) xw[(8 / B0) * d + k] = codes_to_e4m3<B0>((cur.g0[d] >> (B0 * k)) & BM);
-    {
-      f16x2 pv2[NP];
-      g1_pairs(cur, g, pv2);
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int t = C0 + 2 * p;
-        xw[t / 4] = cvt_e4m3x2((float)pv2[p][0], (float)pv2[p][1], xw[t / 4], (t % 4) != 0);
-      }
-      float pv[3];
-      pe_values(pe_lds, cur.ix, cur.iy, g, pv);
-      constexpr int t0 = pg.T_lat;  // even
-      xw[t0 / 4] = cvt_e4m3x2(pv[0], pv[1], xw[t0 / 4], (t0 % 4) != 0);
-      xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], 0.f, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
-    }
-    // ---- layer 1
-    uint32_t hw[SH / 4];
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < S1 / 8; ++kk) {
-        const long b = (long)((uint64_t)xw[2 * kk] | (uint64_t)xw[2 * kk + 1] << 32);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L1, S1, mo, kk), b, acc, 0, 0, 0);
-      }
-      hw[mo] = hidden_word(acc, sc1, b_lds, mo);
-    }
-    // ---- layer 2
-    uint32_t hw2[SH / 4];
-#pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < SH / 8; ++kk) {
-        const long b = (long)((uint64_t)hw[2 * kk] | (uint64_t)hw[2 * kk + 1] << 32);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L2, SH, mo, kk), b, acc, 0, 0, 0);
-      }
-      hw2[mo] = hidden_word(acc, sc2, b_lds + HD, mo);
-    }
-    // ---- layer 3 (no activation)
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < SH / 8; ++kk) {
-      const long b = (long)((uint64_t)hw2[2 * kk] | (uint64_t)hw2[2 * kk + 1] << 32);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L3, SH, 0, kk), b, acc, 0, 0, 0);
-    }
-    const f32x4 b3 = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
-    f32x4 y;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) y[i] = __builtin_fmaf(acc[i], sc3, b3[i]);
-    store_out<C>(out, out_f16, tile * 16 + r, n, g, y);
-    cur = nxt;
-  }
-}
 
 template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
 static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, const void* wpack, const ntc_query* q,
@@ -549,11 +77,6 @@ static hipError_t decode_t(const ntc_material& mm, const void* src, const void* 
              ? decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 1>(mm, src, wpack, mlp, q, n, rect, out, out_f16, s)
              : decode_t1<T, C0, C1, C, HD, B0, B1, PACKED, 0>(mm, src, wpack, mlp, q, n, rect, out, out_f16, s);
 }
-
-#define NTC_DECODE_SHAPES(X)                                                                     \
-  X(8, 8, 8, 64, 4, 4) X(10, 10, 10, 64, 4, 4) X(12, 12, 12, 64, 4, 4) X(16, 16, 16, 64, 4, 4)  \
-  X(8, 8, 8, 32, 4, 4) X(10, 10, 10, 32, 4, 4) X(12, 12, 12, 32, 4, 4) X(16, 16, 16, 32, 4, 4)  \
-  X(16, 16, 16, 64, 2, 4)
 
 bool decode_shape_supported(int c0, int c1, int c, int hd, int b0, int b1) {
 #define NTC_X(a, b, cc, h, x0, x1) \

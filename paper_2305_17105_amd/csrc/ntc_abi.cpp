@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <mutex>
 #include <string>
 
@@ -700,6 +701,43 @@ ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint
     o += (size_t)n * mats[i].channels;
   }
   return NTC_OK;
+}
+
+size_t ntc_decode_table_bytes(int32_t nmat) {
+  if (nmat < 1) return 0;
+  return (size_t)kGroupHeaderBytes + (size_t)nmat * sizeof(GroupEntry);
+}
+
+ntc_status ntc_decode_table_init(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
+                                 const void* const* mlp_packed, ntc_dtype precision, void* table,
+                                 size_t table_bytes) {
+  if (!mats || nmat < 1) return fail(NTC_E_INVALID, "NULL materials or nmat < 1");
+  if (!packed_latents || !mlp_packed || !table) return fail(NTC_E_INVALID, "NULL buffer");
+  if (table_bytes < ntc_decode_table_bytes(nmat)) return fail(NTC_E_WORKSPACE, "decode table too small");
+  for (int i = 0; i < nmat; ++i) {
+    ntc_status st = check_decode(mats + i, precision, NTC_F16);
+    if (st != NTC_OK) return st;
+    if (!packed_latents[i] || !mlp_packed[i]) return fail(NTC_E_INVALID, "NULL latents or weights");
+  }
+  std::vector<char> host(ntc_decode_table_bytes(nmat), 0);
+  const unsigned long long h = group_hash(mats, nmat);
+  std::memcpy(host.data(), &h, sizeof h);
+  GroupEntry* e = reinterpret_cast<GroupEntry*>(host.data() + kGroupHeaderBytes);
+  for (int i = 0; i < nmat; ++i) fill_group_entry(mats[i], packed_latents[i], mlp_packed[i], e[i]);
+  return hip_status(hipMemcpy(table, host.data(), host.size(), hipMemcpyHostToDevice), "ntc_decode_table_init");
+}
+
+ntc_status ntc_decode_grouped(const ntc_material* mats, int32_t nmat, const void* table, ntc_dtype precision,
+                              const ntc_query* q, const int64_t* offsets, void* out, ntc_dtype out_dtype,
+                              void* stream) {
+  ntc_status st = check_batch(mats, nmat, offsets);
+  if (st != NTC_OK) return st;
+  if (!table || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  for (int i = 0; i < nmat; ++i)
+    if ((st = check_decode(mats + i, precision, out_dtype)) != NTC_OK) return st;
+  return hip_status(launch_decode_grouped(mats, nmat, table, precision, q, offsets, out, out_dtype == NTC_F16,
+                                          (hipStream_t)stream),
+                    "ntc_decode_grouped");
 }
 
 }  // extern "C"

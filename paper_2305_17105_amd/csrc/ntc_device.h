@@ -37,6 +37,29 @@ struct DevMat {
   long long latent_count;
 };
 
+// One material of a grouped launch: its geometry, bit-packed latents and decode pack.
+struct GroupEntry {
+  DevMat m;
+  const void* packed;
+  const void* wpack;
+};
+// A material's share of a grouped launch: blocks [block0, next segment's block0),
+// queries q0 .. q0 + n - 1, outputs from element o0.
+constexpr int kGroupSegs = 32;
+struct GroupSeg {
+  int mat, block0;
+  long long q0, n, o0;
+};
+// A grouped launch: `hash` must equal the table's (the table was built for the
+// materials the launch was planned for), otherwise its blocks do nothing.
+struct GroupArgs {
+  unsigned long long hash;
+  int count, blocks;
+  GroupSeg seg[kGroupSegs];
+};
+// Device table of a grouped decode: a header (hash of the materials) then the entries.
+constexpr int kGroupHeaderBytes = 256;
+
 // Coherent decode source: the texels of rectangle [x0, x0+w) x [y0, y0+h) of mip lod,
 // row-major (w == 0: queries come from a query array instead).  inv_w, inv_h = 1 / mip
 // size, so (x + 1/2) * inv_w is the exact texel centre.

@@ -42,6 +42,14 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
                          const ntc_query* q, long long n, const TexelRect* rect, void* out, bool out_f16,
                          hipStream_t s);
 
+// Grouped decode: table entries, the hash that ties a table to its materials, and the
+// launches (one per kernel shape, at most kGroupSegs materials each).
+void fill_group_entry(const ntc_material& m, const void* packed, const void* wpack, GroupEntry& e);
+unsigned long long group_hash(const ntc_material* mats, int nmat);
+hipError_t launch_decode_grouped(const ntc_material* mats, int nmat, const void* table, int precision,
+                                 const ntc_query* q, const int64_t* offsets, void* out, bool out_f16,
+                                 hipStream_t s);
+
 // Tunable plan parameters: samples per work item and largest latent-tile side
 // (0: the kernel's capacity).
 struct TrainTune {

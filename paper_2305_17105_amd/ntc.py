@@ -100,6 +100,11 @@ _sig = {
                                      _P(C.c_int64), C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_crop_queries": (C.c_int, [_P(Material), C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                    C.c_void_p]),
+    "ntc_decode_table_bytes": (C.c_size_t, [C.c_int32]),
+    "ntc_decode_table_init": (C.c_int, [_P(Material), C.c_int32, _P(C.c_void_p), _P(C.c_void_p), C.c_int,
+                                        C.c_void_p, C.c_size_t]),
+    "ntc_decode_grouped": (C.c_int, [_P(Material), C.c_int32, C.c_void_p, C.c_int, C.c_void_p, _P(C.c_int64),
+                                     C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_timing_begin": (C.c_int, [C.c_int32]),
     "ntc_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "ntc_timing_end": (C.c_int, []),
@@ -300,6 +305,34 @@ def decode_batched(mats, packed, wpacks, precision, queries, offsets, out, out_d
     wp = (C.c_void_p * n)(*[_ptr(w) for w in wpacks])
     _check(_lib.ntc_decode_batched(_materials(mats), n, pk, wp, precision, _ptr(queries), off, _ptr(out), out_dtype,
                                    _stream(stream)), "ntc_decode_batched")
+
+
+class DecodeTable:
+    """Device table of a grouped decode batch (ntc_decode_table_init): the materials,
+    their packed latents and decode packs; the buffers are kept referenced."""
+
+    def __init__(self, mats, packed, wpacks, precision, device="cuda"):
+        import torch
+        n = len(mats)
+        self.mats = _materials(mats)
+        self.nmat = n
+        self.precision = precision
+        self._keep = (list(packed), list(wpacks))
+        nbytes = int(_lib.ntc_decode_table_bytes(n))
+        self.table = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        pk = (C.c_void_p * n)(*[_ptr(p) for p in packed])
+        wp = (C.c_void_p * n)(*[_ptr(w) for w in wpacks])
+        _check(_lib.ntc_decode_table_init(self.mats, n, pk, wp, precision, _ptr(self.table), nbytes),
+               "ntc_decode_table_init")
+
+
+def decode_grouped(table: DecodeTable, queries, offsets, out, out_dtype, stream=None, precision=None):
+    """ntc_decode_batched's result with one launch per kernel shape (see DecodeTable)."""
+    n = table.nmat
+    off = (C.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    prec = table.precision if precision is None else precision
+    _check(_lib.ntc_decode_grouped(table.mats, n, _ptr(table.table), prec, _ptr(queries), off, _ptr(out),
+                                   out_dtype, _stream(stream)), "ntc_decode_grouped")
 
 
 class TrainState:

@@ -123,3 +123,21 @@ def test_training_plans_fit_large_materials(ntc, W, C, hd):
     m = ntc.material_init(W, W, C, C, C, 4, 4, hd)
     for prec in (ntc.F32, ntc.F16):
         assert ntc.train_workspace_bytes(m, 262144, prec) > 0
+
+
+def test_decode_table_sizes_and_validation():
+    """The grouped-decode table: header plus one entry per material; set-up calls with
+    missing buffers fail before touching a device."""
+    import ctypes as C
+    from paper_2305_17105_amd import ntc
+    assert ntc._lib.ntc_decode_table_bytes(0) == 0
+    one = ntc._lib.ntc_decode_table_bytes(1)
+    assert one > 256 and ntc._lib.ntc_decode_table_bytes(3) - one == 2 * (one - 256)
+    m = ntc.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    mats = ntc._materials([m])
+    null = (C.c_void_p * 1)(None)
+    st = ntc._lib.ntc_decode_table_init(mats, 1, null, null, ntc.F16, None, one)
+    assert st == ntc.E_INVALID
+    off = (C.c_int64 * 2)(0, 0)
+    st = ntc._lib.ntc_decode_grouped(mats, 1, None, ntc.F16, None, off, None, ntc.F16, None)
+    assert st == ntc.E_INVALID

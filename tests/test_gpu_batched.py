@@ -206,3 +206,66 @@ def test_autotune_picks_a_candidate_and_training_still_matches(lib):
         a, b = getattr(s1, k).double(), getattr(s0, k).double()
         err = float((a - b).abs().max()) / max(float(b.abs().max()), 1e-30)
         assert err <= 1e-4, (k, err)
+
+
+def _decode_batch(lib, P, count, seed):
+    """`count` small decode materials over several kernel shapes (one with hardGELU, one
+    with an empty query group), their packs and queries."""
+    import torch
+    kinds = [(8, 8, 4, 4, 64), (16, 16, 4, 4, 32), (16, 16, 2, 4, 64), (8, 8, 4, 4, 32)]
+    if P != lib.FP8_E4M3:
+        kinds.append((12, 12, 4, 4, 64))
+    r = np.random.default_rng(seed)
+    ms, pk, wp, qs, ns = [], [], [], [], []
+    for i in range(count):
+        C, c0, b0, b1, hd = kinds[0] if (i % 4 or i < 4) else kinds[(i // 4) % len(kinds)]
+        W = int(2 ** r.integers(6, 9))
+        act = lib.ACT_HARDGELU if i == 1 else lib.ACT_RELU
+        m = lib.material_init(W, W, C, c0, c0, b0, b1, hd, activation=act)
+        p = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        lib.quantize_latents(m, to_dev(synth.uniform_latents(seed + i, int(m.latent_count))), p)
+        w = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+        lib.pack_mlp(m, to_dev(mlp_in_unit_range(seed + 100 + i, int(m.input_width), hd, C)), P, w)
+        n = 0 if i == 3 else int(r.integers(1, 2500))
+        ms.append(m); pk.append(p); wp.append(w); ns.append(n)
+        qs.append(synth.random_queries(seed + 200 + i, n, int(m.num_mips)))
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    return ms, pk, wp, queries_dev(np.concatenate(qs)), offsets
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "fp8"])
+@pytest.mark.parametrize("out_dtype", ["f32", "f16"])
+def test_grouped_decode_equals_batched(lib, prec, out_dtype):
+    """Grouped decode (one launch per kernel shape, more materials of one shape than a
+    launch holds) writes exactly what per-material decode writes, for every material."""
+    import torch
+    P = {"f32": lib.F32, "f16": lib.F16, "fp8": lib.FP8_E4M3}[prec]
+    OD, tdt = (lib.F32, torch.float32) if out_dtype == "f32" else (lib.F16, torch.float16)
+    ms, pk, wp, q, offsets = _decode_batch(lib, P, 52, 900)
+    total = sum(int(offsets[i + 1] - offsets[i]) * m.channels for i, m in enumerate(ms))
+    ref = torch.full((total,), float("nan"), dtype=tdt, device="cuda")
+    lib.decode_batched(ms, pk, wp, P, q, offsets, ref, OD)
+    table = lib.DecodeTable(ms, pk, wp, P)
+    for _ in range(2):  # the table is reused
+        out = torch.full((total,), float("nan"), dtype=tdt, device="cuda")
+        lib.decode_grouped(table, q, offsets, out, OD)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+
+
+def test_grouped_decode_table_of_other_materials_decodes_nothing(lib):
+    """A table built for one batch, used with the descriptors of another, leaves the
+    output untouched."""
+    import torch
+    ms, pk, wp, q, offsets = _decode_batch(lib, lib.F16, 6, 950)
+    ms2 = list(ms)
+    ms2[0] = lib.material_init(512, 512, 8, 8, 8, 4, 4, 64)
+    table = lib.DecodeTable(ms, pk, wp, lib.F16)
+    total = sum(int(offsets[i + 1] - offsets[i]) * m.channels for i, m in enumerate(ms2))
+    out = torch.full((total,), 7.0, dtype=torch.float16, device="cuda")
+    t2 = lib.DecodeTable.__new__(lib.DecodeTable)
+    t2.__dict__.update(table.__dict__)
+    t2.mats = lib._materials(ms2)
+    lib.decode_grouped(t2, q, offsets, out, lib.F16)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())

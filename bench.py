@@ -296,11 +296,12 @@ def batched_materials(seed=7, count=64):
 
 
 def run_batched(ntc, synth, torch, steps, warmup, seed=7):
-    """Many-material workload: every material trained (FP16 matrix cores) in one batched
-    step captured in a HIP graph and replayed, samples per material proportional to its
-    area; then decoded in one batched call (queries proportional to area) and through
-    the coherent rectangle entry point (all of mip 0).  Tile shapes per (hidden width,
-    channels) come from the step tuner."""
+    """Many-material workload: every material trained (FP16 matrix cores) in one grouped
+    step (one launch per stage, the fused kernel per material) captured in a HIP graph
+    and replayed, samples per material proportional to its area; then decoded grouped
+    (one launch per kernel shape; queries proportional to area) and through the coherent
+    rectangle entry point (all of mip 0).  Tile shapes per (hidden width, channels) come
+    from the step tuner."""
     b = BATCH
     spec = batched_materials(seed, b["materials"])
     t0 = time.time()
@@ -352,13 +353,23 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
         ntc.train_prepare(m, st, hp_host)
     log(f"[bench] batched: tuned tiles {tuned}")
 
-    # eager batched steps, then one captured step replayed
+    # eager steps with per-material launches, eager grouped steps (one launch per
+    # stage), then one captured grouped step replayed
     for s in range(warmup):
         ntc.train_step_batched(mats, states, qpool[s % 2], offsets, targets, hp, ws)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for s in range(steps):
         ntc.train_step_batched(mats, states, qpool[s % 2], offsets, targets, hp, ws)
+    torch.cuda.synchronize()
+    per_material_ms = (time.perf_counter() - t1) / steps * 1e3
+    table = ntc.TrainTable(mats, states, offsets, targets, ntc.F16, ws)
+    for s in range(warmup):
+        ntc.train_step_grouped(table, qpool[s % 2], hp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(steps):
+        ntc.train_step_grouped(table, qpool[s % 2], hp)
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t1) / steps * 1e3
     graphs = []
@@ -367,7 +378,7 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.stream(stream):
             with torch.cuda.graph(g, stream=stream):
-                ntc.train_step_batched(mats, states, qpool[k], offsets, targets, hp, ws)
+                ntc.train_step_grouped(table, qpool[k], hp)
         graphs.append(g)
     torch.cuda.synchronize()
     graphs[0].replay()
@@ -378,9 +389,10 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
     torch.cuda.synchronize()
     graph_ms = (time.perf_counter() - t1) / steps * 1e3
     loss = float(np.mean([float(st.loss.cpu()[0]) for st in states]))
-    log(f"[bench] batched train: eager {eager_ms:.3f} ms/step, graph replay {graph_ms:.3f} ms/step -> "
+    log(f"[bench] batched train: per-material launches {per_material_ms:.3f} ms/step, grouped eager "
+        f"{eager_ms:.3f} ms/step, grouped graph replay {graph_ms:.3f} ms/step -> "
         f"{ntot / (graph_ms * 1e-3):.3e} samples/s, mean loss {loss:.5f}, step index {int(step_dev.item())}")
-    del graphs, ws
+    del graphs, table, ws
 
     # decode: random queries proportional to area in one batched call; coherent mip 0
     packed, wpacks = [], []
@@ -438,6 +450,7 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
         f"{area.sum() / (coh_ms * 1e-3):.3e} texels/s")
     return dict(materials=len(mats), mip0_texels=int(area.sum()), samples_per_step=ntot,
                 train_ms_per_step_graph=round(graph_ms, 4), train_ms_per_step_eager=round(eager_ms, 4),
+                train_ms_per_step_per_material_launches=round(per_material_ms, 4),
                 train_samples_per_s=ntot / (graph_ms * 1e-3), mean_loss=loss, tuned_tiles=tuned,
                 decode_random=dict(queries=nd, ms=round(dec_ms, 4), texels_per_s=nd / (dec_ms * 1e-3),
                                    launches=sum(1 for n in dq if n > 0)),

@@ -176,6 +176,7 @@ ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents,
  *   loss         1 float: mean squared error of the last step
  *   loss_scale   1 float: dynamic loss scale (used by NTC_F16; set it once, e.g. 65536)
  *   scale_state  2 int32: [0] consecutive good steps, [1] 1 if the last step was skipped
+ * The five latent buffers must be 16-byte aligned (NTC_E_INVALID otherwise).
  */
 typedef struct {
   float* latents;
@@ -344,6 +345,36 @@ ntc_status ntc_train_step_batched(const ntc_material* mats, int32_t nmat, const 
 ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
                               const void* const* mlp_packed, ntc_dtype precision, const ntc_query* q,
                               const int64_t* offsets, void* out, ntc_dtype out_dtype, void* stream);
+
+/*
+ * Grouped training: the batched step of ntc_train_step_batched with each stage that
+ * is not the fused training kernel (binning, scans, partial-tile reduction,
+ * weight-gradient reduction, Adam) run as one launch for the whole group instead of
+ * one per material; the fused kernel still runs per material.  Every member needs
+ * samples (offsets strictly increasing).
+ *   ntc_train_table_bytes: size of the device table for nmat materials.
+ *   ntc_train_table_init: validates the group and writes the table into `table`
+ *     (caller device memory): per material its geometry, training plan (tile shapes
+ *     from the tuning table in effect), sample group and the device pointers of its
+ *     state, targets and workspace slice (the workspace is laid out as for
+ *     ntc_train_step_batched, ntc_train_workspace_bytes_batched bytes).  Synchronous;
+ *     a set-up call, not for stream capture.  Build it again after tuning a member's
+ *     shape or changing any of these.
+ *   ntc_train_step_grouped: one training step of every member; arguments as for
+ *     ntc_train_step_batched plus the table.  The launches carry a hash of the group
+ *     (materials, plans, sample groups, precision, buffers; not the queries or the
+ *     hyper-parameters) and do nothing when it differs from the table's.  Only kernel
+ *     launches are enqueued: with hp->step_dev (and hp->lr_dev) a captured step replays
+ *     as the next step.
+ */
+size_t ntc_train_table_bytes(int32_t nmat);
+ntc_status ntc_train_table_init(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                const int64_t* offsets, const float* const* targets, ntc_dtype precision,
+                                void* workspace, size_t ws_bytes, void* table, size_t table_bytes);
+ntc_status ntc_train_step_grouped(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                  const ntc_query* q, const int64_t* offsets, const float* const* targets,
+                                  const ntc_hparams* hp, void* workspace, size_t ws_bytes, const void* table,
+                                  void* stream);
 
 /*
  * Grouped decode: the batch of ntc_decode_batched decoded with one launch per kernel

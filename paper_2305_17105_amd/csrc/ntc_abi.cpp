@@ -329,6 +329,8 @@ static ntc_status check_state(const ntc_train_state* s, bool f16) {
       !s->mlp_v || !s->mlp_packed || !s->loss || !s->scale_state)
     return fail(NTC_E_INVALID, "NULL state buffer");
   if (f16 && !s->loss_scale) return fail(NTC_E_INVALID, "loss_scale is required for F16 training");
+  for (const float* p : {s->latents, s->latents_fwd, s->lat_m, s->lat_v, s->lat_grad})
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(NTC_E_INVALID, "latent buffers must be 16-byte aligned");
   return NTC_OK;
 }
 
@@ -701,6 +703,134 @@ ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint
     o += (size_t)n * mats[i].channels;
   }
   return NTC_OK;
+}
+
+// ------------------------------------------------------------------ grouped training
+// Validates a grouped-training group and builds each member's buffer view (fused[i],
+// with the queries of `q`, and adam[i], pointers only).
+static ntc_status group_members(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                const ntc_query* q, const int64_t* offsets, const float* const* targets,
+                                ntc_dtype precision, void* workspace, size_t ws_bytes,
+                                std::vector<TrainLaunch>& fused, std::vector<AdamLaunch>& adam) {
+  ntc_status st = check_batch(mats, nmat, offsets);
+  if (st != NTC_OK) return st;
+  if (!states || !targets) return fail(NTC_E_INVALID, "NULL states or targets");
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  const bool f16 = precision == NTC_F16;
+  for (int i = 0; i < nmat; ++i) {
+    if ((st = check_state(states + i, f16)) != NTC_OK) return st;
+    if (!train_shape_supported(mats[i].c0, mats[i].c1, mats[i].channels, mats[i].hidden))
+      return fail(NTC_E_UNSUPPORTED, "no training kernel for a material's (c0, c1, channels, hidden)");
+    if (offsets[i + 1] <= offsets[i]) return fail(NTC_E_INVALID, "every member of a group needs samples");
+    if (!targets[i]) return fail(NTC_E_INVALID, "NULL targets");
+    if (!train_plan(mats[i], f16, offsets[i + 1] - offsets[i]).supported_bins)
+      return fail(NTC_E_UNSUPPORTED, "too many latent tiles for a material");
+  }
+  const size_t need = ntc_train_workspace_bytes_batched(mats, nmat, offsets, precision);
+  if (!workspace || need == 0 || ws_bytes < need) return fail(NTC_E_WORKSPACE, "workspace too small");
+  fused.assign(nmat, TrainLaunch{});
+  adam.assign(nmat, AdamLaunch{});
+  size_t off = 0;
+  for (int i = 0; i < nmat; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    const ntc_train_state* sp = states + i;
+    TrainLaunch& a = fused[i];
+    a.lat_fwd = sp->latents_fwd;
+    a.wpack = sp->mlp_packed;
+    a.mlp = sp->mlp;
+    a.q = q ? q + offsets[i] : nullptr;
+    a.n = n;
+    a.targets = targets[i];
+    a.lat_grad = sp->lat_grad;
+    a.workspace = (char*)workspace + off;
+    a.loss_scale = f16 ? sp->loss_scale : nullptr;
+    a.scale_slot = 0;
+    a.step_dev = nullptr;
+    a.overflow_flag = sp->scale_state + 1;
+    a.scatter_latents = true;
+    a.dout = nullptr;
+    a.dout_scale = 1.f;
+    a.out_scale = 1.f;
+    AdamLaunch& d = adam[i];
+    d.latents = sp->latents;
+    d.latents_fwd = sp->latents_fwd;
+    d.lat_m = sp->lat_m;
+    d.lat_v = sp->lat_v;
+    d.lat_grad = sp->lat_grad;
+    d.mlp = sp->mlp;
+    d.mlp_m = sp->mlp_m;
+    d.mlp_v = sp->mlp_v;
+    d.mlp_grad = nullptr;  // the member's workspace (set with the table)
+    d.wpack = sp->mlp_packed;
+    d.loss_scale = f16 ? sp->loss_scale : nullptr;
+    d.scale_state = sp->scale_state;
+    d.f16 = f16 ? 1 : 0;
+    d.loss_out = sp->loss;
+    off += (ntc_train_workspace_bytes(mats + i, n, precision) + 255) / 256 * 256;
+  }
+  return NTC_OK;
+}
+
+size_t ntc_train_table_bytes(int32_t nmat) { return nmat < 1 ? 0 : train_table_bytes(nmat); }
+
+ntc_status ntc_train_table_init(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                const int64_t* offsets, const float* const* targets, ntc_dtype precision,
+                                void* workspace, size_t ws_bytes, void* table, size_t table_bytes) {
+  std::vector<TrainLaunch> fused;
+  std::vector<AdamLaunch> adam;
+  ntc_status st = group_members(mats, nmat, states, nullptr, offsets, targets, precision, workspace, ws_bytes, fused,
+                                adam);
+  if (st != NTC_OK) return st;
+  if (!table) return fail(NTC_E_INVALID, "NULL table");
+  if (table_bytes < train_table_bytes(nmat)) return fail(NTC_E_WORKSPACE, "training table too small");
+  const bool f16 = precision == NTC_F16;
+  const unsigned long long h = train_group_hash(mats, nmat, offsets, f16, fused.data(), adam.data());
+  std::vector<char> host(train_table_bytes(nmat));
+  fill_train_table(mats, nmat, offsets, f16, fused.data(), adam.data(), h, host.data());
+  return hip_status(hipMemcpy(table, host.data(), host.size(), hipMemcpyHostToDevice), "ntc_train_table_init");
+}
+
+ntc_status ntc_train_step_grouped(const ntc_material* mats, int32_t nmat, const ntc_train_state* states,
+                                  const ntc_query* q, const int64_t* offsets, const float* const* targets,
+                                  const ntc_hparams* hp, void* workspace, size_t ws_bytes, const void* table,
+                                  void* stream) {
+  ntc_status st = check_hparams(hp);
+  if (st != NTC_OK) return st;
+  if (!q || !table) return fail(NTC_E_INVALID, "NULL queries or table");
+  std::vector<TrainLaunch> fused;
+  std::vector<AdamLaunch> adam;
+  st = group_members(mats, nmat, states, q, offsets, targets, (ntc_dtype)hp->precision, workspace, ws_bytes, fused,
+                     adam);
+  if (st != NTC_OK) return st;
+  const bool f16 = hp->precision == NTC_F16;
+  const unsigned long long h = train_group_hash(mats, nmat, offsets, f16, fused.data(), adam.data());
+  for (auto& a : fused) {
+    a.scale_slot = hp->step & 1;
+    a.step_dev = hp->step_dev;
+    a.scatter_latents = !hp->freeze_latents;
+  }
+  AdamLaunch hot{};
+  hot.lr_lat = hp->lr_latent;
+  hot.lr_mlp = hp->lr_mlp;
+  hot.beta1 = hp->beta1;
+  hot.beta2 = hp->beta2;
+  hot.eps = hp->eps;
+  const double t = (double)hp->step + 1.0;
+  hot.bc1 = (float)(1.0 - std::pow((double)hp->beta1, t));
+  hot.bc2 = (float)(1.0 - std::pow((double)hp->beta2, t));
+  hot.next_key = noise_key(hp->noise_seed, hp->step + 1);
+  hot.seed = hp->noise_seed;
+  hot.step = hp->step;
+  hot.noise = hp->noise ? 1 : 0;
+  hot.freeze = hp->freeze_latents ? 1 : 0;
+  hot.growth = hp->scale_growth_interval > 0 ? hp->scale_growth_interval : 2000;
+  hot.step_dev = hp->step_dev;
+  hot.lr_dev = hp->lr_dev;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_status(e, "ntc_train_step_grouped (earlier asynchronous error)");
+  return hip_status(launch_train_grouped(mats, nmat, offsets, f16, table, h, q, !hp->freeze_latents, fused.data(), hot,
+                                         (hipStream_t)stream),
+                    "ntc_train_step_grouped");
 }
 
 size_t ntc_decode_table_bytes(int32_t nmat) {

@@ -91,6 +91,8 @@ struct TrainLaunch {
   const float* dout;        // external output gradient, or nullptr (L2 loss against targets)
   float dout_scale;
   float out_scale;          // multiplies the latent gradient written to lat_grad
+  const unsigned long long* table_hash = nullptr;  // grouped step: the table's hash (kernel no-ops on mismatch)
+  unsigned long long hash = 0;
 };
 hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& a,
                                   hipStream_t s);
@@ -120,11 +122,25 @@ struct AdamLaunch {
   const float* lr_dev;  // device (lr_lat, lr_mlp) or nullptr
   uint64_t seed;        // noise seed (device-step mode derives the key on the device)
   bool advance;         // device-step mode: advance the step index after the update
+  float* loss_out = nullptr;  // grouped step: the member's loss
 };
 hipError_t launch_crop_queries(const ntc_material& m, uint64_t seed, int step, int crops, int side, double fraction,
                                ntc_query* out, hipStream_t s);
 hipError_t launch_adam(const ntc_material& m, const AdamLaunch& a, hipStream_t s);
 hipError_t launch_step_advance(int* step_dev, hipStream_t s);
+
+// Grouped training step (one launch per stage for a group of materials; the fused
+// kernel per material): device-table size, the hash tying a table to its group, the
+// table's host image, and the step's launches.  fused[i] / adam[i]: the member's
+// buffers; hot: the step-dependent Adam scalars shared by the group.
+size_t train_table_bytes(int nmat);
+unsigned long long train_group_hash(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16,
+                                    const TrainLaunch* fused, const AdamLaunch* adam);
+void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16, const TrainLaunch* fused,
+                      const AdamLaunch* adam, unsigned long long hash, void* host_table);
+hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16,
+                                const void* table, unsigned long long hash, const ntc_query* q, bool scatter,
+                                const TrainLaunch* fused, const AdamLaunch& hot, hipStream_t s);
 hipError_t launch_prepare(const ntc_material& m, const float* latents, float* latents_fwd, float* lat_grad,
                           uint64_t key, int noise, hipStream_t s);
 

@@ -66,6 +66,8 @@ struct TrainArgs {
   const float* dout;   // external output gradient (differentiation path) or nullptr
   float dout_scale;    // multiplies dout before the backward (FP16 range)
   float out_scale;     // multiplies the latent gradient written out
+  const unsigned long long* table_hash;  // grouped step: its table's hash, else nullptr
+  unsigned long long hash;               // the hash the grouped step was planned with
   TileGeom tg;
 };
 
@@ -199,6 +201,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
   using RegT = typename Cfg::RegT;
   RegT* reg = reinterpret_cast<RegT*>(smem + Cfg::OFF_REG);
+  if (a.table_hash && *a.table_hash != a.hash) return;  // grouped step against another table
 
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
@@ -644,17 +647,19 @@ struct BinArgs {
   int4* list;
 };
 
+// bi: the binning block (of a.nbb) this block is; q: the material's queries.
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs a) {
+__device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, const BinArgs& a,
+                                         const ntc_query* __restrict__ q, int bi) {
   extern __shared__ int hist[];
   const int nb = tg.nbins;
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)b * a.nbb + blockIdx.x] : 0;
+    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)b * a.nbb + bi] : 0;
   __syncthreads();
-  const long long s0 = (long long)blockIdx.x * a.per_block;
+  const long long s0 = (long long)bi * a.per_block;
   const long long s1 = min(a.n, s0 + a.per_block);
   for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-    const ntc_query qq = a.q[s];
+    const ntc_query qq = q[s];
     const Footprint f = locate(m, qq.u, qq.v, qq.lod, 0);
     const SampleBins sb = sample_bins(f, tg);
     for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
@@ -667,17 +672,22 @@ __global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs
   }
   if (!SCATTER) {
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)b * a.nbb + blockIdx.x] = hist[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)b * a.nbb + bi] = hist[b];
   }
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs a) {
+  bin_body<SCATTER>(m, tg, a, a.q, blockIdx.x);
 }
 
 // Per-bin column scan over the binning blocks: one wavefront per bin, each lane
 // holds 4 consecutive blocks (nbb <= 256).  Writes the per-block offsets and the
 // bin total.
-__global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, const int* __restrict__ counts,
-                                                        int* __restrict__ offsets, int* __restrict__ total) {
+__device__ __forceinline__ void bin_scan1_body(int nbins, int nbb, const int* __restrict__ counts,
+                                               int* __restrict__ offsets, int* __restrict__ total, int bi) {
   const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = bi * 4 + (threadIdx.x >> 6);
   if (b >= nbins) return;
   int v[4];
   int sum = 0;
@@ -703,6 +713,11 @@ __global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, cons
   if (lane == 63) total[b] = incl;
 }
 
+__global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, const int* __restrict__ counts,
+                                                        int* __restrict__ offsets, int* __restrict__ total) {
+  bin_scan1_body(nbins, nbb, counts, offsets, total, blockIdx.x);
+}
+
 // One block of 1024 threads: exclusive scan over the sort bins of their totals (list
 // positions), then per tile its start, total and work items (at most tg.chunk samples
 // per item, at least one), and the exclusive scan of the items over the tiles.
@@ -720,12 +735,11 @@ __device__ inline int block_exclusive_scan(int v, int* sh) {
   return sh[tid] - v;
 }
 
-__global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int* __restrict__ total,
-                                                         int* __restrict__ base, int* __restrict__ tile_start,
-                                                         int* __restrict__ tile_total, int* __restrict__ item_base,
-                                                         int* __restrict__ item_tile, int* __restrict__ nitems) {
-  __shared__ int s_base[kMaxBins + 1];
-  __shared__ int s_scan[1024];
+__device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __restrict__ total,
+                                               int* __restrict__ base, int* __restrict__ tile_start,
+                                               int* __restrict__ tile_total, int* __restrict__ item_base,
+                                               int* __restrict__ item_tile, int* __restrict__ nitems, int* s_base,
+                                               int* s_scan) {
   constexpr int kPer = kMaxBins / 1024;
   const int tid = threadIdx.x;
   const int nb = tg.nbins, nt = tg.ntiles;
@@ -784,11 +798,21 @@ __global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int*
   }
 }
 
+__global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int* __restrict__ total,
+                                                         int* __restrict__ base, int* __restrict__ tile_start,
+                                                         int* __restrict__ tile_total, int* __restrict__ item_base,
+                                                         int* __restrict__ item_tile, int* __restrict__ nitems) {
+  __shared__ int s_base[kMaxBins + 1];
+  __shared__ int s_scan[1024];
+  bin_scan2_body(tg, total, base, tile_start, tile_total, item_base, item_tile, nitems, s_base, s_scan);
+}
+
 // Latent gradients of tiles split over several work items: partials summed in item order.
-__global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
-                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
-                                   float out_scale) {
-  const int tile = blockIdx.y;
+// tile: the latent tile; bx, gx: this block's share of the tile's region (of gx).
+__device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom& tg, const int* __restrict__ item_base,
+                                                 const float* __restrict__ part, int region_max,
+                                                 float* __restrict__ lat_grad, float out_scale, int tile, int bx,
+                                                 int gx) {
   const int it0 = item_base[tile], items = item_base[tile + 1] - it0;
   if (items <= 1) return;
   int j = 0;
@@ -798,7 +822,7 @@ __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict_
   const int C0 = m.C0, C1 = m.C1;
   const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
   const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < RG; k += gridDim.x * blockDim.x) {
+  for (int k = bx * blockDim.x + threadIdx.x; k < RG; k += gx * blockDim.x) {
     float s = 0.f;
 #pragma unroll 8
     for (int i = 0; i < items; ++i) s += part[(long long)(it0 + i) * region_max + k];
@@ -814,14 +838,21 @@ __global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict_
   }
 }
 
+__global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
+                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
+                                   float out_scale) {
+  lat_partial_body(m, tg, item_base, part, region_max, lat_grad, out_scale, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------------------------ weight-gradient reduction
 // Stage 1: block (64 params x 4 row groups) sums its share of the per-block partial rows.
-__global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const float* __restrict__ part,
-                                                  float* __restrict__ tmp) {
+// bx: block of 64 parameters; by: block row (of gy), each of 4 row groups.
+__device__ __forceinline__ void dw_reduce1_body(int G, long long P, const float* __restrict__ part,
+                                                float* __restrict__ tmp, int bx, int by, int gy) {
   __shared__ float red[4][64];
-  const long long p = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int rg = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int ngroups = gridDim.y * 4;
+  const long long p = (long long)bx * 64 + (threadIdx.x & 63);
+  const int rg = by * 4 + (threadIdx.x >> 6);
+  const int ngroups = gy * 4;
   const int per = (G + ngroups - 1) / ngroups;
   const int b0 = rg * per, b1 = min(G, b0 + per);
   float s = 0.f;
@@ -832,20 +863,26 @@ __global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const floa
   red[threadIdx.x >> 6][threadIdx.x & 63] = s;
   __syncthreads();
   if (threadIdx.x < 64 && p < P)
-    tmp[(long long)blockIdx.y * P + p] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    tmp[(long long)by * P + p] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const float* __restrict__ part,
+                                                  float* __restrict__ tmp) {
+  dw_reduce1_body(G, P, part, tmp, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 // Stage 2: final sum, non-finite flag, loss.
-__global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp, float* __restrict__ grad,
-                           int G, const float* __restrict__ part_loss, float* __restrict__ loss_out, float norm,
-                           int32_t* flag, float out_scale) {
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void dw_reduce2_body(int parts, long long P, const float* __restrict__ tmp,
+                                                float* __restrict__ grad, int G, const float* __restrict__ part_loss,
+                                                float* __restrict__ loss_out, float norm, int32_t* flag,
+                                                float out_scale, int bx, int gx) {
+  for (long long p = bx * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gx * blockDim.x) {
     float s = 0.f;
     for (int k = 0; k < parts; ++k) s += tmp[(long long)k * P + p];
     grad[p] = s * out_scale;
     if (flag && !isfinite(s)) atomicOr(flag, 1);
   }
-  if (blockIdx.x == 0 && loss_out) {
+  if (bx == 0 && loss_out) {
     __shared__ float red[256];
     float s = 0.f;
     for (int b = threadIdx.x; b < G; b += blockDim.x) s += part_loss[b];
@@ -857,6 +894,12 @@ __global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp
     }
     if (threadIdx.x == 0) *loss_out = red[0] * norm;
   }
+}
+
+__global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp, float* __restrict__ grad,
+                           int G, const float* __restrict__ part_loss, float* __restrict__ loss_out, float norm,
+                           int32_t* flag, float out_scale) {
+  dw_reduce2_body(parts, P, tmp, grad, G, part_loss, loss_out, norm, flag, out_scale, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ optimiser
@@ -878,8 +921,10 @@ struct AdamArgs {
   int mlp_blocks;
 };
 
+// bx, gx: this block among the gx blocks of the material's update (the first
+// args.mlp_blocks take the network parameters, the rest stride over the latents).
 template <typename T>
-__global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
+__device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args, int bx, int gx) {
   const AdamLaunch& a = args.a;
   const int ovf = a.scale_state[1];
   // step-dependent values: from the host, or derived from the device step index
@@ -901,8 +946,8 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
   const float inv_s = 1.f / scale;
   const float b1 = a.beta1, b2 = a.beta2, eps = a.eps;
   const float ib1 = 1.f / bc1, ib2 = 1.f / bc2;
-  if ((int)blockIdx.x < args.mlp_blocks) {
-    const long long p = blockIdx.x * 256ll + threadIdx.x;
+  if (bx < args.mlp_blocks) {
+    const long long p = bx * 256ll + threadIdx.x;
     if (p < args.P && !ovf) {
       const float gr = a.mlp_grad[p] * inv_s;
       const float mm = b1 * a.mlp_m[p] + (1.f - b1) * gr;
@@ -913,7 +958,7 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
       a.mlp[p] = w;
       scatter_param<T>((T*)a.wpack, args.pg, m.C0, m.C1, m.C, m.Hd, p, w, true);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_scale) {
+    if (bx == 0 && threadIdx.x == 0 && a.loss_scale) {
       float sn = scale;
       int good = a.scale_state[0];
       if (ovf) {
@@ -929,24 +974,60 @@ __global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
     return;
   }
   if (a.freeze) return;
-  const long long base = ((long long)blockIdx.x - args.mlp_blocks) * 256 + threadIdx.x;
-  const long long stride = ((long long)gridDim.x - args.mlp_blocks) * 256;
-  for (long long i = base; i < m.latent_count; i += stride) {
+  // one latent: update in place (unless the step is skipped) and its forward value
+  auto one = [&](long long i, float& p, float gr, float& mm, float& vv) -> float {
     const int bits = latent_bits(m, i);
-    float p = a.latents[i];
     if (!ovf) {
-      const float gr = a.lat_grad[i] * inv_s;
-      const float mm = b1 * a.lat_m[i] + (1.f - b1) * gr;
-      const float vv = b2 * a.lat_v[i] + (1.f - b2) * gr * gr;
+      gr *= inv_s;
+      mm = b1 * mm + (1.f - b1) * gr;
+      vv = b2 * vv + (1.f - b2) * gr * gr;
       p = p - lr_lat * (mm * ib1) / (sqrtf(vv * ib2) + eps);
       const float lo = -0.5f + ldexpf(1.f, -bits - 1);  // -(N-1)/(2N)
       p = fminf(fmaxf(p, lo), 0.5f);
+    }
+    return a.noise ? p + noise_at(next_key, i, bits) : p;
+  };
+  // four consecutive latents per thread and iteration (16-byte accesses), then the tail
+  const long long base = ((long long)bx - args.mlp_blocks) * 256 + threadIdx.x;
+  const long long stride = ((long long)gx - args.mlp_blocks) * 256;
+  const long long nv = m.latent_count / 4;
+  for (long long v4 = base; v4 < nv; v4 += stride) {
+    const long long i = 4 * v4;
+    f32x4 p = reinterpret_cast<const f32x4*>(a.latents)[v4];
+    f32x4 gr = reinterpret_cast<const f32x4*>(a.lat_grad)[v4];
+    f32x4 mm = reinterpret_cast<const f32x4*>(a.lat_m)[v4];
+    f32x4 vv = reinterpret_cast<const f32x4*>(a.lat_v)[v4];
+    f32x4 fw;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float pk = p[k], mk = mm[k], vk = vv[k];
+      fw[k] = one(i + k, pk, gr[k], mk, vk);
+      p[k] = pk;
+      mm[k] = mk;
+      vv[k] = vk;
+    }
+    if (!ovf) {
+      reinterpret_cast<f32x4*>(a.lat_m)[v4] = mm;
+      reinterpret_cast<f32x4*>(a.lat_v)[v4] = vv;
+      reinterpret_cast<f32x4*>(a.latents)[v4] = p;
+    }
+    reinterpret_cast<f32x4*>(a.latents_fwd)[v4] = fw;
+  }
+  for (long long i = 4 * nv + base; i < m.latent_count; i += stride) {
+    float p = a.latents[i], mm = a.lat_m[i], vv = a.lat_v[i];
+    const float fw = one(i, p, a.lat_grad[i], mm, vv);
+    if (!ovf) {
       a.lat_m[i] = mm;
       a.lat_v[i] = vv;
       a.latents[i] = p;
     }
-    a.latents_fwd[i] = a.noise ? p + noise_at(next_key, i, bits) : p;
+    a.latents_fwd[i] = fw;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adam_kernel(DevMat m, AdamArgs args) {
+  adam_body<T>(m, args, blockIdx.x, gridDim.x);
 }
 
 // Device-step mode: the step index advances once the update has read it.
@@ -962,6 +1043,136 @@ __global__ void prepare_kernel(DevMat m, const float* __restrict__ lat, float* _
     fwd[i] = noise ? p + noise_at(key, i, latent_bits(m, i)) : p;
     grad[i] = 0.f;
   }
+}
+
+// ------------------------------------------------------------------ grouped step
+// A training step of many materials where each stage (binning, scans, partial
+// reduction, weight-gradient reduction, Adam) is one launch for the whole group: a
+// block finds its material's segment, then runs the single-material body on that
+// material's entry of a device table.
+struct TrainEntry {
+  DevMat m;
+  TileGeom tg;
+  BinArgs bin;        // q is unused: the launch's queries + q0
+  AdamArgs adam;      // pointers; step-dependent scalars come with each launch
+  long long q0, P;
+  int nbins, ntiles, region_max, fused_grid, dw1_x;
+  float loss_norm;
+  int* offsets;
+  int* total;
+  int* base;
+  int* tstart;
+  int* ttotal;
+  int* ibase;
+  int* itile;
+  int* nitems;
+  const float* part_lat;
+  float* lat_grad;
+  const float* part_dw;
+  float* tmp;
+  float* grad;
+  const float* part_loss;
+  float* loss_out;
+  int32_t* overflow;
+};
+
+constexpr int kTrainGroup = 64;  // materials per grouped launch
+struct TrainSegs {
+  unsigned long long hash;
+  int count, first;             // materials first .. first + count - 1 of the table
+  int block0[kTrainGroup + 1];  // first block of each material; block0[count] = all blocks
+};
+
+// The material of this block (the last segment starting at or before it) and the
+// block's index within it.
+__device__ inline const TrainEntry* group_member(const char* table, const TrainSegs& sg, int& bi, int& nb) {
+  if (*reinterpret_cast<const unsigned long long*>(table) != sg.hash) return nullptr;
+  const int b = blockIdx.x;
+  int lo = 0, hi = sg.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sg.block0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  bi = b - sg.block0[lo];
+  nb = sg.block0[lo + 1] - sg.block0[lo];
+  return reinterpret_cast<const TrainEntry*>(table + kGroupHeaderBytes) + sg.first + lo;
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void bin_grouped(const char* __restrict__ table, TrainSegs sg,
+                                                   const ntc_query* __restrict__ q) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e) bin_body<SCATTER>(e->m, e->tg, e->bin, q + e->q0, bi);
+}
+
+__global__ __launch_bounds__(256) void bin_scan1_grouped(const char* __restrict__ table, TrainSegs sg) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e) bin_scan1_body(e->nbins, e->bin.nbb, e->bin.counts, e->offsets, e->total, bi);
+}
+
+__global__ __launch_bounds__(1024) void bin_scan2_grouped(const char* __restrict__ table, TrainSegs sg) {
+  __shared__ int s_base[kMaxBins + 1];
+  __shared__ int s_scan[1024];
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e) bin_scan2_body(e->tg, e->total, e->base, e->tstart, e->ttotal, e->ibase, e->itile, e->nitems, s_base, s_scan);
+}
+
+__global__ __launch_bounds__(256) void lat_partial_grouped(const char* __restrict__ table, TrainSegs sg) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e) lat_partial_body(e->m, e->tg, e->ibase, e->part_lat, e->region_max, e->lat_grad, 1.f, bi, 0, 1);
+}
+
+__global__ __launch_bounds__(256) void dw_reduce1_grouped(const char* __restrict__ table, TrainSegs sg) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e) dw_reduce1_body(e->fused_grid, e->P, e->part_dw, e->tmp, bi % e->dw1_x, bi / e->dw1_x, kDwYBlocks);
+}
+
+__global__ __launch_bounds__(256) void dw_reduce2_grouped(const char* __restrict__ table, TrainSegs sg) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (e)
+    dw_reduce2_body(kDwYBlocks, e->P, e->tmp, e->grad, e->fused_grid, e->part_loss, e->loss_out, e->loss_norm,
+                    e->overflow, 1.f, bi, nb);
+}
+
+// Step-dependent Adam scalars shared by the group (from the hyper-parameters).
+struct AdamHot {
+  float lr_lat, lr_mlp, beta1, beta2, eps, bc1, bc2;
+  uint64_t next_key, seed;
+  int step, noise, freeze, growth;
+  int* step_dev;
+  const float* lr_dev;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void adam_grouped(const char* __restrict__ table, TrainSegs sg, AdamHot h) {
+  int bi, nb;
+  const TrainEntry* e = group_member(table, sg, bi, nb);
+  if (!e) return;
+  AdamArgs args = e->adam;
+  AdamLaunch& a = args.a;
+  a.lr_lat = h.lr_lat;
+  a.lr_mlp = h.lr_mlp;
+  a.beta1 = h.beta1;
+  a.beta2 = h.beta2;
+  a.eps = h.eps;
+  a.bc1 = h.bc1;
+  a.bc2 = h.bc2;
+  a.next_key = h.next_key;
+  a.seed = h.seed;
+  a.step = h.step;
+  a.noise = h.noise;
+  a.freeze = h.freeze;
+  a.growth = h.growth;
+  a.step_dev = h.step_dev;
+  a.lr_dev = h.lr_dev;
+  adam_body<T>(e->m, args, bi, nb);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1018,6 +1229,8 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.dout = l.dout;
   a.dout_scale = l.dout_scale;
   a.out_scale = l.out_scale;
+  a.table_hash = l.table_hash;
+  a.hash = l.hash;
   a.tg = p.tg;
   const int slot = timing_before(TK_TRAIN_FUSED, s);
   hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(Cfg::NTHR), Cfg::LDS, s, dev_mat(mm),
@@ -1165,6 +1378,20 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTu
   return p;
 }
 
+static hipError_t launch_train_fused(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& l,
+                                     hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+#define NTC_X(a_, b_, cc, h)                                                                     \
+  if (m.c0 == a_ && m.c1 == b_ && m.channels == cc && m.hidden == h)                             \
+    e = f16 ? (m.activation ? fused_t<_Float16, a_, b_, cc, h, 1>(m, p, l, s)                  \
+                            : fused_t<_Float16, a_, b_, cc, h, 0>(m, p, l, s))                   \
+            : (m.activation ? fused_t<float, a_, b_, cc, h, 1>(m, p, l, s)                       \
+                            : fused_t<float, a_, b_, cc, h, 0>(m, p, l, s));
+  NTC_TRAIN_SHAPES(NTC_X)
+#undef NTC_X
+  return e;
+}
+
 hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPlan& p, const TrainLaunch& l,
                                   hipStream_t s) {
   char* ws = (char*)l.workspace;
@@ -1190,14 +1417,7 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-#define NTC_X(a_, b_, cc, h)                                                                     \
-  if (m.c0 == a_ && m.c1 == b_ && m.channels == cc && m.hidden == h)                             \
-    e = f16 ? (m.activation ? fused_t<_Float16, a_, b_, cc, h, 1>(m, p, l, s)                  \
-                            : fused_t<_Float16, a_, b_, cc, h, 0>(m, p, l, s))                   \
-            : (m.activation ? fused_t<float, a_, b_, cc, h, 1>(m, p, l, s)                       \
-                            : fused_t<float, a_, b_, cc, h, 0>(m, p, l, s));
-  NTC_TRAIN_SHAPES(NTC_X)
-#undef NTC_X
+  e = launch_train_fused(m, f16, p, l, s);
   if (e != hipSuccess) return e;
   if (l.scatter_latents) {
     const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
@@ -1254,6 +1474,201 @@ hipError_t launch_prepare(const ntc_material& m, const float* latents, float* la
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dev_mat(m), latents, latents_fwd,
                      lat_grad, key, noise);
   return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------ grouped step (host)
+// Per-material launch geometry of a grouped step, derived identically by the table
+// set-up and by every step.
+struct GroupMember {
+  TrainPlan p;
+  long long q0, n;
+  int lat_blocks;  // Adam blocks over the latents (a share of the device's, by latent count)
+};
+
+static std::vector<GroupMember> plan_group(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16) {
+  std::vector<GroupMember> g(nmat);
+  long long lat_total = 0;
+  for (int i = 0; i < nmat; ++i) lat_total += mats[i].latent_count;
+  const long long cap = (long long)device_cus() * 8;
+  for (int i = 0; i < nmat; ++i) {
+    GroupMember& x = g[i];
+    x.q0 = offsets[i];
+    x.n = offsets[i + 1] - offsets[i];
+    x.p = train_plan(mats[i], f16, x.n);
+    const long long L = mats[i].latent_count;
+    long long b = lat_total > 0 ? (cap * L + lat_total - 1) / lat_total : 1;
+    b = std::max(1LL, std::min(b, (L + 255) / 256));
+    x.lat_blocks = (int)b;
+  }
+  return g;
+}
+
+size_t train_table_bytes(int nmat) { return (size_t)kGroupHeaderBytes + (size_t)nmat * sizeof(TrainEntry); }
+
+// FNV-1a over everything a table encodes that a step can see: the materials, their
+// plans and sample groups, the precision and the buffers of every member.
+unsigned long long train_group_hash(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16,
+                                    const TrainLaunch* fused, const AdamLaunch* adam) {
+  unsigned long long h = 1469598103934665603ULL;
+  auto mix = [&](const void* p, size_t bytes) {
+    const unsigned char* c = reinterpret_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ULL;
+  };
+  mix(&nmat, sizeof nmat);
+  const int fl = f16 ? 1 : 0;
+  mix(&fl, sizeof fl);
+  const std::vector<GroupMember> g = plan_group(mats, nmat, offsets, f16);
+  for (int i = 0; i < nmat; ++i) {
+    const DevMat d = dev_mat(mats[i]);
+    mix(&d, sizeof d);
+    mix(&g[i].p.tg, sizeof g[i].p.tg);
+    mix(&g[i].p.grid, sizeof g[i].p.grid);
+    mix(&g[i].q0, sizeof g[i].q0);
+    mix(&g[i].n, sizeof g[i].n);
+    const void* ptrs[] = {fused[i].lat_fwd, fused[i].wpack, fused[i].mlp, fused[i].targets, fused[i].lat_grad,
+                          fused[i].workspace, fused[i].loss_scale, fused[i].overflow_flag, adam[i].latents,
+                          adam[i].lat_m, adam[i].lat_v, adam[i].mlp_m, adam[i].mlp_v, adam[i].scale_state};
+    mix(ptrs, sizeof ptrs);
+  }
+  return h;
+}
+
+void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16, const TrainLaunch* fused,
+                      const AdamLaunch* adam, unsigned long long hash, void* host_table) {
+  char* t = reinterpret_cast<char*>(host_table);
+  std::memset(t, 0, train_table_bytes(nmat));
+  std::memcpy(t, &hash, sizeof hash);
+  const std::vector<GroupMember> g = plan_group(mats, nmat, offsets, f16);
+  TrainEntry* ent = reinterpret_cast<TrainEntry*>(t + kGroupHeaderBytes);
+  for (int i = 0; i < nmat; ++i) {
+    const ntc_material& m = mats[i];
+    const TrainPlan& p = g[i].p;
+    TrainEntry& e = ent[i];
+    char* ws = (char*)fused[i].workspace;
+    e.m = dev_mat(m);
+    e.tg = p.tg;
+    e.bin.q = nullptr;
+    e.bin.n = g[i].n;
+    e.bin.per_block = p.per_bin_block;
+    e.bin.nbb = p.nbb;
+    e.bin.counts = (int*)(ws + p.off_counts);
+    e.bin.offsets = (const int*)(ws + p.off_offsets);
+    e.bin.base = (const int*)(ws + p.off_base);
+    e.bin.list = (int4*)(ws + p.off_list);
+    e.adam.a = adam[i];
+    e.adam.a.mlp_grad = (const float*)(ws + p.off_grad);
+    e.adam.pg = pack_geom(m.c0, m.c1, m.hidden, f16);
+    e.adam.P = m.mlp_params;
+    e.adam.mlp_blocks = (int)((m.mlp_params + 255) / 256);
+    e.q0 = g[i].q0;
+    e.P = m.mlp_params;
+    e.nbins = p.nbins;
+    e.ntiles = p.ntiles;
+    e.region_max = p.region_max;
+    e.fused_grid = p.grid;
+    e.dw1_x = (int)((m.mlp_params + 63) / 64);
+    e.loss_norm = 1.0f / (float)((double)g[i].n * m.channels);
+    e.offsets = (int*)(ws + p.off_offsets);
+    e.total = (int*)(ws + p.off_total);
+    e.base = (int*)(ws + p.off_base);
+    e.tstart = (int*)(ws + p.off_tstart);
+    e.ttotal = (int*)(ws + p.off_ttotal);
+    e.ibase = (int*)(ws + p.off_ibase);
+    e.itile = (int*)(ws + p.off_itile);
+    e.nitems = (int*)(ws + p.off_misc);
+    e.part_lat = (const float*)(ws + p.off_part_lat);
+    e.lat_grad = fused[i].lat_grad;
+    e.part_dw = (const float*)(ws + p.off_part_dw);
+    e.tmp = (float*)(ws + p.off_tmp);
+    e.grad = (float*)(ws + p.off_grad);
+    e.part_loss = (const float*)(ws + p.off_part_loss);
+    e.loss_out = adam[i].loss_out;
+    e.overflow = fused[i].overflow_flag;
+  }
+}
+
+// One grouped launch per stage (and per kTrainGroup materials); blocks(i) gives the
+// blocks of material i.
+template <typename Blocks, typename Launch>
+static hipError_t group_launch(int nmat, unsigned long long hash, Blocks&& blocks, Launch&& launch) {
+  for (int f = 0; f < nmat; f += kTrainGroup) {
+    TrainSegs sg{};
+    sg.hash = hash;
+    sg.first = f;
+    sg.count = std::min(kTrainGroup, nmat - f);
+    int total = 0;
+    for (int i = 0; i < sg.count; ++i) {
+      sg.block0[i] = total;
+      total += blocks(f + i);
+    }
+    sg.block0[sg.count] = total;
+    if (total == 0) continue;
+    launch(sg, total);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16,
+                                const void* table, unsigned long long hash, const ntc_query* q, bool scatter,
+                                const TrainLaunch* fused, const AdamLaunch& hot, hipStream_t s) {
+  const char* tab = reinterpret_cast<const char*>(table);
+  const std::vector<GroupMember> g = plan_group(mats, nmat, offsets, f16);
+  int max_bins = 0;
+  for (int i = 0; i < nmat; ++i) max_bins = std::max(max_bins, g[i].p.nbins);
+  hipError_t e = hipSuccess;
+  auto run = [&](auto blocks, auto launch) {
+    if (e == hipSuccess) e = group_launch(nmat, hash, blocks, launch);
+  };
+  if (scatter) {
+    const size_t lds = (size_t)max_bins * 4;
+    run([&](int i) { return g[i].p.nbb; },
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<false>, dim3(n), dim3(256), lds, s, tab, sg, q); });
+    run([&](int i) { return (g[i].p.nbins + 3) / 4; },
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_scan1_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
+    run([&](int) { return 1; },
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_scan2_grouped, dim3(n), dim3(1024), 0, s, tab, sg); });
+    run([&](int i) { return g[i].p.nbb; },
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<true>, dim3(n), dim3(256), lds, s, tab, sg, q); });
+  }
+  for (int i = 0; i < nmat && e == hipSuccess; ++i) {
+    TrainLaunch l = fused[i];
+    l.table_hash = reinterpret_cast<const unsigned long long*>(tab);
+    l.hash = hash;
+    e = launch_train_fused(mats[i], f16, g[i].p, l, s);
+  }
+  if (scatter)
+    run([&](int i) { return g[i].p.ntiles; },
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(lat_partial_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
+  run([&](int i) { return (int)((mats[i].mlp_params + 63) / 64) * kDwYBlocks; },
+      [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(dw_reduce1_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
+  run([&](int i) { return (int)std::max<long long>(1, std::min<long long>((mats[i].mlp_params + 255) / 256, 1024)); },
+      [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(dw_reduce2_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
+  AdamHot h;
+  h.lr_lat = hot.lr_lat;
+  h.lr_mlp = hot.lr_mlp;
+  h.beta1 = hot.beta1;
+  h.beta2 = hot.beta2;
+  h.eps = hot.eps;
+  h.bc1 = hot.bc1;
+  h.bc2 = hot.bc2;
+  h.next_key = hot.next_key;
+  h.seed = hot.seed;
+  h.step = hot.step;
+  h.noise = hot.noise;
+  h.freeze = hot.freeze;
+  h.growth = hot.growth;
+  h.step_dev = hot.step_dev;
+  h.lr_dev = hot.lr_dev;
+  run([&](int i) { return (int)((mats[i].mlp_params + 255) / 256) + g[i].lat_blocks; },
+      [&](const TrainSegs& sg, int n) {
+        if (f16) hipLaunchKernelGGL(adam_grouped<_Float16>, dim3(n), dim3(256), 0, s, tab, sg, h);
+        else hipLaunchKernelGGL(adam_grouped<float>, dim3(n), dim3(256), 0, s, tab, sg, h);
+      });
+  if (e == hipSuccess && hot.step_dev) e = launch_step_advance(hot.step_dev, s);
+  return e;
 }
 
 }  // namespace ntc

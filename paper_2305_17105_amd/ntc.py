@@ -100,6 +100,12 @@ _sig = {
                                      _P(C.c_int64), C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_crop_queries": (C.c_int, [_P(Material), C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                    C.c_void_p]),
+    "ntc_train_table_bytes": (C.c_size_t, [C.c_int32]),
+    "ntc_train_table_init": (C.c_int, [_P(Material), C.c_int32, _P(TrainStateC), _P(C.c_int64), _P(C.c_void_p),
+                                       C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]),
+    "ntc_train_step_grouped": (C.c_int, [_P(Material), C.c_int32, _P(TrainStateC), C.c_void_p, _P(C.c_int64),
+                                         _P(C.c_void_p), _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p,
+                                         C.c_void_p]),
     "ntc_decode_table_bytes": (C.c_size_t, [C.c_int32]),
     "ntc_decode_table_init": (C.c_int, [_P(Material), C.c_int32, _P(C.c_void_p), _P(C.c_void_p), C.c_int,
                                         C.c_void_p, C.c_size_t]),
@@ -294,6 +300,38 @@ def train_step_batched(mats, states, queries, offsets, targets, hp: HParams, wor
     _check(_lib.ntc_train_step_batched(_materials(mats), n, st, _ptr(queries), off, tg, C.byref(hp), _ptr(workspace),
                                        workspace.numel() * workspace.element_size(), _stream(stream)),
            "ntc_train_step_batched")
+
+
+class TrainTable:
+    """A grouped training step's device table (ntc_train_table_init) with the host
+    arrays the step passes again; the materials, states, targets and workspace stay
+    referenced."""
+
+    def __init__(self, mats, states, offsets, targets, precision, workspace, device="cuda"):
+        import torch
+        n = len(mats)
+        self.nmat = n
+        self.mats = _materials(mats)
+        self.states = (TrainStateC * n)()
+        for i, s in enumerate(states):
+            self.states[i] = s.c
+        self.offsets = (C.c_int64 * (n + 1))(*[int(o) for o in offsets])
+        self.targets = (C.c_void_p * n)(*[_ptr(t) for t in targets])
+        self.workspace = workspace
+        self._keep = (list(states), list(targets))
+        nbytes = int(_lib.ntc_train_table_bytes(n))
+        self.table = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        _check(_lib.ntc_train_table_init(self.mats, n, self.states, self.offsets, self.targets, precision,
+                                         _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                         _ptr(self.table), nbytes), "ntc_train_table_init")
+
+
+def train_step_grouped(table: TrainTable, queries, hp: HParams, stream=None):
+    """ntc_train_step_batched's step with one launch per stage for the whole group."""
+    ws = table.workspace
+    _check(_lib.ntc_train_step_grouped(table.mats, table.nmat, table.states, _ptr(queries), table.offsets,
+                                       table.targets, C.byref(hp), _ptr(ws), ws.numel() * ws.element_size(),
+                                       _ptr(table.table), _stream(stream)), "ntc_train_step_grouped")
 
 
 def decode_batched(mats, packed, wpacks, precision, queries, offsets, out, out_dtype, stream=None):

@@ -141,3 +141,20 @@ def test_decode_table_sizes_and_validation():
     off = (C.c_int64 * 2)(0, 0)
     st = ntc._lib.ntc_decode_grouped(mats, 1, None, ntc.F16, None, off, None, ntc.F16, None)
     assert st == ntc.E_INVALID
+
+
+def test_train_table_validation():
+    """Grouped-training set-up rejects missing arguments before touching a device."""
+    import ctypes as C
+    from paper_2305_17105_amd import ntc
+    assert ntc._lib.ntc_train_table_bytes(0) == 0
+    assert ntc._lib.ntc_train_table_bytes(2) > ntc._lib.ntc_train_table_bytes(1) > 256
+    m = ntc.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    off = (C.c_int64 * 2)(0, 100)
+    tg = (C.c_void_p * 1)(None)
+    st = ntc._lib.ntc_train_table_init(ntc._materials([m]), 1, None, off, tg, ntc.F16, None, 0, None, 0)
+    assert st == ntc.E_INVALID
+    hp = ntc.hparams(precision=ntc.F16)
+    st = ntc._lib.ntc_train_step_grouped(ntc._materials([m]), 1, None, None, off, tg, C.byref(hp), None, 0, None,
+                                         None)
+    assert st == ntc.E_INVALID

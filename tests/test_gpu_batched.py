@@ -269,3 +269,143 @@ def test_grouped_decode_table_of_other_materials_decodes_nothing(lib):
     lib.decode_grouped(t2, q, offsets, out, lib.F16)
     torch.cuda.synchronize()
     assert bool((out == 7.0).all())
+
+
+def _grouped_vs_batched(lib, P, mats, ns, seed, steps=2):
+    """Runs `steps` steps of the batched and of the grouped step from the same start;
+    returns both state lists."""
+    import torch
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    qs = [synth.random_queries(seed + i, n, int(mats[i][0].num_mips)) for i, n in enumerate(ns)]
+    qall = queries_dev(np.concatenate(qs))
+    ms = [x[0] for x in mats]
+    tg = [x[4] for x in mats]
+    out = []
+    for grouped in (False, True):
+        st = _states(lib, mats, P)
+        ws = torch.zeros(lib.train_workspace_bytes_batched(ms, offsets, P), dtype=torch.uint8, device="cuda")
+        table = lib.TrainTable(ms, st, offsets, tg, P, ws) if grouped else None
+        for step in range(steps):
+            hp = lib.hparams(precision=P, step=step, lr_latent=0.01, lr_mlp=0.005, seed=seed)
+            if step == 0:
+                for m, s in zip(ms, st):
+                    lib.train_prepare(m, s, hp)
+            if grouped:
+                lib.train_step_grouped(table, qall, hp)
+            else:
+                lib.train_step_batched(ms, st, qall, offsets, tg, hp, ws)
+        torch.cuda.synchronize()
+        out.append(st)
+    return out
+
+
+def _assert_states_close(sb, sg, tol, steps=2, lr=0.01):
+    """Equal up to the order of floating-point additions (samples enter a tile's list
+    in LDS-atomic order): at least 99.9% of every buffer within `tol` of its largest
+    magnitude, and every parameter within 2 lr per step, the most an Adam step can move
+    a parameter whose gradient is at rounding level (the update is then
+    -lr g / |g| of a sign that rounding decides)."""
+    for i in range(len(sb)):
+        for name in ("latents", "latents_fwd", "mlp", "lat_m", "mlp_v", "loss"):
+            a = getattr(sb[i], name).cpu().numpy().astype(np.float64)
+            b = getattr(sg[i], name).cpu().numpy().astype(np.float64)
+            d = np.abs(a - b) / max(np.max(np.abs(b)), 1e-30)
+            assert np.mean(d <= tol) >= 0.999, (i, name, float(np.max(d)))
+            if name in ("latents", "latents_fwd", "mlp"):
+                assert np.max(np.abs(a - b)) <= 2 * lr * steps, (i, name)
+            else:
+                assert np.max(d) <= 1e-3, (i, name, float(np.max(d)))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_grouped_train_equals_batched(lib, prec):
+    """The grouped step (one launch per stage) gives the batched step's states."""
+    P = lib.F32 if prec == "f32" else lib.F16
+    mats = [_material(lib, W, C, hd, 140 + i) for i, (W, C, hd, _) in enumerate(SHAPES)]
+    sb, sg = _grouped_vs_batched(lib, P, mats, [n for (_, _, _, n) in SHAPES], 150)
+    # same kernels on the same data; only the order of floating-point atomics differs
+    _assert_states_close(sb, sg, 1e-5)
+
+
+def test_grouped_train_more_members_than_one_launch(lib):
+    """70 small materials (two launches per stage) trained grouped and batched."""
+    mats = [_material(lib, 64 if i % 3 else 128, 8, 32 if i % 2 else 64, 300 + i) for i in range(70)]
+    ns = [200 + 37 * (i % 11) for i in range(70)]
+    sb, sg = _grouped_vs_batched(lib, lib.F16, mats, ns, 310)
+    _assert_states_close(sb, sg, 1e-5)
+
+
+def test_grouped_train_table_of_other_group_does_nothing(lib):
+    """A table built for other sample groups: the step leaves every state as it was."""
+    import torch
+    mats = [_material(lib, W, C, hd, 160 + i) for i, (W, C, hd, _) in enumerate(SHAPES)]
+    ms = [x[0] for x in mats]
+    ns = [n for (_, _, _, n) in SHAPES]
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    other = np.concatenate([[0], np.cumsum([n + 1 for n in ns])])
+    st = _states(lib, mats, lib.F16)
+    hp = lib.hparams(precision=lib.F16, step=0, lr_latent=0.01, lr_mlp=0.005, seed=4)
+    for m, s in zip(ms, st):
+        lib.train_prepare(m, s, hp)
+    ws = torch.zeros(lib.train_workspace_bytes_batched(ms, other, lib.F16), dtype=torch.uint8, device="cuda")
+    table = lib.TrainTable(ms, st, offsets, [x[4] for x in mats], lib.F16, ws)
+    table.offsets = (lib.C.c_int64 * (len(ms) + 1))(*[int(o) for o in other])
+    before = [s.latents.clone() for s in st]
+    q = queries_dev(synth.random_queries(161, int(other[-1]), int(ms[0].num_mips)))
+    lib.train_step_grouped(table, q, hp)
+    torch.cuda.synchronize()
+    for s, b in zip(st, before):
+        assert torch.equal(s.latents, b)
+
+
+def test_grouped_graph_replay_matches_eager(lib):
+    """A captured grouped step (device step index and learning rates) replayed three
+    times, with eager work between replays, matches eager grouped steps."""
+    import torch
+    P = lib.F16
+    mats = [_material(lib, W, C, hd, 170 + i) for i, (W, C, hd, _) in enumerate(SHAPES)]
+    ms = [x[0] for x in mats]
+    ns = [n for (_, _, _, n) in SHAPES]
+    offsets = np.concatenate([[0], np.cumsum(ns)])
+    q = queries_dev(np.concatenate([synth.random_queries(180 + i, n, int(ms[i].num_mips)) for i, n in enumerate(ns)]))
+    tg = [x[4] for x in mats]
+    lr = [(0.01 * (1 - 0.1 * s), 0.005 * (1 - 0.1 * s)) for s in range(3)]
+    runs = []
+    for graph in (False, True):
+        st = _states(lib, mats, P)
+        ws = torch.zeros(lib.train_workspace_bytes_batched(ms, offsets, P), dtype=torch.uint8, device="cuda")
+        table = lib.TrainTable(ms, st, offsets, tg, P, ws)
+        step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+        lr_dev = torch.tensor(lr[0], dtype=torch.float32, device="cuda")
+        hp = lib.hparams(precision=P, step=0, seed=6, step_dev=step_dev, lr_dev=lr_dev)
+        for m, s in zip(ms, st):
+            lib.train_prepare(m, s, hp)
+        torch.cuda.synchronize()
+        if graph:
+            g = torch.cuda.CUDAGraph()
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                with torch.cuda.graph(g, stream=stream):
+                    lib.train_step_grouped(table, q, hp)
+            torch.cuda.synchronize()
+            assert int(step_dev.item()) == 0
+        snaps = []
+        for s in range(3):
+            lr_dev.copy_(torch.tensor(lr[s], dtype=torch.float32))
+            if graph:
+                g.replay()
+            else:
+                lib.train_step_grouped(table, q, hp)
+            torch.cuda.synchronize()
+            _ = torch.ones(1024, device="cuda").sum().item()
+            assert int(step_dev.item()) == s + 1
+            snaps.append([{k: getattr(x, k).clone() for k in ("latents", "mlp", "loss")} for x in st])
+        runs.append(snaps)
+    for s in range(3):
+        for i in range(len(ms)):
+            for k, v in runs[0][s][i].items():
+                a = runs[1][s][i][k].double()
+                d = (a - v.double()).abs() / max(float(v.double().abs().max()), 1e-30)
+                # order of floating-point additions only (see _assert_states_close)
+                assert float((d <= 1e-4).double().mean()) >= 0.999, (s, i, k)
+                assert float((a - v.double()).abs().max()) <= 2 * 0.01 * (s + 1), (s, i, k)

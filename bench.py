@@ -279,6 +279,34 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
         res[f"psnr_mip0_{name}"] = round(-10.0 * math.log10(mse), 3)
     log(f"[bench] decode PSNR of mip 0: f32 {res['psnr_mip0_f32']} dB, f16 {res['psnr_mip0_f16']} dB, "
         f"fp8 {res['psnr_mip0_fp8']} dB")
+    # filtered decode (FP16): the same random positions with a continuous LOD
+    r = np.random.default_rng(seed + 6)
+    fq = np.zeros(nq, dtype=[("u", "<f4"), ("v", "<f4"), ("lod", "<f4")])
+    fq["u"] = r.random(nq, dtype=np.float32)
+    fq["v"] = r.random(nq, dtype=np.float32)
+    fq["lod"] = r.random(nq, dtype=np.float32) * np.float32(m.num_mips - 1)
+    fq_dev = torch.from_numpy(fq.view(np.uint8).copy()).cuda()
+    del fq
+    wp = torch.zeros(ntc.mlp_packed_bytes(m, ntc.F16), dtype=torch.uint8, device="cuda")
+    ntc.pack_mlp(m, mlp, ntc.F16, wp)
+    for name, mode, taps in (("bilinear", ntc.FILTER_BILINEAR, 4), ("trilinear", ntc.FILTER_TRILINEAR, 8),
+                             ("stochastic", ntc.FILTER_STOCHASTIC, 1)):
+        call = lambda: ntc.decode_filtered(m, packed, wp, ntc.F16, fq_dev, nq, mode, out, ntc.F16, seed=3)
+        for _ in range(2):
+            call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"filtered_{name}_f16"] = dict(outputs=nq, texels_decoded=nq * taps, ms=round(ms, 4),
+                                          outputs_per_s=nq / (ms * 1e-3),
+                                          cost_vs_point_decode=round(ms / res["random_f16"]["ms"], 3))
+        log(f"[bench] decode filtered {name} f16: {ms:.3f} ms for {nq} outputs ({taps} texels each) -> "
+            f"{nq / (ms * 1e-3):.3e} outputs/s, {ms / res['random_f16']['ms']:.2f}x a point decode")
     return res
 
 

@@ -163,6 +163,34 @@ ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents,
                            int32_t height, void* out, ntc_dtype out_dtype, void* stream);
 
 /*
+ * Filtered decode (section 5.3, Filtering): the network is fitted at discrete texels
+ * and mips only, so filtering is done in software on decoded texels.  A filter query
+ * has a continuous mip level `lod` (clamped to [0, num_mips - 1]; NaN -> 0); u, v as
+ * for ntc_decode.  Modes:
+ *   NTC_FILTER_BILINEAR: mip l = floor(lod + 1/2); with x = u W_l - 1/2, x0 = floor(x),
+ *     fx = x - x0 (y likewise), the texels (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1)
+ *     (clamped to the mip) weighted (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx fy: 4 decodes.
+ *   NTC_FILTER_TRILINEAR: bilinear in mips l0 = floor(lod) and min(l0 + 1, M - 1),
+ *     weighted 1 - t and t with t = lod - l0: 8 decodes.
+ *   NTC_FILTER_STOCHASTIC: one decode.  With SplitMix64 counters key = mix(seed ^
+ *     0x66696C74), h1 = mix(key + gamma (2i + 1)), h2 = mix(key + gamma (2i + 2)) for
+ *     output i, and r1 = (h1 >> 40) 2^-24, r2 = ((h1 >> 16) & (2^24 - 1)) 2^-24,
+ *     r3 = (h2 >> 40) 2^-24: mip l = l0 + (r3 < lod - l0) (at most M - 1), then the
+ *     nearest texel of mip l at (u + (r1 - 1/2) / W_l, v + (r2 - 1/2) / H_l), i.e. a
+ *     uniform jitter of up to half a texel (bilinear filtering in expectation).
+ * Built for NTC_F16 decode packs (NTC_E_UNSUPPORTED otherwise); out holds n x C values.
+ */
+typedef struct {
+  float u, v, lod;
+} ntc_filter_query;
+
+typedef enum { NTC_FILTER_BILINEAR = 1, NTC_FILTER_TRILINEAR = 2, NTC_FILTER_STOCHASTIC = 3 } ntc_filter;
+
+ntc_status ntc_decode_filtered(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                               ntc_dtype precision, const ntc_filter_query* q, int64_t n, int32_t filter,
+                               uint64_t seed, void* out, ntc_dtype out_dtype, void* stream);
+
+/*
  * Training (autodecoder, section 4; optimiser section 4.5 and section 5.1).
  * State buffers (all caller-owned device memory):
  *   latents      latent_count  FP32 masters

@@ -22,7 +22,8 @@ __all__ = [
     "mlp_param_count", "activation", "activation_grad", "mlp_forward", "decode",
     "loss_and_grads", "adam_update", "train_step", "loss_scale_update", "psnr",
     "storage_bytes_paper", "hard_gelu", "E4M3_MAX", "e4m3_value", "round_e4m3", "fp8_layer_scales",
-    "mlp_forward_fp8", "decode_fp8", "crop_lod", "crop_queries",
+    "mlp_forward_fp8", "decode_fp8", "crop_lod", "crop_queries", "FILTER_BILINEAR", "FILTER_TRILINEAR",
+    "FILTER_STOCHASTIC", "FILTER_QUERY", "filter_randoms", "filter_taps", "decode_filtered",
 ]
 
 GAMMA = 0x9E3779B97F4A7C15
@@ -670,3 +671,108 @@ def psnr(ref_mips, test_mips):
         se += float(np.sum((r - t) ** 2))
         count += r.size
     return -10.0 * math.log10(se / count)
+
+
+# --------------------------------------------------------------------------------------
+# Filtered decode: section 5.3 (Filtering).  The network is fitted at discrete texels and
+# mips only, so texture filtering combines decoded texels: bilinear (4 texels of the
+# nearest mip), trilinear (bilinear in the two mips around a continuous LOD, blended),
+# and stochastic filtering (one texel after a uniform jitter of up to half a texel of the
+# position and a random choice between the two mips).  Positions are computed in float32
+# (the arithmetic the decoder's texel addressing uses, so both pick the same texels);
+# the combination is float64.  The random numbers of stochastic filtering are SplitMix64
+# outputs of counters: key = mix(seed ^ FILTER_TAG), h1 = mix(key + gamma (2i + 1)),
+# h2 = mix(key + gamma (2i + 2)) for output i; r1 = (h1 >> 40) 2^-24,
+# r2 = ((h1 >> 16) & (2^24 - 1)) 2^-24, r3 = (h2 >> 40) 2^-24.
+# --------------------------------------------------------------------------------------
+FILTER_BILINEAR, FILTER_TRILINEAR, FILTER_STOCHASTIC = 1, 2, 3
+FILTER_TAG = 0x66696C74
+FILTER_QUERY = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<f4")])
+_QREC = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
+
+
+def _filter_inputs(geom: Geometry, fq):
+    f32 = np.float32
+    u = np.where(np.isnan(fq["u"]), f32(0), fq["u"]).astype(f32)
+    v = np.where(np.isnan(fq["v"]), f32(0), fq["v"]).astype(f32)
+    lod = np.where(np.isnan(fq["lod"]), f32(0), fq["lod"]).astype(f32)
+    lf = np.minimum(np.maximum(lod, f32(0)), f32(geom.M - 1))
+    return u, v, lf
+
+
+def _bilinear_taps(geom: Geometry, u, v, l):
+    """The four texel centres around (u, v) in mip l (clamped) and their weights."""
+    f32 = np.float32
+    W = np.array([geom.mip_w[i] for i in range(geom.M)], dtype=np.int64)[l]
+    H = np.array([geom.mip_h[i] for i in range(geom.M)], dtype=np.int64)[l]
+    x = u * W.astype(f32) - f32(0.5)
+    y = v * H.astype(f32) - f32(0.5)
+    x0, y0 = np.floor(x), np.floor(y)
+    fx, fy = (x - x0).astype(np.float64), (y - y0).astype(np.float64)
+    taps, wts = [], []
+    for dy in (0, 1):
+        for dx in (0, 1):
+            xi = np.clip(x0.astype(np.int64) + dx, 0, W - 1)
+            yi = np.clip(y0.astype(np.int64) + dy, 0, H - 1)
+            taps.append(((xi.astype(f32) + f32(0.5)) / W.astype(f32), (yi.astype(f32) + f32(0.5)) / H.astype(f32)))
+            wts.append((fx if dx else 1.0 - fx) * (fy if dy else 1.0 - fy))
+    return taps, wts
+
+
+def filter_randoms(seed: int, n: int):
+    """(r1, r2, r3) of outputs 0..n-1, each in [0, 1) with 24 bits, as float32."""
+    key = int(splitmix64_mix(np.uint64((seed ^ FILTER_TAG) & MASK64)))
+    i = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        h1 = splitmix64_mix(np.uint64(key) + np.uint64(GAMMA) * (np.uint64(2) * i + np.uint64(1)))
+        h2 = splitmix64_mix(np.uint64(key) + np.uint64(GAMMA) * (np.uint64(2) * i + np.uint64(2)))
+    s = np.float32(2.0 ** -24)
+    r1 = (h1 >> np.uint64(40)).astype(np.float32) * s
+    r2 = ((h1 >> np.uint64(16)) & np.uint64(0xFFFFFF)).astype(np.float32) * s
+    r3 = (h2 >> np.uint64(40)).astype(np.float32) * s
+    return r1, r2, r3
+
+
+def filter_taps(geom: Geometry, fq, mode: int, seed: int = 0):
+    """Point queries (QUERY records) [n, T] and float64 weights [n, T] that filtered output
+    i combines: T = 4 (bilinear), 8 (trilinear) or 1 (stochastic)."""
+    f32 = np.float32
+    u, v, lf = _filter_inputs(geom, fq)
+    n = len(u)
+    l0 = np.floor(lf).astype(np.int64)
+    if mode == FILTER_BILINEAR:
+        levels = [np.minimum(np.floor(lf + f32(0.5)).astype(np.int64), geom.M - 1)]
+        blend = [np.ones(n)]
+    elif mode == FILTER_TRILINEAR:
+        t = (lf - l0.astype(f32)).astype(np.float64)
+        levels = [l0, np.minimum(l0 + 1, geom.M - 1)]
+        blend = [1.0 - t, t]
+    elif mode == FILTER_STOCHASTIC:
+        r1, r2, r3 = filter_randoms(seed, n)
+        l = np.minimum(l0 + (r3 < (lf - l0.astype(f32))).astype(np.int64), geom.M - 1)
+        W = np.array(geom.mip_w, dtype=np.int64)[l].astype(f32)
+        H = np.array(geom.mip_h, dtype=np.int64)[l].astype(f32)
+        q = np.zeros((n, 1), dtype=_QREC)
+        q["u"][:, 0] = u + (r1 - f32(0.5)) / W
+        q["v"][:, 0] = v + (r2 - f32(0.5)) / H
+        q["lod"][:, 0] = l
+        return q, np.ones((n, 1))
+    else:
+        raise ValueError("unknown filter")
+    cols, wcols = [], []
+    for l, b in zip(levels, blend):
+        taps, wts = _bilinear_taps(geom, u, v, l)
+        for (tu, tv), w in zip(taps, wts):
+            rec = np.zeros(n, dtype=_QREC)
+            rec["u"], rec["v"], rec["lod"] = tu, tv, l
+            cols.append(rec)
+            wcols.append(w * b)
+    return np.stack(cols, axis=1), np.stack(wcols, axis=1)
+
+
+def decode_filtered(geom: Geometry, lat, params, fq, mode: int, seed: int = 0):
+    """Filtered outputs [n, C]: the weighted sum of the decoded taps (section 5.3)."""
+    q, w = filter_taps(geom, fq, mode, seed)
+    n, T = q.shape
+    y = decode(geom, lat, params, q.reshape(-1)).reshape(n, T, geom.C)
+    return np.einsum("nt,ntc->nc", w, y)

@@ -158,16 +158,73 @@ __device__ inline void store_out(void* __restrict__ out, int out_f16, long long 
   }
 }
 
+// Filtered decode (section 5.3): texel filtering done in software by decoding the
+// texels it combines.  FILT 1: bilinear, the 4 texels around (u, v) in the nearest mip;
+// FILT 2: trilinear, bilinear in the two mips around lod blended by its fraction (8
+// texels); FILT 3: stochastic, one texel after a uniform jitter of (u, v) by up to half
+// a texel and a random choice between the two mips around lod.  TAPS texels feed one
+// output; tap k of output s at position (u, v), integer mip lod, weight wt.
+template <int FILT>
+constexpr int filter_taps() { return FILT == 1 ? 4 : FILT == 2 ? 8 : 1; }
+
+constexpr uint64_t kFilterTag = 0x66696C74ull;  // "filt"
+
+// Bilinear tap k (dx = k & 1, dy = k >> 1) of (fu, fv) in mip l: texel centre and weight.
+__device__ inline void bilinear_tap(const DevMat& m, float fu, float fv, int l, int k, float& u, float& v,
+                                    float& wt) {
+  const int W = m.mip_w[l], H = m.mip_h[l];
+  const float x = fu * (float)W - 0.5f, y = fv * (float)H - 0.5f;
+  const float x0 = floorf(x), y0 = floorf(y);
+  const float fx = x - x0, fy = y - y0;
+  const int xi = min(max((int)x0 + (k & 1), 0), W - 1), yi = min(max((int)y0 + (k >> 1), 0), H - 1);
+  u = ((float)xi + 0.5f) / (float)W;
+  v = ((float)yi + 0.5f) / (float)H;
+  wt = ((k & 1) ? fx : 1.f - fx) * ((k >> 1) ? fy : 1.f - fy);
+}
+
+template <int FILT>
+__device__ inline void filter_tap(const DevMat& m, const ntc_filter_query& fq, long long s, int k, uint64_t key,
+                                  float& u, float& v, int& lod, float& wt) {
+  float fu = fq.u, fv = fq.v;
+  if (!(fu == fu)) fu = 0.f;  // NaN -> 0, as for point queries
+  if (!(fv == fv)) fv = 0.f;
+  const float lf = fminf(fmaxf(fq.lod, 0.f), (float)(m.M - 1));  // NaN -> 0
+  const int l0 = (int)floorf(lf);
+  if constexpr (FILT == 1) {
+    lod = min((int)floorf(lf + 0.5f), m.M - 1);
+    bilinear_tap(m, fu, fv, lod, k, u, v, wt);
+  } else if constexpr (FILT == 2) {
+    const int l1 = min(l0 + 1, m.M - 1);
+    const float t = lf - (float)l0;
+    lod = k < 4 ? l0 : l1;
+    bilinear_tap(m, fu, fv, lod, k & 3, u, v, wt);
+    wt *= k < 4 ? 1.f - t : t;
+  } else {
+    const uint64_t h1 = mix64(key + kGamma * (uint64_t)(2 * s + 1)), h2 = mix64(key + kGamma * (uint64_t)(2 * s + 2));
+    const float r1 = (float)(uint32_t)(h1 >> 40) * 0x1p-24f, r2 = (float)(uint32_t)((h1 >> 16) & 0xFFFFFFu) * 0x1p-24f;
+    const float r3 = (float)(uint32_t)(h2 >> 40) * 0x1p-24f;
+    lod = min(l0 + (r3 < lf - (float)l0 ? 1 : 0), m.M - 1);
+    u = fu + (r1 - 0.5f) / (float)m.mip_w[lod];
+    v = fv + (r2 - 0.5f) / (float)m.mip_h[lod];
+    wt = 1.f;
+  }
+}
+
 // PACKED: latents come as bit-packed codes (ntc_decode); otherwise as FP32 values
 // in the canonical latent layout (ntc_forward, the differentiation path).
 // bias: b1 (HD), b2 (HD), b3 (C) at the three given addresses.
 // bi, nb: this block's index among the nb blocks that share the n queries.
-template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT>
+// FILT (packed codes only): 0 point queries (ntc_query), else the filter above over n
+// outputs of ntc_filter_query records; fkey: the stochastic filter's counter key.
+template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED, int ACT, int FILT = 0>
 __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, const void* __restrict__ src,
                                             const T* __restrict__ wpack, const float* __restrict__ bias1,
                                             const float* __restrict__ bias2, const float* __restrict__ bias3,
                                             const ntc_query* __restrict__ q, long long n, const TexelRect& rect,
-                                            void* __restrict__ out, int out_f16, int bi, int nb) {
+                                            void* __restrict__ out, int out_f16, int bi, int nb,
+                                            uint64_t fkey = 0) {
+  static_assert(FILT == 0 || PACKED, "filtered decode reads packed codes");
+  constexpr int TAPS = filter_taps<FILT>();
   const uint32_t* __restrict__ packed = reinterpret_cast<const uint32_t*>(src);
   const float* __restrict__ lat = reinterpret_cast<const float*>(src);
   using IS = InSlots<C0, C1>;
@@ -189,11 +246,12 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const long long tiles = (n + 15) / 16, stride = (long long)nb * 4;
+  const long long tiles = (n * TAPS + 15) / 16, stride = (long long)nb * 4;
 
-  // three layers on one tile's assembled inputs, then the store
-  auto mlp_store = [&](T (&xs)[S1], long long tile) {
-    const long long s = tile * 16 + r;
+  // three layers on one tile's assembled inputs, then the store (filters: the weighted
+  // taps of an output are summed across its TAPS lanes first)
+  auto mlp_store = [&](T (&xs)[S1], long long tile, float wt) {
+    const long long s = tile * (16 / TAPS) + r / TAPS;
     f32x4 acc[MT];
 #pragma unroll
     for (int mo = 0; mo < MT; ++mo) {
@@ -213,6 +271,16 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
     // layer 3 (no activation): lane group g holds channels 4g .. 4g+3
     f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
     y = mma_slots<SH>(y, w_lds + pg.L3, h, lane);
+    if constexpr (TAPS > 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float t = y[i] * wt;
+#pragma unroll
+        for (int o = 1; o < TAPS; o <<= 1) t += __shfl_xor(t, o);
+        y[i] = t;
+      }
+      if (r % TAPS != 0) return;
+    }
     store_out<C>(out, out_f16, s, n, g, y);
   };
   auto pe_slots = [&](T (&xs)[S1], int ix, int iy) {
@@ -224,18 +292,25 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
     for (int t = pg.T_used; t < S1; ++t) xs[t] = (T)0.f;
   };
   // query record of this lane's texel of a tile (zeros past the end)
-  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
-    const long long s = tile * 16 + r;
+  auto load_query = [&](long long tile, float& u, float& v, int& lod, float& wt) {
     u = v = 0.f;
     lod = 0;
-    if (tile < tiles && s < n) {
-      if (rect.w > 0) {
-        rect_query(rect, s, u, v, lod);
-      } else {
-        u = q[s].u;
-        v = q[s].v;
-        lod = q[s].lod;
+    wt = 1.f;
+    if constexpr (FILT == 0) {
+      const long long s = tile * 16 + r;
+      if (tile < tiles && s < n) {
+        if (rect.w > 0) {
+          rect_query(rect, s, u, v, lod);
+        } else {
+          u = q[s].u;
+          v = q[s].v;
+          lod = q[s].lod;
+        }
       }
+    } else {
+      const long long s = tile * (16 / TAPS) + r / TAPS;
+      if (tile < tiles && s < n)
+        filter_tap<FILT>(m, reinterpret_cast<const ntc_filter_query*>(q)[s], s, r % TAPS, fkey, u, v, lod, wt);
     }
   };
 
@@ -288,26 +363,29 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
 
     long long tile = (long long)bi * 4 + wave;
     if (tile >= tiles) return;
-    float u, v;
+    float u, v, wt;
     int lod;
-    load_query(tile, u, v, lod);
+    load_query(tile, u, v, lod, wt);
     Raw cur;
     cur.fetch(m, lb, packed, u, v, lod, g);
-    load_query(tile + stride, u, v, lod);
+    float cwt = wt;
+    load_query(tile + stride, u, v, lod, wt);
     for (; tile < tiles; tile += stride) {
       Raw nxt;
+      float nwt = wt;
       if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
-      if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
+      if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod, wt);
       T xs[S1];
       assemble(cur, xs);
-      mlp_store(xs, tile);
+      mlp_store(xs, tile, cwt);
       cur = nxt;
+      cwt = nwt;
     }
   } else {
     for (long long tile = (long long)bi * 4 + wave; tile < tiles; tile += stride) {
-      float u, v;
+      float u, v, wt;
       int lod;
-      load_query(tile, u, v, lod);
+      load_query(tile, u, v, lod, wt);
       const Footprint f = locate(m, u, v, lod, g);
       T xs[S1];
       const long long g0base = m.g0_off[f.j] + (long long)f.g0_cell * C0;
@@ -325,7 +403,7 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
         xs[C0 + i] = (T)acc;
       }
       pe_slots(xs, f.ix, f.iy);
-      mlp_store(xs, tile);
+      mlp_store(xs, tile, wt);
     }
   }
 }
@@ -339,6 +417,18 @@ __global__ __launch_bounds__(256) void decode_kernel(DevMat m, PeTable pe, const
                                                      TexelRect rect, void* __restrict__ out, int out_f16) {
   decode_body<T, C0, C1, C, HD, B0, B1, PACKED, ACT>(m, pe, src, wpack, bias1, bias2, bias3, q, n, rect, out, out_f16,
                                                      blockIdx.x, gridDim.x);
+}
+
+template <typename T, int C0, int C1, int C, int HD, int B0, int B1, int ACT, int FILT>
+__global__ __launch_bounds__(256) void decode_filtered_kernel(DevMat m, PeTable pe, const void* __restrict__ src,
+                                                              const T* __restrict__ wpack,
+                                                              const ntc_filter_query* __restrict__ fq, long long n,
+                                                              uint64_t key, void* __restrict__ out, int out_f16) {
+  constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, true>::WB;
+  const float* b1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
+  decode_body<T, C0, C1, C, HD, B0, B1, true, ACT, FILT>(m, pe, src, wpack, b1, b1 + HD, b1 + 2 * HD,
+                                                         reinterpret_cast<const ntc_query*>(fq), n, TexelRect{}, out,
+                                                         out_f16, blockIdx.x, gridDim.x, key);
 }
 
 // Segment of a grouped launch holding block b: the last one whose first block is <= b.

@@ -309,6 +309,22 @@ ntc_status ntc_decode_tile(const ntc_material* m, const uint8_t* packed_latents,
                     "ntc_decode_tile");
 }
 
+ntc_status ntc_decode_filtered(const ntc_material* m, const uint8_t* packed_latents, const void* mlp_packed,
+                               ntc_dtype precision, const ntc_filter_query* q, int64_t n, int32_t filter,
+                               uint64_t seed, void* out, ntc_dtype out_dtype, void* stream) {
+  ntc_status st = check_decode(m, precision, out_dtype);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "filtered decode is built for F16 decode packs");
+  if (filter != NTC_FILTER_BILINEAR && filter != NTC_FILTER_TRILINEAR && filter != NTC_FILTER_STOCHASTIC)
+    return fail(NTC_E_INVALID, "unknown filter");
+  if (n < 0 || n > ((int64_t)1 << 40)) return fail(NTC_E_INVALID, "n outside [0, 2^40]");
+  if (n == 0) return NTC_OK;
+  if (!packed_latents || !mlp_packed || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_decode_filtered(*m, packed_latents, mlp_packed, q, n, filter, seed, out,
+                                           out_dtype == NTC_F16, (hipStream_t)stream),
+                    "ntc_decode_filtered");
+}
+
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
   if (!m || n <= 0 || (precision != NTC_F32 && precision != NTC_F16)) return 0;
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden)) return 0;

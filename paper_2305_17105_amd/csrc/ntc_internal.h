@@ -42,6 +42,11 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
                          const ntc_query* q, long long n, const TexelRect* rect, void* out, bool out_f16,
                          hipStream_t s);
 
+// Filtered decode (FP16 decode packs): filter 1 bilinear, 2 trilinear, 3 stochastic.
+hipError_t launch_decode_filtered(const ntc_material& m, const uint8_t* packed, const void* wpack,
+                                  const ntc_filter_query* q, long long n, int filter, uint64_t seed, void* out,
+                                  bool out_f16, hipStream_t s);
+
 // Grouped decode: table entries, the hash that ties a table to its materials, and the
 // launches (one per kernel shape, at most kGroupSegs materials each).
 void fill_group_entry(const ntc_material& m, const void* packed, const void* wpack, GroupEntry& e);

@@ -21,6 +21,7 @@ _lib = C.CDLL(LIB_PATH)
 OK, E_INVALID, E_UNSUPPORTED, E_WORKSPACE, E_HIP = range(5)
 F32, F16, FP8_E4M3 = 0, 1, 2
 ACT_RELU, ACT_HARDGELU = 0, 1
+FILTER_BILINEAR, FILTER_TRILINEAR, FILTER_STOCHASTIC = 1, 2, 3
 MAX_LEVELS, MAX_MIPS = 8, 16
 
 QUERY_DTYPE = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
@@ -100,6 +101,8 @@ _sig = {
                                      _P(C.c_int64), C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_crop_queries": (C.c_int, [_P(Material), C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                    C.c_void_p]),
+    "ntc_decode_filtered": (C.c_int, [_P(Material), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                                      C.c_int32, C.c_uint64, C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_train_table_bytes": (C.c_size_t, [C.c_int32]),
     "ntc_train_table_init": (C.c_int, [_P(Material), C.c_int32, _P(TrainStateC), _P(C.c_int64), _P(C.c_void_p),
                                        C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]),
@@ -343,6 +346,14 @@ def decode_batched(mats, packed, wpacks, precision, queries, offsets, out, out_d
     wp = (C.c_void_p * n)(*[_ptr(w) for w in wpacks])
     _check(_lib.ntc_decode_batched(_materials(mats), n, pk, wp, precision, _ptr(queries), off, _ptr(out), out_dtype,
                                    _stream(stream)), "ntc_decode_batched")
+
+
+def decode_filtered(m: Material, packed, wpack, precision, fqueries, n, filt, out, out_dtype, seed=0, stream=None):
+    """Filtered decode of n filter queries (12-byte records u, v, lod as float32):
+    bilinear, trilinear or stochastic (ntc_decode_filtered)."""
+    _check(_lib.ntc_decode_filtered(C.byref(m), _ptr(packed), _ptr(wpack), precision, _ptr(fqueries), int(n),
+                                    int(filt), int(seed) & (2 ** 64 - 1), _ptr(out), out_dtype, _stream(stream)),
+           "ntc_decode_filtered")
 
 
 class DecodeTable:

@@ -242,3 +242,96 @@ def test_decode_full_size_sampled(lib, prec):
     err = np.max(np.abs(got - ref))
     print(f"full-size decode {prec} (FP16 output): max-abs err {err:.3e} on {len(pick)} sampled queries")
     assert err <= {"f32": 1e-3, "f16": 3e-3, "fp8": 3e-2}[prec]  # includes the FP16 rounding of the output
+
+
+FSHAPES = [  # W, C, c0, c1, b0, b1, hidden, n
+    (256, 8, 8, 8, 4, 4, 64, 3001),
+    (512, 16, 16, 16, 2, 4, 64, 2049),   # paired FP16 layout
+    (256, 10, 10, 10, 4, 4, 32, 777),    # C not a multiple of 4
+]
+FMODES = {"bilinear": 1, "trilinear": 2, "stochastic": 3}
+
+
+def _filter_queries(seed, n, M):
+    r = np.random.default_rng(seed)
+    fq = np.zeros(n, dtype=O.FILTER_QUERY)
+    fq["u"] = r.uniform(0, 1, n)
+    fq["v"] = r.uniform(0, 1, n)
+    fq["lod"] = r.uniform(0, M - 1, n)
+    k = min(n, 8)  # edges: borders, integer and out-of-range LODs, NaN
+    fq["u"][:k] = [0.0, 0.99999, 0.5, np.nan, 0.25, 1.0, -0.1, 0.75][:k]
+    fq["lod"][:k] = [0.0, M - 1, -2.0, 1.0, M + 3.0, np.nan, 0.5, 2.0][:k]
+    return fq
+
+
+def _fq_dev(fq):
+    import torch
+    return torch.from_numpy(fq.view(np.uint8).copy()).cuda()
+
+
+@pytest.mark.parametrize("mode", list(FMODES))
+@pytest.mark.parametrize("shape", FSHAPES)
+def test_decode_filtered_parity(lib, shape, mode):
+    """Filtered FP16 decode against the float64 oracle's weighted sum of decoded taps
+    (the same texels, chosen in the same float32 arithmetic) at the FP16 decode bar."""
+    import torch
+    W, C, c0, c1, b0, b1, hd, n = shape
+    m = lib.material_init(W, W, C, c0, c1, b0, b1, hd)
+    g = geometry(m)
+    raw = synth.uniform_latents(21, int(m.latent_count))
+    mlp = mlp_in_unit_range(21, g.K, hd, C)
+    packed = _packed(lib, m, raw)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, lib.F16), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), lib.F16, wp)
+    fq = _filter_queries(22, n, g.M)
+    out = torch.full((n * C,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode_filtered(m, packed, wp, lib.F16, _fq_dev(fq), n, FMODES[mode], out, lib.F32, seed=77)
+    torch.cuda.synchronize()
+    ref = O.decode_filtered(g, quantized_latents_oracle(g, raw), mlp, fq, FMODES[mode], seed=77).ravel()
+    err = np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref))
+    print(f"filtered {mode} {shape}: max-abs err {err:.3e}")
+    assert err <= 2e-3
+
+
+def test_decode_filtered_reductions(lib):
+    """Bilinear at texel centres is the point decode of those texels, and trilinear at
+    integer LODs is bilinear, bit for bit on the GPU."""
+    import torch
+    m = lib.material_init(256, 256, 16, 16, 16, 2, 4, 64)
+    g = geometry(m)
+    packed = _packed(lib, m, synth.uniform_latents(23, int(m.latent_count)))
+    wp = torch.zeros(lib.mlp_packed_bytes(m, lib.F16), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp_in_unit_range(23, g.K, 64, 16)), lib.F16, wp)
+    r = np.random.default_rng(24)
+    n = 5003
+    lod = r.integers(0, g.M, n)
+    Wl = np.array(g.mip_w)[lod]
+    ix, iy = r.integers(0, Wl), r.integers(0, Wl)
+    fq = np.zeros(n, dtype=O.FILTER_QUERY)
+    fq["u"], fq["v"], fq["lod"] = (ix + 0.5) / Wl, (iy + 0.5) / Wl, lod
+    pq = np.zeros(n, dtype=synth.QUERY_DTYPE)
+    pq["u"], pq["v"], pq["lod"] = fq["u"], fq["v"], lod
+    outs = {}
+    for name, fn in (("point", None), ("bilinear", 1), ("trilinear", 2)):
+        o = torch.full((n * 16,), float("nan"), dtype=torch.float16, device="cuda")
+        if fn is None:
+            lib.decode(m, packed, wp, lib.F16, queries_dev(pq), n, o, lib.F16)
+        else:
+            lib.decode_filtered(m, packed, wp, lib.F16, _fq_dev(fq), n, fn, o, lib.F16)
+        outs[name] = o
+    torch.cuda.synchronize()
+    assert torch.equal(outs["bilinear"], outs["point"])
+    assert torch.equal(outs["trilinear"], outs["bilinear"])
+
+
+def test_decode_filtered_rejects_other_precisions(lib):
+    import torch
+    m = lib.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, lib.F32), dtype=torch.uint8, device="cuda")
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(8 * 4, dtype=torch.float32, device="cuda")
+    fq = _fq_dev(_filter_queries(1, 4, 9))
+    with pytest.raises(lib.NtcError):
+        lib.decode_filtered(m, packed, wp, lib.F32, fq, 4, 1, out, lib.F32)
+    with pytest.raises(lib.NtcError):
+        lib.decode_filtered(m, packed, wp, lib.F16, fq, 4, 7, out, lib.F32)

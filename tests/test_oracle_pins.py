@@ -427,3 +427,115 @@ def test_psnr_eq1():
     # errors only in the 2x2 mip: MSE = 4*3*0.25 / (3*(16+4)) = 0.05
     t = [np.zeros((4, 4, 3)), np.full((2, 2, 3), 0.5)]
     assert O.psnr(r, t) == pytest.approx(-10 * math.log10(0.05), abs=1e-12)
+
+
+# ---------------------------------------------------------------- section 5.3 (filtering)
+def _fq(u, v, lod):
+    fq = np.zeros(len(u), dtype=O.FILTER_QUERY)
+    fq["u"], fq["v"], fq["lod"] = u, v, lod
+    return fq
+
+
+def test_filter_bilinear_reproduces_position():
+    """Bilinear weights reproduce an affine function of the texel position (interior):
+    sum_k w_k x_k = u W - 1/2 and likewise in y, in the nearest mip; weights sum to 1."""
+    g = O.make_geometry(256, 128, 4, 4, 4, 4, 4, Hd=16)
+    r = np.random.default_rng(11)
+    n = 2000
+    lod = r.uniform(0, 3.4, n).astype(np.float32)
+    u = r.uniform(0.1, 0.9, n).astype(np.float32)
+    v = r.uniform(0.1, 0.9, n).astype(np.float32)
+    q, w = O.filter_taps(g, _fq(u, v, lod), O.FILTER_BILINEAR)
+    l = np.floor(lod.astype(np.float64) + 0.5).astype(np.int64)
+    W = (256 >> l).astype(np.float64)
+    H = (128 >> l).astype(np.float64)
+    assert np.array_equal(q["lod"], np.repeat(l[:, None], 4, axis=1))
+    xs = q["u"].astype(np.float64) * W[:, None] - 0.5
+    ys = q["v"].astype(np.float64) * H[:, None] - 0.5
+    assert np.allclose(w.sum(1), 1.0, atol=1e-15)
+    assert np.allclose((w * xs).sum(1), u.astype(np.float64) * W - 0.5, atol=1e-9)
+    assert np.allclose((w * ys).sum(1), v.astype(np.float64) * H - 0.5, atol=1e-9)
+
+
+def test_filter_bilinear_at_texel_centre_is_point_decode():
+    """At a texel centre the bilinear filter is that texel alone."""
+    g = O.make_geometry(64, 64, 4, 4, 4, 4, 4, Hd=16)
+    p = np.random.default_rng(2).standard_normal(O.mlp_param_count(g.K, g.Hd, g.C)) * 0.3
+    lat = np.random.default_rng(3).uniform(-0.4, 0.4, g.latent_count)
+    ix = np.arange(0, 64, 7)
+    lod = np.zeros(len(ix), dtype=np.float32)
+    u = ((ix + 0.5) / 64).astype(np.float32)
+    got = O.decode_filtered(g, lat, p, _fq(u, u, lod), O.FILTER_BILINEAR)
+    pq = np.zeros(len(ix), dtype=synth.QUERY_DTYPE)
+    pq["u"], pq["v"] = u, u
+    assert np.array_equal(got, O.decode(g, lat, p, pq))
+
+
+def test_filter_trilinear_blend():
+    """Trilinear at an integer LOD is bilinear in that mip; at LOD l + t it is
+    (1 - t) bilinear(l) + t bilinear(l + 1)."""
+    g = O.make_geometry(128, 128, 4, 4, 4, 4, 4, Hd=16)
+    p = np.random.default_rng(5).standard_normal(O.mlp_param_count(g.K, g.Hd, g.C)) * 0.3
+    lat = np.random.default_rng(6).uniform(-0.4, 0.4, g.latent_count)
+    r = np.random.default_rng(7)
+    u = r.uniform(0, 1, 300).astype(np.float32)
+    v = r.uniform(0, 1, 300).astype(np.float32)
+    li = r.integers(0, g.M - 1, 300).astype(np.float32)
+    tri = O.decode_filtered(g, lat, p, _fq(u, v, li), O.FILTER_TRILINEAR)
+    bil = O.decode_filtered(g, lat, p, _fq(u, v, li), O.FILTER_BILINEAR)
+    assert np.allclose(tri, bil, atol=1e-14)
+    t = np.float32(0.25)
+    mid = O.decode_filtered(g, lat, p, _fq(u, v, li + t), O.FILTER_TRILINEAR)
+    up = O.decode_filtered(g, lat, p, _fq(u, v, li + 1), O.FILTER_BILINEAR)
+    assert np.allclose(mid, 0.75 * bil + 0.25 * up, atol=1e-12)
+
+
+def test_stochastic_filter_is_bilinear_in_expectation():
+    """Section 5.3: a uniform jitter of (-1/2, 1/2) texel followed by nearest sampling is
+    bilinear filtering in expectation (each of the four texels is chosen with its
+    bilinear weight); the mip is l0 + 1 with probability frac(lod); the jitter stays
+    within half a texel."""
+    g = O.make_geometry(64, 64, 4, 4, 4, 4, 4, Hd=16)
+    n = 40000
+    u0, v0, lod0 = np.float32(0.3), np.float32(0.61), np.float32(1.3)
+    fq = _fq(np.full(n, u0), np.full(n, v0), np.full(n, lod0))
+    q, w = O.filter_taps(g, fq, O.FILTER_STOCHASTIC, seed=9)
+    assert np.all(w == 1.0)
+    l = q["lod"][:, 0]
+    p_up = np.mean(l == 2)
+    assert set(np.unique(l)) <= {1, 2}
+    assert abs(p_up - 0.3) < 5 * math.sqrt(0.3 * 0.7 / n)
+    sel = l == 1
+    Wl = 32
+    x = q["u"][sel, 0].astype(np.float64) * Wl
+    assert np.all(np.abs(x - float(u0) * Wl) <= 0.5)
+    ix = np.floor(x).astype(np.int64)
+    iy = np.floor(q["v"][sel, 0].astype(np.float64) * Wl).astype(np.int64)
+    # expected: bilinear weights of the four texels around (u0 W - 1/2, v0 W - 1/2)
+    gx, gy = float(u0) * Wl - 0.5, float(v0) * Wl - 0.5
+    x0, y0 = math.floor(gx), math.floor(gy)
+    fx, fy = gx - x0, gy - y0
+    expect = {(x0, y0): (1 - fx) * (1 - fy), (x0 + 1, y0): fx * (1 - fy), (x0, y0 + 1): (1 - fx) * fy,
+              (x0 + 1, y0 + 1): fx * fy}
+    m = int(sel.sum())
+    chi2 = 0.0
+    for (a, b), pk in expect.items():
+        cnt = np.sum((ix == a) & (iy == b))
+        chi2 += (cnt - m * pk) ** 2 / (m * pk)
+    assert np.sum(np.isin(ix, [x0, x0 + 1]) & np.isin(iy, [y0, y0 + 1])) == m
+    assert chi2 < 16.3  # chi-square, 3 degrees of freedom, p = 0.001
+
+
+def test_filter_randoms_are_splitmix_counters():
+    """r1, r2, r3 of output 0 from the published SplitMix64 finalizer by hand."""
+    def mix(z):
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9 & O.MASK64
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EB & O.MASK64
+        return z ^ (z >> 31)
+    key = mix((5 ^ 0x66696C74) & O.MASK64)
+    h1 = mix((key + O.GAMMA) & O.MASK64)
+    h2 = mix((key + 2 * O.GAMMA) & O.MASK64)
+    r1, r2, r3 = O.filter_randoms(5, 1)
+    assert float(r1[0]) == (h1 >> 40) * 2.0 ** -24
+    assert float(r2[0]) == ((h1 >> 16) & 0xFFFFFF) * 2.0 ** -24
+    assert float(r3[0]) == (h2 >> 40) * 2.0 ** -24

@@ -460,7 +460,7 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
     per_shape = {}
     for m, n in zip(mats, dq):
         if n > 0:
-            k = (m.c0, m.c1, m.channels, m.hidden, m.b0, m.b1, m.activation)
+            k = (m.c0, m.c1, m.channels, m.hidden, m.b0, m.b1, m.activation, m.posenc)
             per_shape[k] = per_shape.get(k, 0) + 1
     classes = sum((c + 31) // 32 for c in per_shape.values())  # launches: at most 32 materials each
     big = max(int(m.width) ** 2 * m.channels for m in mats)

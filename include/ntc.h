@@ -46,6 +46,14 @@ typedef enum { NTC_F32 = 0, NTC_F16 = 1, NTC_FP8_E4M3 = 2 } ntc_dtype;
 
 typedef enum { NTC_ACT_RELU = 0, NTC_ACT_HARDGELU = 1 } ntc_activation;
 
+/* Positional encoding (section 4.3.2): per axis, at the texel-centre phase
+ * t = ((i mod 8) + 1/2) / 8 and frequencies f = 1, 2, 4 per 8-texel tile, the pair
+ * (S(f t), K(f t)).  NTC_PE_SINCOS: S = sin 2 pi x, K = cos 2 pi x.  NTC_PE_TRIANGLE
+ * (the paper's triangular waves): S(x) = 4 |frac(x - 1/4) - 1/2| - 1, K(x) =
+ * 4 |frac(x) - 1/2| - 1, the piecewise-linear waves with the zeros and extrema of sin
+ * and cos.  Either way the last value per axis is identically 0 at texel centres. */
+typedef enum { NTC_PE_SINCOS = 0, NTC_PE_TRIANGLE = 1 } ntc_posenc;
+
 /* One texel query: u, v in [0, 1) over the whole texture, integer mip level. 12 bytes. */
 typedef struct {
   float u, v;
@@ -84,6 +92,7 @@ typedef struct {
   int32_t grid_shift;      /* G0 at level 0 is the texture size >> grid_shift (2: W/4) */
   int32_t hidden;          /* Hd: 32 or 64 */
   int32_t activation;      /* ntc_activation */
+  int32_t posenc;          /* ntc_posenc */
   /* filled by ntc_material_init */
   int32_t num_levels;
   int32_t input_width;
@@ -406,7 +415,7 @@ ntc_status ntc_train_step_grouped(const ntc_material* mats, int32_t nmat, const 
 
 /*
  * Grouped decode: the batch of ntc_decode_batched decoded with one launch per kernel
- * shape (c0, c1, channels, hidden, b0, b1, activation) instead of one per material;
+ * shape (c0, c1, channels, hidden, b0, b1, activation, posenc) instead of one per material;
  * each launch shares its blocks out over its materials (at most 32 per launch) in
  * proportion to their queries, and every block decodes with its own material's weights.
  *   ntc_decode_table_bytes: size of the device table for nmat materials.

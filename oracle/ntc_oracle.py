@@ -46,6 +46,7 @@ class Geometry:
     shift: int        # log2(W / width of G0 at level 0); 2 in Table 1, 1 for NTC 1.0/2.25
     Hd: int
     act: str = "relu"
+    pe: str = "sincos"
     J: int = 0
     mip_w: list = field(default_factory=list)
     mip_h: list = field(default_factory=list)
@@ -60,7 +61,7 @@ class Geometry:
     target_count: int = 0
 
 
-def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu") -> Geometry:
+def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu", pe="sincos") -> Geometry:
     """Feature-pyramid geometry (section 4.1, Table 1).
 
     Level j holds G0^j at (W, H) >> (shift + 2j) and G1^j at half that.  Levels are
@@ -76,7 +77,7 @@ def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu") -
     M = full if M is None else M
     if not 1 <= M <= full:
         raise ValueError("bad mip count")
-    g = Geometry(W, H, C, M, C0, C1, B0, B1, shift, Hd, act)
+    g = Geometry(W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe)
     jmax = 0
     while (W >> (shift + 2 * jmax + 1)) >= 1 and (H >> (shift + 2 * jmax + 1)) >= 1:
         jmax += 1
@@ -293,17 +294,26 @@ def crop_queries(geom: Geometry, seed: int, step: int, crops: int = 8, side: int
 # Sampling and concatenation: sections 4.3.1 (feature interpolation), 4.3.2 (positional
 # encoding), Figure 4(c).
 # --------------------------------------------------------------------------------------
-def pos_enc(ix, iy):
+def pos_enc(ix, iy, kind="sincos"):
     """Tiled positional encoding, section 4.3.2: log2(8) = 3 octaves, period 8x8
-    texels, 6 values per axis.  Reading taken: sin/cos at frequencies 1, 2, 4 per tile
-    with texel-centre phase t = ((i mod 8) + 1/2) / 8; the last value per axis,
-    cos(8 pi t), is identically zero (the constant value of Figure 5)."""
+    texels, 6 values per axis.  Reading taken: a sine-like and a cosine-like wave at
+    frequencies 1, 2, 4 per tile with texel-centre phase t = ((i mod 8) + 1/2) / 8; the
+    last value per axis (the cosine-like wave at 4 cycles per tile) is identically zero
+    at texel centres (the constant value of Figure 5).  kind "sincos": sin 2 pi f t and
+    cos 2 pi f t; kind "triangle" (the paper's triangular waves): the piecewise-linear
+    waves through the same zeros and extrema, 4 |frac(f t - 1/4) - 1/2| - 1 and
+    4 |frac(f t) - 1/2| - 1."""
     cols = []
     for i in (ix, iy):
         t = ((np.asarray(i) % 8) + 0.5) / 8.0
         for f in (1, 2, 4):
-            cols.append(np.sin(2.0 * np.pi * f * t))
-            cols.append(np.cos(2.0 * np.pi * f * t))
+            x = f * t
+            if kind == "triangle":
+                cols.append(4.0 * np.abs((x - 0.25) - np.floor(x - 0.25) - 0.5) - 1.0)
+                cols.append(4.0 * np.abs(x - np.floor(x) - 0.5) - 1.0)
+            else:
+                cols.append(np.sin(2.0 * np.pi * x))
+                cols.append(np.cos(2.0 * np.pi * x))
     return np.stack(cols, axis=-1)
 
 
@@ -381,7 +391,7 @@ def sample_inputs(geom: Geometry, lat, queries):
         for k in range(4):
             g1v += wts[k][:, None] * lat[cells1[k][:, None] + np.arange(C1)[None, :]]
         x[sel, 4 * C0:4 * C0 + C1] = g1v
-        x[sel, 4 * C0 + C1:] = pos_enc(ix, iy)
+        x[sel, 4 * C0 + C1:] = pos_enc(ix, iy, geom.pe)
         rec["ix"][sel] = ix
         rec["iy"][sel] = iy
     return x, rec

@@ -25,7 +25,7 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
   const long long cap = (long long)device_cus() * per_cu;
   if (grid > cap) grid = cap;
   const int slot = timing_before(TK_DECODE, s);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(),
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(mm),
                      reinterpret_cast<const uint32_t*>(packed), reinterpret_cast<const uint8_t*>(wpack), scales,
                      scales + 4, q, n, rect, out, out_f16 ? 1 : 0);
   timing_after(TK_DECODE, s, slot);
@@ -63,7 +63,7 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
   const long long cap = (long long)device_cus() * per_cu;
   if (grid > cap) grid = cap;
   const int slot = PACKED ? timing_before(TK_DECODE, s) : -1;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(), src,
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(mm), src,
                      reinterpret_cast<const T*>(wpack), b1, b2, b3, q, n, rect, out, out_f16 ? 1 : 0);
   timing_after(TK_DECODE, s, slot);
   return hipGetLastError();

@@ -23,7 +23,7 @@ hipError_t filtered_t(const ntc_material& mm, const uint8_t* packed, const void*
   }
   const long long tiles = (n * filter_taps<FILT>() + 15) / 16;
   const long long grid = std::min((tiles + 3) / 4, (long long)device_cus() * per_cu);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(), packed,
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(mm), packed,
                      reinterpret_cast<const _Float16*>(wpack), q, n, key, out, out_f16 ? 1 : 0);
   return hipGetLastError();
 }

@@ -60,27 +60,29 @@ int blocks_per_cu(K kern, size_t lds) {
 }
 
 template <typename T, int C0, int C1, int C, int HD, int B0, int B1, int ACT>
-hipError_t grouped_t(const char* tab, unsigned long long hash, const std::vector<GroupItem>& items,
+hipError_t grouped_t(const ntc_material* mats, const char* tab, unsigned long long hash,
+                     const std::vector<GroupItem>& items,
                      const ntc_query* q, char* out, bool out_f16, hipStream_t s) {
   constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, true>::WB;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_grouped_kernel<T, C0, C1, C, HD, B0, B1, ACT>;
   static const int per_cu = blocks_per_cu(kern, lds);
-  const PeTable pe = pe_table();
+  const PeTable pe = pe_table(mats[items[0].mat]);
   return launch_segments(items, (long long)device_cus() * per_cu, hash, [&](const GroupArgs& ga) {
     hipLaunchKernelGGL(kern, dim3((unsigned)ga.blocks), dim3(256), lds, s, tab, pe, ga, q, out, out_f16 ? 1 : 0);
   });
 }
 
 template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
-hipError_t grouped_fp8_t(const char* tab, unsigned long long hash, const std::vector<GroupItem>& items,
+hipError_t grouped_fp8_t(const ntc_material* mats, const char* tab, unsigned long long hash,
+                         const std::vector<GroupItem>& items,
                          const ntc_query* q, char* out, bool out_f16, hipStream_t s) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_fp8_grouped_kernel<C0, C1, C, HD, B0, B1, ACT>;
   static const int per_cu = blocks_per_cu(kern, lds);
-  const PeTable pe = pe_table();
+  const PeTable pe = pe_table(mats[items[0].mat]);
   return launch_segments(items, (long long)device_cus() * per_cu, hash, [&](const GroupArgs& ga) {
     hipLaunchKernelGGL(kern, dim3((unsigned)ga.blocks), dim3(256), lds, s, tab, pe, ga, q, out, out_f16 ? 1 : 0);
   });
@@ -123,13 +125,13 @@ hipError_t launch_decode_grouped(const ntc_material* mats, int nmat, const void*
   }
   std::vector<bool> done(nmat, false);
   std::vector<GroupItem> items;
-  // the materials of one kernel (shape and activation), in batch order
-  auto collect = [&](int c0, int c1, int c, int hd, int b0, int b1, int act) {
+  // the materials of one launch (shape, activation, positional encoding), in batch order
+  auto collect = [&](int c0, int c1, int c, int hd, int b0, int b1, int act, int pe) {
     items.clear();
     for (int i = 0; i < nmat; ++i) {
       const ntc_material& m = mats[i];
       if (done[i] || m.c0 != c0 || m.c1 != c1 || m.channels != c || m.hidden != hd || m.b0 != b0 || m.b1 != b1 ||
-          m.activation != act)
+          m.activation != act || m.posenc != pe)
         continue;
       done[i] = true;
       const long long n = offsets[i + 1] - offsets[i];
@@ -140,20 +142,21 @@ hipError_t launch_decode_grouped(const ntc_material* mats, int nmat, const void*
   char* ob = reinterpret_cast<char*>(out);
   hipError_t e = hipSuccess;
 #define NTC_X(a, b, cc, h, x0, x1)                                                                              \
-  for (int act = 0; act < 2 && e == hipSuccess; ++act) {                                                        \
-    if (!collect(a, b, cc, h, x0, x1, act)) continue;                                                           \
+  for (int cls = 0; cls < 4 && e == hipSuccess; ++cls) {                                                       \
+    const int act = cls & 1;                                                                                    \
+    if (!collect(a, b, cc, h, x0, x1, act, cls >> 1)) continue;                                                 \
     if (precision == NTC_FP8_E4M3) {                                                                            \
       if constexpr (fp8_layout(a, b, x0, x1, h))                                                                \
-        e = act ? grouped_fp8_t<a, b, cc, h, x0, x1, 1>(tab, hash, items, q, ob, out_f16, s)                          \
-                : grouped_fp8_t<a, b, cc, h, x0, x1, 0>(tab, hash, items, q, ob, out_f16, s);                         \
+        e = act ? grouped_fp8_t<a, b, cc, h, x0, x1, 1>(mats, tab, hash, items, q, ob, out_f16, s)                          \
+                : grouped_fp8_t<a, b, cc, h, x0, x1, 0>(mats, tab, hash, items, q, ob, out_f16, s);                         \
       else                                                                                                      \
         e = hipErrorInvalidValue;                                                                               \
     } else if (precision == NTC_F16) {                                                                          \
-      e = act ? grouped_t<_Float16, a, b, cc, h, x0, x1, 1>(tab, hash, items, q, ob, out_f16, s)                      \
-              : grouped_t<_Float16, a, b, cc, h, x0, x1, 0>(tab, hash, items, q, ob, out_f16, s);                     \
+      e = act ? grouped_t<_Float16, a, b, cc, h, x0, x1, 1>(mats, tab, hash, items, q, ob, out_f16, s)                      \
+              : grouped_t<_Float16, a, b, cc, h, x0, x1, 0>(mats, tab, hash, items, q, ob, out_f16, s);                     \
     } else {                                                                                                    \
-      e = act ? grouped_t<float, a, b, cc, h, x0, x1, 1>(tab, hash, items, q, ob, out_f16, s)                         \
-              : grouped_t<float, a, b, cc, h, x0, x1, 0>(tab, hash, items, q, ob, out_f16, s);                        \
+      e = act ? grouped_t<float, a, b, cc, h, x0, x1, 1>(mats, tab, hash, items, q, ob, out_f16, s)                         \
+              : grouped_t<float, a, b, cc, h, x0, x1, 0>(mats, tab, hash, items, q, ob, out_f16, s);                        \
     }                                                                                                           \
   }
   NTC_DECODE_SHAPES(NTC_X)

@@ -35,7 +35,7 @@ DevMat dev_mat(const ntc_material& m) {
   std::memset(&d, 0, sizeof d);
   d.W = m.width; d.H = m.height; d.C = m.channels; d.M = m.num_mips;
   d.C0 = m.c0; d.C1 = m.c1; d.B0 = m.b0; d.B1 = m.b1; d.shift = m.grid_shift;
-  d.Hd = m.hidden; d.act = m.activation; d.J = m.num_levels; d.K = m.input_width;
+  d.Hd = m.hidden; d.act = m.activation; d.pe = m.posenc; d.J = m.num_levels; d.K = m.input_width;
   for (int l = 0; l < kMaxMips; ++l) {
     d.mip_w[l] = m.mip_w[l]; d.mip_h[l] = m.mip_h[l]; d.level_of_mip[l] = m.level_of_mip[l];
     d.mip_off[l] = m.mip_offset[l];
@@ -54,15 +54,21 @@ DevMat dev_mat(const ntc_material& m) {
   return d;
 }
 
-PeTable pe_table() {
+PeTable pe_table(const ntc_material& m) {
   PeTable p;
   const double two_pi = 6.283185307179586476925286766559;
+  auto frac = [](double x) { return x - std::floor(x); };
   for (int i = 0; i < 8; ++i) {
     const double t = (i + 0.5) / 8.0;
     for (int f = 0; f < 3; ++f) {
-      const double a = two_pi * (double)(1 << f) * t;
-      p.v[i][2 * f] = (float)std::sin(a);
-      p.v[i][2 * f + 1] = (float)std::cos(a);
+      const double x = (double)(1 << f) * t;
+      if (m.posenc == NTC_PE_TRIANGLE) {
+        p.v[i][2 * f] = (float)(4.0 * std::fabs(frac(x - 0.25) - 0.5) - 1.0);
+        p.v[i][2 * f + 1] = (float)(4.0 * std::fabs(frac(x) - 0.5) - 1.0);
+      } else {
+        p.v[i][2 * f] = (float)std::sin(two_pi * x);
+        p.v[i][2 * f + 1] = (float)std::cos(two_pi * x);
+      }
     }
   }
   return p;
@@ -134,6 +140,7 @@ ntc_status ntc_material_init(ntc_material* m) {
     return fail(NTC_E_INVALID, "hidden must be 16, 32, 48 or 64");
   if (m->activation != NTC_ACT_RELU && m->activation != NTC_ACT_HARDGELU)
     return fail(NTC_E_INVALID, "unknown activation");
+  if (m->posenc != NTC_PE_SINCOS && m->posenc != NTC_PE_TRIANGLE) return fail(NTC_E_INVALID, "unknown posenc");
   const int W = m->width, H = m->height, sh = m->grid_shift;
   int full = 1;
   while ((std::max(W, H) >> (full - 1)) > 1) ++full;

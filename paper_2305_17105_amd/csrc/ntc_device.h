@@ -27,7 +27,7 @@ constexpr int kMaxMips = 16;
 
 // Geometry as the kernels see it (filled on the host from ntc_material).
 struct DevMat {
-  int W, H, C, M, C0, C1, B0, B1, shift, Hd, act, J, K;
+  int W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe, J, K;
   int mip_w[kMaxMips], mip_h[kMaxMips], level_of_mip[kMaxMips];
   int g0_w[kMaxLevels], g0_h[kMaxLevels], g1_w[kMaxLevels], g1_h[kMaxLevels];
   long long g0_off[kMaxLevels], g1_off[kMaxLevels];

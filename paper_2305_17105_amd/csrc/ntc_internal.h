@@ -20,7 +20,7 @@ void set_error(const std::string& msg);
 
 // ntc_material (validated) -> kernel view.
 DevMat dev_mat(const ntc_material& m);
-PeTable pe_table();
+PeTable pe_table(const ntc_material& m);
 
 // Number of CUs of the current device (cached per device).
 int device_cus();

@@ -1234,7 +1234,7 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.tg = p.tg;
   const int slot = timing_before(TK_TRAIN_FUSED, s);
   hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(Cfg::NTHR), Cfg::LDS, s, dev_mat(mm),
-                     pe_table(), a);
+                     pe_table(mm), a);
   timing_after(TK_TRAIN_FUSED, s, slot);
   return hipGetLastError();
 }

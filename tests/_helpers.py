@@ -10,8 +10,9 @@ from paper_2305_17105_amd import synth
 def geometry(m):
     """Oracle geometry for a library material descriptor (independent implementation)."""
     act = "relu" if m.activation == 0 else "hardgelu"
+    pe = "sincos" if m.posenc == 0 else "triangle"
     return O.make_geometry(m.width, m.height, m.channels, m.c0, m.c1, m.b0, m.b1, Hd=m.hidden, M=m.num_mips,
-                           shift=m.grid_shift, act=act)
+                           shift=m.grid_shift, act=act, pe=pe)
 
 
 def to_dev(a, dtype=None):

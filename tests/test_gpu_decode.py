@@ -105,6 +105,28 @@ def test_decode_parity(lib, shape, prec):
     assert np.max(np.abs(got16 - got)) <= 2e-3  # FP16 output is the FP32 result rounded
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_decode_parity_triangle_encoding(lib, prec):
+    """Decode with the triangular-wave positional encoding (section 4.3.2)."""
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    m = lib.material_init(512, 512, 16, 16, 16, 2, 4, 64, posenc=lib.PE_TRIANGLE)
+    g = geometry(m)
+    raw = synth.uniform_latents(8, int(m.latent_count))
+    mlp = mlp_in_unit_range(8, g.K, 64, 16)
+    n = 6007
+    q = synth.random_queries(8, n, g.M)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    out = torch.full((n * 16,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode(m, _packed(lib, m, raw), wp, P, queries_dev(q), n, out, lib.F32)
+    torch.cuda.synchronize()
+    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q).ravel()
+    err = np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref))
+    print(f"triangle encoding {prec}: max-abs err {err:.3e}")
+    assert err <= (1e-5 if prec == "f32" else 2e-3)
+
+
 F8SHAPES = [  # W, C, c0, c1, b0, b1, hidden, mips, n, lod
     (256, 8, 8, 8, 4, 4, 64, 1, 65536, 0),        # tiny configuration shapes
     (512, 16, 16, 16, 2, 4, 64, 0, 20011, None),  # 2-bit G0 / 4-bit G1, full chain, ragged

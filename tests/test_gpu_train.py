@@ -24,11 +24,11 @@ def lib():
 class Run:
     """One material with its GPU training state and the matching oracle state."""
 
-    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None):
+    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0):
         import torch
         self.lib = lib
         self.prec = lib.F32 if prec is None else prec
-        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips)
+        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips, posenc=posenc)
         self.g = geometry(self.m)
         g = self.g
         raw = synth.uniform_latents(seed, int(self.m.latent_count))
@@ -113,6 +113,15 @@ def test_gradients_fp32(lib, name):
     # lr = 0: parameters unchanged
     assert np.array_equal(run.get("latents"), run.ostate["latents"])
     assert np.array_equal(run.get("mlp"), run.ostate["mlp"])
+
+
+def test_gradients_triangle_encoding(lib):
+    """The triangular-wave positional encoding (section 4.3.2) through the training step."""
+    run = Run(lib, *CONFIGS["chain"], seed=6, posenc=lib.PE_TRIANGLE)
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=False)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    _check_grads(run, hp)
 
 
 def test_gradients_with_noise(lib):

@@ -207,6 +207,25 @@ def test_pos_enc_values():
     assert np.all(np.abs(a[:, 5]) < 1e-14) and np.all(np.abs(a[:, 11]) < 1e-14)
 
 
+def test_pos_enc_triangle_values():
+    """Section 4.3.2's triangular waves: hand values at texel centres (x: i = 0,
+    t = 1/16; y: i = 3, t = 7/16), period 8, the last value per axis constant 0, the
+    signs of the sine/cosine encoding, and |S| + |K| = 1 for every pair (quadrature
+    triangle waves)."""
+    pe = O.pos_enc(np.array([0]), np.array([3]), "triangle")[0]
+    assert list(pe[:6]) == [0.25, 0.75, 0.5, 0.5, 1.0, 0.0]
+    assert list(pe[6:]) == [0.25, -0.75, -0.5, 0.5, -1.0, 0.0]
+    i = np.arange(64)
+    a = O.pos_enc(i, i, "triangle")
+    b = O.pos_enc(i, i, "sincos")
+    assert np.array_equal(a, np.roll(a, 8, axis=0))
+    assert np.all(a[:, 5] == 0) and np.all(a[:, 11] == 0)
+    nz = np.abs(b) > 1e-12
+    assert np.array_equal(np.sign(a[nz]), np.sign(b[nz]))
+    for k in range(0, 12, 2):
+        assert np.allclose(np.abs(a[:, k]) + np.abs(a[:, k + 1]), 1.0, atol=0)
+
+
 def test_lod_clamp_and_snap():
     g = O.make_geometry(16, 16, 1, 1, 1, 4, 4)
     q = np.zeros(4, dtype=synth.QUERY_DTYPE)

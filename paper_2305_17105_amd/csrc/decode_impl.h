@@ -336,10 +336,11 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
         }
         f16x2 v[Raw::NW1 * (4 / B1)];
         g1_pairs(R, g, v);
+        constexpr int G0S = paired_g0_slots(C0, B0);
 #pragma unroll
         for (int p = 0; p < Raw::NW1 * (4 / B1); ++p) {
-          xs[C0 + 2 * p] = v[p][0];
-          xs[C0 + 2 * p + 1] = v[p][1];
+          xs[G0S + 2 * p] = v[p][0];
+          xs[G0S + 2 * p + 1] = v[p][1];
         }
       } else {
 #pragma unroll

@@ -131,20 +131,23 @@ __host__ __device__ constexpr PackGeom pack_geom(int c0, int c1, int hd, bool f1
 
 // Paired input layout of the FP16 decoder reading bit-packed codes: two channels per
 // 32-bit register, taken straight from the packed words (channel c and c + 16/B of
-// the same dword share a register), when a G0 cell fills whole dwords and B <= 4.
+// the same dword share a register), when B <= 4.  A G0 cell's window is read as whole
+// dwords; the codes past its last channel (the next cell's bits) meet zero weights.
 //   G0: window dword d, pair p = d*(16/B0) + c (c < 16/B0) -> slots 2p, 2p+1 hold
-//       channels d*32/B0 + c and d*32/B0 + c + 16/B0.
-//   G1: lane group g, dword d, k < 4/B1: pair q = d*(4/B1) + k -> slots C0 + 2q, +1
+//       channels d*32/B0 + c and d*32/B0 + c + 16/B0 (padding if >= C0);
+//       G0S = ceil(C0 B0 / 32) * 32/B0 slots.
+//   G1: lane group g, dword d, k < 4/B1: pair q = d*(4/B1) + k -> slots G0S + 2q, +1
 //       hold channels ch = d*32/B1 + g + 4k and ch + 16/B1 (padding if >= C1).
 //   PE: the next 3 slots.
 __host__ __device__ constexpr bool paired_layout(int c0, int c1, int b0, int b1, bool f16) {
-  return f16 && b0 <= 4 && b1 <= 4 && (c0 * b0) % 32 == 0 && c1 >= 1;
+  return f16 && b0 <= 4 && b1 <= 4 && c0 >= 1 && c1 >= 1;
 }
+__host__ __device__ constexpr int paired_g0_slots(int c0, int b0) { return (c0 * b0 + 31) / 32 * (32 / b0); }
 __host__ __device__ constexpr int paired_g1_slots(int c1, int b1) { return 2 * ((c1 * b1 + 31) / 32) * (4 / b1); }
 __host__ __device__ constexpr PackGeom pack_geom_decode(int c0, int c1, int b0, int b1, int hd, bool f16) {
   PackGeom p = pack_geom(c0, c1, hd, f16);
   if (paired_layout(c0, c1, b0, b1, f16)) {
-    p.T_lat = c0 + paired_g1_slots(c1, b1);
+    p.T_lat = paired_g0_slots(c0, b0) + paired_g1_slots(c1, b1);
     p.T_used = p.T_lat + 3;
     p.S1 = (p.T_used + 3) / 4 * 4;
     p.ML = (p.T_lat + 3) / 4;
@@ -167,22 +170,22 @@ __host__ __device__ inline void in_slot_of_paired(int k, int c0, int c1, int b0,
     g = ch % 4;
     const bool lo = cc < half;
     const int kk = ((lo ? cc : cc - half) - g) / 4;
-    t = c0 + 2 * (d * (4 / b1) + kk) + (lo ? 0 : 1);
+    t = paired_g0_slots(c0, b0) + 2 * (d * (4 / b1) + kk) + (lo ? 0 : 1);
   } else {
     const int p = k - 4 * c0 - c1;
     g = p / 3;
-    t = c0 + paired_g1_slots(c1, b1) + p % 3;
+    t = paired_g0_slots(c0, b0) + paired_g1_slots(c1, b1) + p % 3;
   }
 }
 
 // FP8-e4m3 decode layout (16x16x32 fp8 matrix cores: 8 slots of a lane group per
-// instruction, one byte each).  Same eligibility as the paired layout.  G0 codes are
-// spread into bytes four at a time: for dword d and k < 8/B0, the word
+// instruction, one byte each).  The paired layout's eligibility with G0 cells of
+// whole dwords (so G0S = C0).  G0 codes are spread into bytes four at a time: for dword d and k < 8/B0, the word
 // (w >> B0*k) & byte-mask holds in byte b the code of channel d*32/B0 + b*8/B0 + k,
 // which goes to slot d*32/B0 + 4k + b.  G1 pairs and the PE follow the paired layout;
 // slots are padded to a multiple of 8.  Element offsets are bytes.
 __host__ __device__ constexpr bool fp8_layout(int c0, int c1, int b0, int b1, int hd) {
-  return paired_layout(c0, c1, b0, b1, true) && hd % 32 == 0;
+  return paired_layout(c0, c1, b0, b1, true) && (c0 * b0) % 32 == 0 && hd % 32 == 0;
 }
 __host__ __device__ constexpr PackGeom pack_geom_fp8(int c0, int c1, int b0, int b1, int hd) {
   PackGeom p{};

@@ -76,10 +76,10 @@ typedef struct {
  *     B-bit codes in cell-major, channel-minor order, padded to 16 bytes; the
  *     unpadded size is the paper's w*h*C*B/8 (Appendix 'Storage Cost').
  *   MLP (FP32, canonical): W1[K][Hd], b1[Hd], W2[Hd][Hd], b2[Hd], W3[Hd][C], b3[C],
- *     K = 4 c0 + c1 + 12 (section 4.4; the LOD input is not used).  Input order:
- *     G0 neighbours (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1) each c0 wide, G1
- *     bilinear (c1), positional encoding (x: sin/cos at 1, 2, 4 cycles per 8
- *     texels, then y).
+ *     K = 4 c0 + c1 + 12 + lod_input (section 4.4).  Input order: G0 neighbours
+ *     (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1) each c0 wide, G1 bilinear (c1),
+ *     positional encoding (x: the two waves at 1, 2, 4 cycles per 8 texels, then
+ *     y), and with lod_input the decoded texel's mip l / (M - 1) (0 when M = 1).
  *   targets (FP32): mips 0..M-1 concatenated, each [H_l][W_l][C].
  */
 typedef struct {
@@ -93,6 +93,7 @@ typedef struct {
   int32_t hidden;          /* Hd: 32 or 64 */
   int32_t activation;      /* ntc_activation */
   int32_t posenc;          /* ntc_posenc */
+  int32_t lod_input;       /* 1: the normalized mip l / (M - 1) is a network input (section 4.4) */
   /* filled by ntc_material_init */
   int32_t num_levels;
   int32_t input_width;

@@ -6,7 +6,7 @@ CPU-baseline leg.  Nothing here is called by the HIP library.
 Notation follows the paper (arXiv 2305.17105, section 4):
   texture set W x H x C with mips l = 0..M-1, feature levels F^j = (G0^j, G1^j),
   latent channels C0, C1, bits B0, B1, N = 2^B quantization levels, Q = 1/N,
-  MLP  K -> Hd -> Hd -> C  with K = 4*C0 + C1 + 12.
+  MLP  K -> Hd -> Hd -> C  with K = 4*C0 + C1 + 12 (+ 1 with the LOD input).
 """
 from __future__ import annotations
 
@@ -47,6 +47,7 @@ class Geometry:
     Hd: int
     act: str = "relu"
     pe: str = "sincos"
+    lod_input: bool = False
     J: int = 0
     mip_w: list = field(default_factory=list)
     mip_h: list = field(default_factory=list)
@@ -61,7 +62,8 @@ class Geometry:
     target_count: int = 0
 
 
-def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu", pe="sincos") -> Geometry:
+def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu", pe="sincos",
+                  lod_input=False) -> Geometry:
     """Feature-pyramid geometry (section 4.1, Table 1).
 
     Level j holds G0^j at (W, H) >> (shift + 2j) and G1^j at half that.  Levels are
@@ -77,7 +79,7 @@ def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu", p
     M = full if M is None else M
     if not 1 <= M <= full:
         raise ValueError("bad mip count")
-    g = Geometry(W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe)
+    g = Geometry(W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe, bool(lod_input))
     jmax = 0
     while (W >> (shift + 2 * jmax + 1)) >= 1 and (H >> (shift + 2 * jmax + 1)) >= 1:
         jmax += 1
@@ -99,7 +101,8 @@ def make_geometry(W, H, C, C0, C1, B0, B1, Hd=64, M=None, shift=2, act="relu", p
         g.g1_off.append(off)
         off += w1 * h1 * C1
     g.latent_count = off
-    g.K = 4 * C0 + C1 + 12
+    # section 4.4: 4 C0 + C1 + 12 inputs and, as the paper's network has it, a LOD value
+    g.K = 4 * C0 + C1 + 12 + (1 if lod_input else 0)
     toff = 0
     for l in range(M):
         g.mip_off.append(toff)
@@ -391,7 +394,9 @@ def sample_inputs(geom: Geometry, lat, queries):
         for k in range(4):
             g1v += wts[k][:, None] * lat[cells1[k][:, None] + np.arange(C1)[None, :]]
         x[sel, 4 * C0:4 * C0 + C1] = g1v
-        x[sel, 4 * C0 + C1:] = pos_enc(ix, iy, geom.pe)
+        x[sel, 4 * C0 + C1:4 * C0 + C1 + 12] = pos_enc(ix, iy, geom.pe)
+        if geom.lod_input:  # the mip as a value in [0, 1] (reading: l / (M - 1))
+            x[sel, -1] = l / (geom.M - 1) if geom.M > 1 else 0.0
         rec["ix"][sel] = ix
         rec["iy"][sel] = iy
     return x, rec

@@ -42,7 +42,7 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   const float *b1, *b2, *b3;
   if (mlp) {
-    const long long K = 4 * C0 + C1 + 12;
+    const long long K = mm.input_width;
     b1 = mlp + K * HD;
     b2 = b1 + HD + (long long)HD * HD;
     b3 = b2 + HD + (long long)HD * C;

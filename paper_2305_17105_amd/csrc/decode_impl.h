@@ -87,7 +87,7 @@ __device__ inline void load_window(const char* __restrict__ packed, uint32_t bas
 template <int C0, int C1, int B0, int B1>
 struct CodeWindow {
   static constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
-  int ix, iy;
+  int ix, iy, l;
   float fx, fy, w[4];
   uint32_t g0[NW0];
   uint32_t g1[4][NW1];
@@ -96,6 +96,7 @@ struct CodeWindow {
     const Footprint f = locate(m, u, v, lod, g);
     ix = f.ix;
     iy = f.iy;
+    l = f.l;
     fx = f.fx;
     fy = f.fy;
 #pragma unroll
@@ -283,11 +284,14 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
     }
     store_out<C>(out, out_f16, s, n, g, y);
   };
-  auto pe_slots = [&](T (&xs)[S1], int ix, int iy) {
+  // LOD input (section 4.4): mip l / (M - 1) in group 0's slot after the encoding
+  const float lod_norm = m.lod_in && m.M > 1 ? 1.f / (float)(m.M - 1) : 0.f;
+  auto pe_slots = [&](T (&xs)[S1], int ix, int iy, int l) {
     float pv[3];
     pe_values(pe_lds, ix, iy, g, pv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) xs[pg.T_lat + k] = (T)pv[k];
+    xs[pg.T_lat + 3] = (T)(g == 0 ? (float)l * lod_norm : 0.f);
 #pragma unroll
     for (int t = pg.T_used; t < S1; ++t) xs[t] = (T)0.f;
   };
@@ -359,7 +363,7 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
 #pragma unroll
         for (int i = 0; i < IS::n1max; ++i) xs[C0 + i] = (g + 4 * i < C1) ? (T)acc[i] : (T)0.f;
       }
-      pe_slots(xs, R.ix, R.iy);
+      pe_slots(xs, R.ix, R.iy, R.l);
     };
 
     long long tile = (long long)bi * 4 + wave;
@@ -403,7 +407,7 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
         }
         xs[C0 + i] = (T)acc;
       }
-      pe_slots(xs, f.ix, f.iy);
+      pe_slots(xs, f.ix, f.iy, f.l);
       mlp_store(xs, tile, wt);
     }
   }
@@ -503,6 +507,7 @@ __device__ __forceinline__ void decode_fp8_body(const DevMat& m, const PeTable& 
   for (int i = threadIdx.x; i < 2 * HD + 16; i += blockDim.x) b_lds[i] = i < 2 * HD + C ? bias[i] : 0.f;
   __syncthreads();
   const float sc1 = scales[0], sc2 = scales[1], sc3 = scales[2];
+  const float lod_norm = m.lod_in && m.M > 1 ? 1.f / (float)(m.M - 1) : 0.f;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   const long long tiles = (n + 15) / 16, stride = (long long)nb * 4;
@@ -570,8 +575,9 @@ __device__ __forceinline__ void decode_fp8_body(const DevMat& m, const PeTable& 
       float pv[3];
       pe_values(pe_lds, cur.ix, cur.iy, g, pv);
       constexpr int t0 = pg.T_lat;  // even
+      const float lodv = g == 0 ? (float)cur.l * lod_norm : 0.f;  // LOD input (section 4.4)
       xw[t0 / 4] = cvt_e4m3x2(pv[0], pv[1], xw[t0 / 4], (t0 % 4) != 0);
-      xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], 0.f, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
+      xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], lodv, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
     }
     // ---- layer 1
     uint32_t hw[SH / 4];

@@ -35,7 +35,7 @@ DevMat dev_mat(const ntc_material& m) {
   std::memset(&d, 0, sizeof d);
   d.W = m.width; d.H = m.height; d.C = m.channels; d.M = m.num_mips;
   d.C0 = m.c0; d.C1 = m.c1; d.B0 = m.b0; d.B1 = m.b1; d.shift = m.grid_shift;
-  d.Hd = m.hidden; d.act = m.activation; d.pe = m.posenc; d.J = m.num_levels; d.K = m.input_width;
+  d.Hd = m.hidden; d.act = m.activation; d.pe = m.posenc; d.lod_in = m.lod_input; d.J = m.num_levels; d.K = m.input_width;
   for (int l = 0; l < kMaxMips; ++l) {
     d.mip_w[l] = m.mip_w[l]; d.mip_h[l] = m.mip_h[l]; d.level_of_mip[l] = m.level_of_mip[l];
     d.mip_off[l] = m.mip_offset[l];
@@ -141,6 +141,7 @@ ntc_status ntc_material_init(ntc_material* m) {
   if (m->activation != NTC_ACT_RELU && m->activation != NTC_ACT_HARDGELU)
     return fail(NTC_E_INVALID, "unknown activation");
   if (m->posenc != NTC_PE_SINCOS && m->posenc != NTC_PE_TRIANGLE) return fail(NTC_E_INVALID, "unknown posenc");
+  if (m->lod_input != 0 && m->lod_input != 1) return fail(NTC_E_INVALID, "lod_input must be 0 or 1");
   const int W = m->width, H = m->height, sh = m->grid_shift;
   int full = 1;
   while ((std::max(W, H) >> (full - 1)) > 1) ++full;
@@ -154,7 +155,7 @@ ntc_status ntc_material_init(ntc_material* m) {
   if (J > NTC_MAX_LEVELS) return fail(NTC_E_INVALID, "too many feature levels");
   m->num_mips = M;
   m->num_levels = J;
-  m->input_width = 4 * m->c0 + m->c1 + 12;
+  m->input_width = 4 * m->c0 + m->c1 + 12 + m->lod_input;
   std::memset(m->mip_w, 0, sizeof m->mip_w);
   std::memset(m->mip_h, 0, sizeof m->mip_h);
   std::memset(m->level_of_mip, 0, sizeof m->level_of_mip);

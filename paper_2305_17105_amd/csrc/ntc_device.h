@@ -27,7 +27,7 @@ constexpr int kMaxMips = 16;
 
 // Geometry as the kernels see it (filled on the host from ntc_material).
 struct DevMat {
-  int W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe, J, K;
+  int W, H, C, M, C0, C1, B0, B1, shift, Hd, act, pe, lod_in, J, K;
   int mip_w[kMaxMips], mip_h[kMaxMips], level_of_mip[kMaxMips];
   int g0_w[kMaxLevels], g0_h[kMaxLevels], g1_w[kMaxLevels], g1_h[kMaxLevels];
   long long g0_off[kMaxLevels], g1_off[kMaxLevels];
@@ -88,18 +88,20 @@ __host__ __device__ constexpr int hid_feature(int g, int t) { return 16 * (t / 4
 //   t <  C0                 : G0 neighbour g, channel t
 //   C0 <= t < T_lat         : G1 channel g + 4 (t - C0) (padding if >= C1)
 //   T_lat <= t < T_lat + 3  : positional-encoding values 3g .. 3g+2
+//   t = T_lat + 3           : the LOD input in group 0 (section 4.4; zero without it)
 //   beyond                  : zero padding
 template <int C0, int C1>
 struct InSlots {
   static constexpr int n1max = (C1 + 3) / 4;
   static constexpr int T_lat = C0 + n1max;
-  static constexpr int T_used = T_lat + 3;
-  static constexpr int K = 4 * C0 + C1 + 12;
+  static constexpr int T_used = T_lat + 4;
+  static constexpr int K_LOD = 4 * C0 + C1 + 12;  // canonical row of the LOD input
   // canonical input feature of slot (g, t); -1 for padding
   static constexpr int psi(int g, int t) {
     return t < C0 ? g * C0 + t
          : t < T_lat ? (g + 4 * (t - C0) < C1 ? 4 * C0 + g + 4 * (t - C0) : -1)
-         : t < T_used ? 4 * C0 + C1 + 3 * g + (t - T_lat)
+         : t < T_lat + 3 ? 4 * C0 + C1 + 3 * g + (t - T_lat)
+         : t == T_lat + 3 && g == 0 ? K_LOD
          : -1;
   }
 };
@@ -113,7 +115,7 @@ struct PackGeom {
 __host__ __device__ constexpr PackGeom pack_geom(int c0, int c1, int hd, bool f16) {
   PackGeom p{};
   p.T_lat = c0 + (c1 + 3) / 4;
-  p.T_used = p.T_lat + 3;
+  p.T_used = p.T_lat + 4;  // 3 positional-encoding slots and the LOD slot
   p.S1 = f16 ? (p.T_used + 3) / 4 * 4 : p.T_used;
   p.SH = hd / 4;
   p.MT = hd / 16;
@@ -138,7 +140,7 @@ __host__ __device__ constexpr PackGeom pack_geom(int c0, int c1, int hd, bool f1
 //       G0S = ceil(C0 B0 / 32) * 32/B0 slots.
 //   G1: lane group g, dword d, k < 4/B1: pair q = d*(4/B1) + k -> slots G0S + 2q, +1
 //       hold channels ch = d*32/B1 + g + 4k and ch + 16/B1 (padding if >= C1).
-//   PE: the next 3 slots.
+//   PE: the next 3 slots; LOD input: the one after, in group 0.
 __host__ __device__ constexpr bool paired_layout(int c0, int c1, int b0, int b1, bool f16) {
   return f16 && b0 <= 4 && b1 <= 4 && c0 >= 1 && c1 >= 1;
 }
@@ -148,7 +150,7 @@ __host__ __device__ constexpr PackGeom pack_geom_decode(int c0, int c1, int b0, 
   PackGeom p = pack_geom(c0, c1, hd, f16);
   if (paired_layout(c0, c1, b0, b1, f16)) {
     p.T_lat = paired_g0_slots(c0, b0) + paired_g1_slots(c1, b1);
-    p.T_used = p.T_lat + 3;
+    p.T_used = p.T_lat + 4;
     p.S1 = (p.T_used + 3) / 4 * 4;
     p.ML = (p.T_lat + 3) / 4;
     p.L1 = 0;
@@ -172,9 +174,9 @@ __host__ __device__ inline void in_slot_of_paired(int k, int c0, int c1, int b0,
     const int kk = ((lo ? cc : cc - half) - g) / 4;
     t = paired_g0_slots(c0, b0) + 2 * (d * (4 / b1) + kk) + (lo ? 0 : 1);
   } else {
-    const int p = k - 4 * c0 - c1;
-    g = p / 3;
-    t = paired_g0_slots(c0, b0) + paired_g1_slots(c1, b1) + p % 3;
+    const int p = k - 4 * c0 - c1;  // 12: the LOD input
+    g = p < 12 ? p / 3 : 0;
+    t = paired_g0_slots(c0, b0) + paired_g1_slots(c1, b1) + (p < 12 ? p % 3 : 3);
   }
 }
 
@@ -190,7 +192,7 @@ __host__ __device__ constexpr bool fp8_layout(int c0, int c1, int b0, int b1, in
 __host__ __device__ constexpr PackGeom pack_geom_fp8(int c0, int c1, int b0, int b1, int hd) {
   PackGeom p{};
   p.T_lat = c0 + paired_g1_slots(c1, b1);
-  p.T_used = p.T_lat + 3;
+  p.T_used = p.T_lat + 4;
   p.S1 = (p.T_used + 7) / 8 * 8;
   p.SH = hd / 4;
   p.MT = hd / 16;
@@ -243,7 +245,7 @@ __host__ __device__ inline void in_slot_of(int k, int c0, int c1, int& g, int& t
   const int tl = c0 + (c1 + 3) / 4;
   if (k < 4 * c0) { g = k / c0; t = k % c0; }
   else if (k < 4 * c0 + c1) { const int ch = k - 4 * c0; g = ch % 4; t = c0 + ch / 4; }
-  else { const int p = k - 4 * c0 - c1; g = p / 3; t = tl + p % 3; }
+  else { const int p = k - 4 * c0 - c1; g = p < 12 ? p / 3 : 0; t = tl + (p < 12 ? p % 3 : 3); }  // 12: LOD
 }
 __host__ __device__ inline void hid_slot_of(int h, int& g, int& t) { g = (h / 4) % 4; t = 4 * (h / 16) + h % 4; }
 
@@ -564,8 +566,8 @@ __device__ inline float noise_at(uint64_t key, long long i, int bits) {
 template <typename T>
 __device__ inline void scatter_param(T* __restrict__ pack, const PackGeom& pg, int c0, int c1, int C, int Hd,
                                      long long p, float value, bool bwd, int b0 = 0, int b1 = 0,
-                                     bool paired = false) {
-  const long long K = 4 * c0 + c1 + 12;
+                                     bool paired = false, int lod_in = 0) {
+  const long long K = 4 * c0 + c1 + 12 + lod_in;
   const long long nW1 = K * Hd, nW2 = (long long)Hd * Hd, nW3 = (long long)Hd * C;
   const T v = (T)value;
   if (p < nW1) {

@@ -13,11 +13,12 @@ __global__ void zero_kernel(T* __restrict__ p, long long n) {
 
 template <typename T>
 __global__ void pack_kernel(PackGeom pg, int c0, int c1, int C, int Hd, long long P, const float* __restrict__ mlp,
-                            T* __restrict__ pack, float* __restrict__ bias_out, int bwd, int b0, int b1, int paired) {
-  const long long K = 4 * c0 + c1 + 12;
+                            T* __restrict__ pack, float* __restrict__ bias_out, int bwd, int b0, int b1, int paired,
+                            int lod_in) {
+  const long long K = 4 * c0 + c1 + 12 + lod_in;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
     const float v = mlp[p];
-    scatter_param<T>(pack, pg, c0, c1, C, Hd, p, v, bwd != 0, b0, b1, paired != 0);
+    scatter_param<T>(pack, pg, c0, c1, C, Hd, p, v, bwd != 0, b0, b1, paired != 0, lod_in);
     if (bias_out) {
       const long long b1 = K * Hd, b2 = b1 + Hd + (long long)Hd * Hd, b3 = b2 + Hd + (long long)Hd * C;
       if (p >= b1 && p < b1 + Hd) bias_out[p - b1] = v;
@@ -45,7 +46,8 @@ static hipError_t pack_t(const ntc_material& m, const float* mlp, bool bwd, void
   const long long P = m.mlp_params;
   const int pb = (int)std::min<long long>((P + 255) / 256, 1024);
   hipLaunchKernelGGL(pack_kernel<T>, dim3(pb), dim3(256), 0, s, pg, (int)m.c0, (int)m.c1, (int)m.channels,
-                     (int)m.hidden, P, mlp, w, bias, bwd ? 1 : 0, (int)m.b0, (int)m.b1, paired ? 1 : 0);
+                     (int)m.hidden, P, mlp, w, bias, bwd ? 1 : 0, (int)m.b0, (int)m.b1, paired ? 1 : 0,
+                     (int)m.lod_input);
   return hipGetLastError();
 }
 
@@ -75,10 +77,9 @@ __global__ void fp8_scale_kernel(const float* __restrict__ mlp, int K, int Hd, i
   if (threadIdx.x == 0 && l == 0) scales[3] = 0.f;
 }
 
-__global__ void pack_fp8_kernel(PackGeom pg, int c0, int c1, int C, int Hd, int b0, int b1, long long P,
+__global__ void pack_fp8_kernel(PackGeom pg, int c0, int c1, int C, int Hd, int b0, int b1, long long P, int K,
                                 const float* __restrict__ mlp, uint8_t* __restrict__ pack,
                                 const float* __restrict__ scales, float* __restrict__ bias_out) {
-  const long long K = 4 * c0 + c1 + 12;
   const long long nW1 = K * Hd, nW2 = (long long)Hd * Hd, nW3 = (long long)Hd * C;
   const float s1 = scales[0], s2 = scales[1], s3 = scales[2];
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
@@ -134,7 +135,7 @@ hipError_t launch_pack_mlp_fp8(const ntc_material& m, const float* mlp, void* pa
   const long long P = m.mlp_params;
   const int pb = (int)std::min<long long>((P + 255) / 256, 1024);
   hipLaunchKernelGGL(pack_fp8_kernel, dim3(pb), dim3(256), 0, s, pg, (int)m.c0, (int)m.c1, (int)m.channels,
-                     (int)m.hidden, (int)m.b0, (int)m.b1, P, mlp, w, (const float*)scales, bias);
+                     (int)m.hidden, (int)m.b0, (int)m.b1, P, (int)m.input_width, mlp, w, (const float*)scales, bias);
   return hipGetLastError();
 }
 

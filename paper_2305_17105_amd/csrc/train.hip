@@ -155,10 +155,6 @@ struct TrainCfg {
   static constexpr int TR3 = cmax(cmax(RX + HD, 2 * HD), HD + 16);  // three-phase staging
   static constexpr int NT2 = (MT * MT + NW - 1) / NW;     // dW2 tiles per wavefront
   static constexpr int NT1 = (MT1 * MT + NW - 1) / NW;    // dW1 tiles per wavefront
-  static constexpr long long K = 4 * C0 + C1 + 12;
-  static constexpr long long P = K * HD + HD + (long long)HD * HD + HD + (long long)HD * C + C;
-  static constexpr long long W1o = 0, b1o = K * HD, W2o = b1o + HD, b2o = W2o + (long long)HD * HD;
-  static constexpr long long W3o = b2o + HD, b3o = W3o + (long long)HD * C;
   static constexpr int WB = ((int)pg.train_end * (int)sizeof(T) + 15) / 16 * 16;
   static constexpr int OFF_PE = WB;
   static constexpr int OFF_BIAS = OFF_PE + 48 * 4;
@@ -207,11 +203,15 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.wpack)[i];
   for (int i = tid; i < 48; i += NTHR) pe_lds[i] = pe.v[i / 6][i % 6];
+  // canonical parameter offsets (the input width K includes the optional LOD input)
+  const long long b1o = (long long)m.K * HD, W2o = b1o + HD, b2o = W2o + (long long)HD * HD, W3o = b2o + HD;
+  const long long b3o = W3o + (long long)HD * C, Pn = b3o + C;
+  const float lod_norm = m.lod_in && m.M > 1 ? 1.f / (float)(m.M - 1) : 0.f;
   for (int i = tid; i < 2 * HD + 16; i += NTHR) {
     float v = 0.f;
-    if (i < HD) v = a.mlp[Cfg::b1o + i];
-    else if (i < 2 * HD) v = a.mlp[Cfg::b2o + i - HD];
-    else if (i < 2 * HD + C) v = a.mlp[Cfg::b3o + i - 2 * HD];
+    if (i < HD) v = a.mlp[b1o + i];
+    else if (i < 2 * HD) v = a.mlp[b2o + i - HD];
+    else if (i < 2 * HD + C) v = a.mlp[b3o + i - 2 * HD];
     b_lds[i] = v;
   }
   if (tid < 8) {
@@ -322,6 +322,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
         pe_values(pe_lds, f.ix, f.iy, g, pv);
 #pragma unroll
         for (int k = 0; k < 3; ++k) xs[IS::T_lat + k] = (T)pv[k];
+        xs[IS::T_lat + 3] = (T)(g == 0 ? (float)f.l * lod_norm : 0.f);  // LOD input (section 4.4)
 #pragma unroll
         for (int t = IS::T_used; t < S1; ++t) xs[t] = (T)0.f;
       }
@@ -577,12 +578,12 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   }
 
   // ---------------- per-block partial weight gradient (canonical layout) and loss
-  float* part = a.part_dw + (long long)blockIdx.x * Cfg::P;
+  float* part = a.part_dw + (long long)blockIdx.x * Pn;
   if (wave < MT) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int h = 16 * wave + 4 * g + i;
-      if (r < C) part[Cfg::W3o + (long long)h * C + r] = acc3[i];
+      if (r < C) part[W3o + (long long)h * C + r] = acc3[i];
     }
   }
 #pragma unroll
@@ -592,7 +593,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int h1 = 16 * (id / MT) + 4 * g + i, h2 = 16 * (id % MT) + r;
-        part[Cfg::W2o + (long long)h1 * HD + h2] = acc2[k][i];
+        part[W2o + (long long)h1 * HD + h2] = acc2[k][i];
       }
     }
   }
@@ -603,9 +604,10 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int t = 4 * (id / MT) + g;  // slot row 4t + gi with gi = i
-        const int kin = t < S1 ? IS::psi(i, t) : -1;
+        int kin = t < S1 ? IS::psi(i, t) : -1;
+        if (kin == IS::K_LOD && !m.lod_in) kin = -1;  // the LOD slot holds zeros without that input
         const int h = 16 * (id % MT) + r;
-        if (kin >= 0) part[Cfg::W1o + (long long)kin * HD + h] = acc1[k][i];
+        if (kin >= 0) part[(long long)kin * HD + h] = acc1[k][i];
       }
     }
   }
@@ -620,10 +622,10 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   if (tid % PARTS == 0) {
     const int row = tid / PARTS;
     if (row < HD) {
-      part[Cfg::b1o + row] = db1;
-      part[Cfg::b2o + row] = db2;
+      part[b1o + row] = db1;
+      part[b2o + row] = db2;
     }
-    if (row < C) part[Cfg::b3o + row] = db3;
+    if (row < C) part[b3o + row] = db3;
   }
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
   if (lane == 0) red[wave] = loss;
@@ -956,7 +958,7 @@ __device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args,
       a.mlp_m[p] = mm;
       a.mlp_v[p] = vv;
       a.mlp[p] = w;
-      scatter_param<T>((T*)a.wpack, args.pg, m.C0, m.C1, m.C, m.Hd, p, w, true);
+      scatter_param<T>((T*)a.wpack, args.pg, m.C0, m.C1, m.C, m.Hd, p, w, true, 0, 0, false, m.lod_in);
     }
     if (bx == 0 && threadIdx.x == 0 && a.loss_scale) {
       float sn = scale;

@@ -33,6 +33,7 @@ class Material(C.Structure):
         ("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32), ("num_mips", C.c_int32),
         ("c0", C.c_int32), ("c1", C.c_int32), ("b0", C.c_int32), ("b1", C.c_int32),
         ("grid_shift", C.c_int32), ("hidden", C.c_int32), ("activation", C.c_int32), ("posenc", C.c_int32),
+        ("lod_input", C.c_int32),
         ("num_levels", C.c_int32), ("input_width", C.c_int32),
         ("mip_w", C.c_int32 * MAX_MIPS), ("mip_h", C.c_int32 * MAX_MIPS), ("level_of_mip", C.c_int32 * MAX_MIPS),
         ("g0_w", C.c_int32 * MAX_LEVELS), ("g0_h", C.c_int32 * MAX_LEVELS),
@@ -159,11 +160,12 @@ def _stream(stream):
 
 # ------------------------------------------------------------------ descriptor
 def material_init(width, height, channels, c0, c1, b0, b1, hidden=64, num_mips=0, grid_shift=2,
-                  activation=ACT_RELU, posenc=PE_SINCOS) -> Material:
+                  activation=ACT_RELU, posenc=PE_SINCOS, lod_input=0) -> Material:
     m = Material()
     m.width, m.height, m.channels, m.num_mips = width, height, channels, num_mips
     m.c0, m.c1, m.b0, m.b1 = c0, c1, b0, b1
     m.grid_shift, m.hidden, m.activation, m.posenc = grid_shift, hidden, activation, posenc
+    m.lod_input = lod_input
     _check(_lib.ntc_material_init(C.byref(m)), "ntc_material_init")
     return m
 

@@ -12,7 +12,7 @@ def geometry(m):
     act = "relu" if m.activation == 0 else "hardgelu"
     pe = "sincos" if m.posenc == 0 else "triangle"
     return O.make_geometry(m.width, m.height, m.channels, m.c0, m.c1, m.b0, m.b1, Hd=m.hidden, M=m.num_mips,
-                           shift=m.grid_shift, act=act, pe=pe)
+                           shift=m.grid_shift, act=act, pe=pe, lod_input=bool(m.lod_input))
 
 
 def to_dev(a, dtype=None):

@@ -105,6 +105,33 @@ def test_decode_parity(lib, shape, prec):
     assert np.max(np.abs(got16 - got)) <= 2e-3  # FP16 output is the FP32 result rounded
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16", "fp8"])
+def test_decode_parity_lod_input(lib, prec):
+    """Decode with the LOD input of section 4.4 (K = 4 C0 + C1 + 13)."""
+    import torch
+    P = {"f32": lib.F32, "f16": lib.F16, "fp8": lib.FP8_E4M3}[prec]
+    m = lib.material_init(512, 512, 16, 16, 16, 2, 4, 64, lod_input=1)
+    g = geometry(m)
+    assert g.K == int(m.input_width) == 93
+    raw = synth.uniform_latents(9, int(m.latent_count))
+    mlp = mlp_in_unit_range(9, g.K, 64, 16)
+    n = 6007
+    q = synth.random_queries(9, n, g.M)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    out = torch.full((n * 16,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode(m, _packed(lib, m, raw), wp, P, queries_dev(q), n, out, lib.F32)
+    torch.cuda.synchronize()
+    lat = quantized_latents_oracle(g, raw)
+    ref = (O.decode_fp8(g, lat, mlp, q) if prec == "fp8" else O.decode(g, lat, mlp, q)).ravel()
+    err = np.abs(out.cpu().numpy().astype(np.float64) - ref)
+    print(f"LOD input {prec}: max-abs err {err.max():.3e}")
+    if prec == "fp8":  # against the oracle's e4m3 evaluation, the FP8 bars
+        assert err.mean() <= 2e-5 and np.quantile(err, 0.99) <= 1e-3 and err.max() <= 2e-2
+    else:
+        assert err.max() <= (1e-5 if prec == "f32" else 2e-3)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_decode_parity_triangle_encoding(lib, prec):
     """Decode with the triangular-wave positional encoding (section 4.3.2)."""

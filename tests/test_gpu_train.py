@@ -24,11 +24,11 @@ def lib():
 class Run:
     """One material with its GPU training state and the matching oracle state."""
 
-    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0):
+    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0, lod_input=0):
         import torch
         self.lib = lib
         self.prec = lib.F32 if prec is None else prec
-        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips, posenc=posenc)
+        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips, posenc=posenc, lod_input=lod_input)
         self.g = geometry(self.m)
         g = self.g
         raw = synth.uniform_latents(seed, int(self.m.latent_count))
@@ -118,6 +118,17 @@ def test_gradients_fp32(lib, name):
 def test_gradients_triangle_encoding(lib):
     """The triangular-wave positional encoding (section 4.3.2) through the training step."""
     run = Run(lib, *CONFIGS["chain"], seed=6, posenc=lib.PE_TRIANGLE)
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=False)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp)
+    _check_grads(run, hp)
+
+
+@pytest.mark.parametrize("name", ["chain", "ragged32"])
+def test_gradients_lod_input(lib, name):
+    """Training gradients with the LOD input of section 4.4 (its W1 row included)."""
+    run = Run(lib, *CONFIGS[name], seed=7, lod_input=1)
+    assert run.g.K == int(run.m.input_width)
     hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=False)
     lib.train_prepare(run.m, run.state, hp)
     run.step(hp)
@@ -217,10 +228,11 @@ def test_nonfinite_gradient_skips_step(lib):
     assert run.get("scale_state")[1] == 0
 
 
-@pytest.mark.parametrize("name", ["tiny", "chain", "c16"])
-def test_gradients_fp16(lib, name):
-    """FP16 matrix-core forward and backward, FP32 accumulation, loss scale 2^16."""
-    run = Run(lib, *CONFIGS[name], seed=12, prec=lib.F16)
+@pytest.mark.parametrize("name,lod_input", [("tiny", 0), ("chain", 0), ("c16", 0), ("ragged32", 0), ("chain", 1)])
+def test_gradients_fp16(lib, name, lod_input):
+    """FP16 matrix-core forward and backward, FP32 accumulation, loss scale 2^16 (and
+    with the LOD input of section 4.4)."""
+    run = Run(lib, *CONFIGS[name], seed=12, prec=lib.F16, lod_input=lod_input)
     hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=True, seed=2)
     lib.train_prepare(run.m, run.state, hp)
     run.step(hp)

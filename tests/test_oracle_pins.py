@@ -60,6 +60,24 @@ def test_input_width():
     assert O.make_geometry(256, 256, 8, 8, 8, 4, 4).K == 52
     assert O.make_geometry(2048, 2048, 12, 12, 12, 4, 4).K == 72
     assert O.make_geometry(4096, 4096, 16, 16, 16, 2, 4).K == 92
+    assert O.make_geometry(2048, 2048, 12, 12, 12, 4, 4, lod_input=True).K == 73
+
+
+def test_lod_input_value():
+    """Section 4.4's LOD input, read as the mip over the chain, l / (M - 1): a network
+    whose only path is that input (W1 row K-1 to hidden 0, W2 = I, W3 hidden 0 to every
+    output) outputs l / (M - 1) for each query's mip (M = 9: 0, 1/8, ..., 1)."""
+    g = O.make_geometry(256, 256, 4, 4, 4, 4, 4, Hd=16, lod_input=True)
+    assert g.M == 9 and g.K == 4 * 4 + 4 + 12 + 1
+    K, Hd, C = g.K, g.Hd, g.C
+    W1 = np.zeros((K, Hd)); W1[K - 1, 0] = 1.0
+    W3 = np.zeros((Hd, C)); W3[0, :] = 1.0
+    p = np.concatenate([W1.ravel(), np.zeros(Hd), np.eye(Hd).ravel(), np.zeros(Hd), W3.ravel(), np.zeros(C)])
+    q = np.zeros(9, dtype=synth.QUERY_DTYPE)
+    q["u"], q["v"], q["lod"] = 0.3, 0.7, np.arange(9)
+    lat = np.random.default_rng(0).uniform(-0.5, 0.5, g.latent_count)
+    y = O.decode(g, lat, p, q)
+    assert np.array_equal(y, np.repeat((np.arange(9) / 8.0)[:, None], C, axis=1))
 
 
 # ---------------------------------------------------------------- quantization (sec 4.2)

@@ -488,6 +488,65 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
                                           texels_per_s=float(area.sum() / (coh_ms * 1e-3))))
 
 
+def run_mixed(ntc, synth, torch, nq=4 * 2 ** 20, reps=5, seed=11):
+    """Mixed-material decode (Appendix A): 8 materials of the decode shape (16 channels,
+    2/4-bit, hidden 64; sides 512..4096), 4M queries naming their material in random
+    order, in runs of 64 (screen regions), and for comparison sorted by material and
+    decoded grouped."""
+    d = DECODE
+    r = np.random.default_rng(seed)
+    mats, packed, wpacks = [], [], []
+    for i in range(8):
+        w = int(2 ** (9 + i % 4))
+        m = ntc.material_init(w, w, d["C"], d["c0"], d["c1"], d["b0"], d["b1"], d["hidden"])
+        raw = torch.from_numpy(synth.uniform_latents(seed + i, int(m.latent_count))).cuda()
+        p = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        ntc.quantize_latents(m, raw, p)
+        mlp = torch.from_numpy(synth.xavier_mlp(seed + i, m.input_width, d["hidden"], d["C"])).cuda()
+        wp = torch.zeros(ntc.mlp_packed_bytes(m, ntc.F16), dtype=torch.uint8, device="cuda")
+        ntc.pack_mlp(m, mlp, ntc.F16, wp)
+        mats.append(m); packed.append(p); wpacks.append(wp)
+    table = ntc.DecodeTable(mats, packed, wpacks, ntc.F16)
+    out = torch.empty(nq * d["C"], dtype=torch.float16, device="cuda")
+
+    def timed(call):
+        for _ in range(2):
+            call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {}
+    for order in ("random", "runs64"):
+        mat = r.integers(0, 8, nq) if order == "random" else np.repeat(r.integers(0, 8, nq // 64 + 1), 64)[:nq]
+        mq = np.zeros(nq, dtype=ntc.MIXED_QUERY_DTYPE)
+        mq["u"] = r.random(nq, dtype=np.float32)
+        mq["v"] = r.random(nq, dtype=np.float32)
+        mq["material"] = mat
+        mq["lod"] = np.floor(r.random(nq) * np.array([m.num_mips for m in mats])[mat]).astype(np.int32)
+        mq_dev = torch.from_numpy(mq.view(np.uint8).copy()).cuda()
+        ms = timed(lambda: ntc.decode_mixed(table, mq_dev, nq, out, ntc.F16))
+        res[order] = dict(queries=nq, ms=round(ms, 4), texels_per_s=nq / (ms * 1e-3))
+        log(f"[bench] mixed-material decode ({order}, 8 materials): {ms:.3f} ms for {nq} queries -> "
+            f"{nq / (ms * 1e-3):.3e} texels/s")
+        if order == "random":  # the same queries sorted by material, decoded grouped
+            idx = np.argsort(mat, kind="stable")
+            qs = np.zeros(nq, dtype=synth.QUERY_DTYPE)
+            qs["u"], qs["v"], qs["lod"] = mq["u"][idx], mq["v"][idx], mq["lod"][idx]
+            offs = np.concatenate([[0], np.cumsum(np.bincount(mat, minlength=8))])
+            qs_dev = torch.from_numpy(qs.view(np.uint8).copy()).cuda()
+            ms = timed(lambda: ntc.decode_grouped(table, qs_dev, offs, out, ntc.F16))
+            res["sorted_grouped"] = dict(queries=nq, ms=round(ms, 4), texels_per_s=nq / (ms * 1e-3))
+            log(f"[bench] same queries sorted by material, grouped decode: {ms:.3f} ms -> "
+                f"{nq / (ms * 1e-3):.3e} texels/s")
+    return res
+
+
 def cpu_baseline():
     """FP64 oracle on the host: one training step of the same material, gradient part
     on 32,768 of the 262,144 samples, dense per-latent part (noise, Adam, clamp) on all
@@ -587,6 +646,7 @@ def main():
     decode = None
     if not args.no_decode:
         decode = run_decode(ntc, synth, torch, args.decode_queries, args.decode_reps)
+        decode["mixed_material"] = run_mixed(ntc, synth, torch)
 
     batched = None
     if not args.no_batched:

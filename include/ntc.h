@@ -433,6 +433,24 @@ ntc_status ntc_train_step_grouped(const ntc_material* mats, int32_t nmat, const 
  *     launches are enqueued, so the call can be captured in a HIP graph.
  */
 size_t ntc_decode_table_bytes(int32_t nmat);
+
+/*
+ * Mixed-material decode (Appendix A, handling divergence): queries in any order, each
+ * naming its material (an index into mats; out-of-range indices are clamped).  A
+ * wavefront's 16-texel tile gathers every texel from its own material, then evaluates
+ * the network once per distinct material in the tile (that material's weights for the
+ * whole tile, outputs kept for its texels), as the paper's divergence loop does.  All
+ * materials share one decode shape (c0, c1, channels, hidden, b0, b1, activation,
+ * posenc); at most 64; NTC_F16 decode packs; the table from ntc_decode_table_init
+ * (same hash rule as ntc_decode_grouped).  out holds n x C values in query order.
+ */
+typedef struct {
+  float u, v;
+  int32_t lod;
+  int32_t material;
+} ntc_mixed_query;
+ntc_status ntc_decode_mixed(const ntc_material* mats, int32_t nmat, const void* table, ntc_dtype precision,
+                            const ntc_mixed_query* q, int64_t n, void* out, ntc_dtype out_dtype, void* stream);
 ntc_status ntc_decode_table_init(const ntc_material* mats, int32_t nmat, const uint8_t* const* packed_latents,
                                  const void* const* mlp_packed, ntc_dtype precision, void* table,
                                  size_t table_bytes);

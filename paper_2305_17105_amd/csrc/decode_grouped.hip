@@ -88,7 +88,34 @@ hipError_t grouped_fp8_t(const ntc_material* mats, const char* tab, unsigned lon
   });
 }
 
+template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
+hipError_t mixed_t(const char* tab, unsigned long long hash, int nmat, const PeTable& pe, const ntc_mixed_query* q,
+                   long long n, void* out, bool out_f16, hipStream_t s) {
+  const size_t lds = 48 * 4 + (size_t)nmat * kMaxLevels * sizeof(LevelBytes);
+  auto kern = decode_mixed_kernel<C0, C1, C, HD, B0, B1, ACT>;
+  static const int per_cu = blocks_per_cu(kern, 48 * 4 + (size_t)kMixedMax * kMaxLevels * sizeof(LevelBytes));
+  const long long tiles = (n + 15) / 16;
+  const long long grid = std::min((tiles + 3) / 4, (long long)device_cus() * per_cu);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, tab, pe, hash, nmat, q, n, out, out_f16 ? 1 : 0);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_decode_mixed(const ntc_material* mats, int nmat, const void* table, const ntc_mixed_query* q,
+                               long long n, void* out, bool out_f16, hipStream_t s) {
+  const char* tab = reinterpret_cast<const char*>(table);
+  const unsigned long long hash = group_hash(mats, nmat);
+  const ntc_material& m = mats[0];
+  const PeTable pe = pe_table(m);
+#define NTC_X(a, b, cc, h, x0, x1)                                                                          \
+  if (m.c0 == a && m.c1 == b && m.channels == cc && m.hidden == h && m.b0 == x0 && m.b1 == x1)            \
+    return m.activation ? mixed_t<a, b, cc, h, x0, x1, 1>(tab, hash, nmat, pe, q, n, out, out_f16, s)     \
+                        : mixed_t<a, b, cc, h, x0, x1, 0>(tab, hash, nmat, pe, q, n, out, out_f16, s);
+  NTC_DECODE_SHAPES(NTC_X)
+#undef NTC_X
+  return hipErrorInvalidValue;
+}
 
 // FNV-1a over the kernel views of the materials: what a table was built for.
 unsigned long long group_hash(const ntc_material* mats, int nmat) {

@@ -134,6 +134,33 @@ __device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
     }
 }
 
+// Latent slots of the paired FP16 layout from a code window: G0 two channels per
+// instruction ((1024 + code) / N - (N/2 - 1 + 1024) / N is exact), then the G1 pairs.
+template <int C0, int C1, int B0, int B1, int S1>
+__device__ inline void paired_inputs(const CodeWindow<C0, C1, B0, B1>& R, int g, _Float16 (&xs)[S1]) {
+  using Raw = CodeWindow<C0, C1, B0, B1>;
+  constexpr int HALF = 16 / B0, N0 = 1 << B0;
+  const f16x2 sc = {(_Float16)(1.f / N0), (_Float16)(1.f / N0)};
+  const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
+  const f16x2 of = {o, o};
+#pragma unroll
+  for (int d = 0; d < Raw::NW0; ++d)
+#pragma unroll
+    for (int c = 0; c < HALF; ++c) {
+      const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
+      xs[2 * (d * HALF + c)] = x[0];
+      xs[2 * (d * HALF + c) + 1] = x[1];
+    }
+  f16x2 v[Raw::NW1 * (4 / B1)];
+  g1_pairs(R, g, v);
+  constexpr int G0S = paired_g0_slots(C0, B0);
+#pragma unroll
+  for (int p = 0; p < Raw::NW1 * (4 / B1); ++p) {
+    xs[G0S + 2 * p] = v[p][0];
+    xs[G0S + 2 * p + 1] = v[p][1];
+  }
+}
+
 // Lane group g's four output channels 4g .. 4g+3 of texel s.
 template <int C>
 __device__ inline void store_out(void* __restrict__ out, int out_f16, long long s, long long n, int g, f32x4 y) {
@@ -324,28 +351,7 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
     using Raw = CodeWindow<C0, C1, B0, B1>;
     auto assemble = [&](const Raw& R, T (&xs)[S1]) {
       if constexpr (DL::paired) {
-        {  // G0: two channels per instruction; (1024 + code) / N - (N/2 - 1 + 1024) / N is exact
-          constexpr int HALF = 16 / B0, N0 = 1 << B0;
-          const f16x2 sc = {(_Float16)(1.f / N0), (_Float16)(1.f / N0)};
-          const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
-          const f16x2 of = {o, o};
-#pragma unroll
-          for (int d = 0; d < Raw::NW0; ++d)
-#pragma unroll
-            for (int c = 0; c < HALF; ++c) {
-              const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
-              xs[2 * (d * HALF + c)] = x[0];
-              xs[2 * (d * HALF + c) + 1] = x[1];
-            }
-        }
-        f16x2 v[Raw::NW1 * (4 / B1)];
-        g1_pairs(R, g, v);
-        constexpr int G0S = paired_g0_slots(C0, B0);
-#pragma unroll
-        for (int p = 0; p < Raw::NW1 * (4 / B1); ++p) {
-          xs[G0S + 2 * p] = v[p][0];
-          xs[G0S + 2 * p + 1] = v[p][1];
-        }
+        paired_inputs(R, g, xs);
       } else {
 #pragma unroll
         for (int t = 0; t < C0; ++t) xs[t] = (T)dequant<B0>(code_at<B0>(R.g0, t));
@@ -462,6 +468,102 @@ __global__ __launch_bounds__(256) void decode_grouped_kernel(const char* __restr
                                                    b1 + HD, b1 + 2 * HD, q + sg.q0, sg.n, TexelRect{},
                                                    out + sg.o0 * (out_f16 ? 2 : 4), out_f16,
                                                    (int)blockIdx.x - sg.block0, nb);
+}
+
+// Mixed-material decode (Appendix A): the queries of a tile may name different
+// materials of one shape.  Each lane gathers its own material's codes (geometry and
+// packed latents per lane, per-material level offsets in LDS); then the wave loops
+// over the tile's distinct materials, broadcasting one per iteration and running the
+// three layers with that material's weights (read straight from its pack, which L1
+// and L2 keep), and stores the texels of that material.  FP16 packs (paired layout).
+template <int C0, int C1, int C, int HD, int B0, int B1, int ACT>
+__global__ __launch_bounds__(256) void decode_mixed_kernel(const char* __restrict__ table, PeTable pe,
+                                                           unsigned long long hash, int nmat,
+                                                           const ntc_mixed_query* __restrict__ q, long long n,
+                                                           void* __restrict__ out, int out_f16) {
+  using T = _Float16;
+  using DL = DecodeLayout<T, C0, C1, HD, B0, B1, true>;
+  static_assert(DL::paired, "mixed decode reads the paired layout");
+  constexpr PackGeom pg = DL::pg;
+  constexpr int S1 = pg.S1, SH = pg.SH, MT = pg.MT, WB = DL::WB;
+  using Raw = CodeWindow<C0, C1, B0, B1>;
+  if (*reinterpret_cast<const unsigned long long*>(table) != hash) return;
+  const GroupEntry* __restrict__ tab = reinterpret_cast<const GroupEntry*>(table + kGroupHeaderBytes);
+  extern __shared__ __align__(16) char smem[];
+  float* pe_lds = reinterpret_cast<float*>(smem);
+  LevelBytes* lb = reinterpret_cast<LevelBytes*>(pe_lds + 48);
+  for (int i = threadIdx.x; i < 48; i += blockDim.x) pe_lds[i] = pe.v[i / 6][i % 6];
+  for (int i = threadIdx.x; i < nmat * kMaxLevels; i += blockDim.x) {
+    const DevMat& dm = tab[i / kMaxLevels].m;
+    const int j = i % kMaxLevels;
+    LevelBytes b;
+    b.g0 = (uint32_t)dm.g0_pk[j];
+    b.g1 = (uint32_t)dm.g1_pk[j];
+    b.g0_last = (uint32_t)(dm.g0_pk_end[j] * 4);
+    b.g1_last = (uint32_t)(dm.g1_pk_end[j] * 4);
+    lb[i] = b;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const long long tiles = (n + 15) / 16, stride = (long long)gridDim.x * 4;
+  for (long long tile = (long long)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
+    const long long s = tile * 16 + r;
+    const bool valid = s < n;
+    float u = 0.f, v = 0.f;
+    int lod = 0, mt = 0;
+    if (valid) {
+      const ntc_mixed_query qq = q[s];
+      u = qq.u;
+      v = qq.v;
+      lod = qq.lod;
+      mt = min(max(qq.material, 0), nmat - 1);
+    }
+    const GroupEntry& e = tab[mt];
+    Raw R;
+    R.fetch(e.m, lb + mt * kMaxLevels, reinterpret_cast<const uint32_t*>(e.packed), u, v, lod, g);
+    T xs[S1];
+    paired_inputs(R, g, xs);
+    {
+      float pv[3];
+      pe_values(pe_lds, R.ix, R.iy, g, pv);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xs[pg.T_lat + k] = (T)pv[k];
+      const float lod_norm = e.m.lod_in && e.m.M > 1 ? 1.f / (float)(e.m.M - 1) : 0.f;
+      xs[pg.T_lat + 3] = (T)(g == 0 ? (float)R.l * lod_norm : 0.f);
+#pragma unroll
+      for (int t = pg.T_used; t < S1; ++t) xs[t] = (T)0.f;
+    }
+    // the tile's distinct materials, one network evaluation each
+    unsigned long long pending = __ballot(valid);
+    while (pending) {
+      const int cur = __builtin_amdgcn_readfirstlane(__shfl(mt, (int)__builtin_ctzll(pending)));
+      const T* __restrict__ w = reinterpret_cast<const T*>(tab[cur].wpack);
+      const float* __restrict__ bias = reinterpret_cast<const float*>(reinterpret_cast<const char*>(w) + WB);
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(bias + 16 * mo + 4 * g);
+        acc[mo] = mma_slots<S1>(acc[mo], w + pg.L1 + mo * S1 * 64, xs, lane);
+      }
+      T h[SH];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(bias + HD + 16 * mo + 4 * g);
+        acc[mo] = mma_slots<SH>(acc[mo], w + pg.L2 + mo * SH * 64, h, lane);
+      }
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
+      f32x4 y = {0.f, 0.f, 0.f, 0.f};
+      if (4 * g < C) y = *reinterpret_cast<const f32x4*>(bias + 2 * HD + 4 * g);
+      y = mma_slots<SH>(y, w + pg.L3, h, lane);
+      const bool mine = valid && mt == cur;
+      if (mine) store_out<C>(out, out_f16, s, n, g, y);
+      pending &= ~__ballot(mine);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ FP8-e4m3 decode

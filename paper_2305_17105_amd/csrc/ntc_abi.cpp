@@ -881,6 +881,26 @@ ntc_status ntc_decode_table_init(const ntc_material* mats, int32_t nmat, const u
   return hip_status(hipMemcpy(table, host.data(), host.size(), hipMemcpyHostToDevice), "ntc_decode_table_init");
 }
 
+ntc_status ntc_decode_mixed(const ntc_material* mats, int32_t nmat, const void* table, ntc_dtype precision,
+                            const ntc_mixed_query* q, int64_t n, void* out, ntc_dtype out_dtype, void* stream) {
+  if (!mats || nmat < 1 || nmat > kMixedMax) return fail(NTC_E_INVALID, "nmat must be in 1..64");
+  ntc_status st = NTC_OK;
+  for (int i = 0; i < nmat; ++i) {
+    if ((st = check_decode(mats + i, precision, out_dtype)) != NTC_OK) return st;
+    const ntc_material& a = mats[0];
+    const ntc_material& b = mats[i];
+    if (a.c0 != b.c0 || a.c1 != b.c1 || a.channels != b.channels || a.hidden != b.hidden || a.b0 != b.b0 ||
+        a.b1 != b.b1 || a.activation != b.activation || a.posenc != b.posenc)
+      return fail(NTC_E_UNSUPPORTED, "mixed decode needs materials of one decode shape");
+  }
+  if (precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "mixed decode is built for F16 decode packs");
+  if (n < 0) return fail(NTC_E_INVALID, "n < 0");
+  if (n == 0) return NTC_OK;
+  if (!table || !q || !out) return fail(NTC_E_INVALID, "NULL buffer");
+  return hip_status(launch_decode_mixed(mats, nmat, table, q, n, out, out_dtype == NTC_F16, (hipStream_t)stream),
+                    "ntc_decode_mixed");
+}
+
 ntc_status ntc_decode_grouped(const ntc_material* mats, int32_t nmat, const void* table, ntc_dtype precision,
                               const ntc_query* q, const int64_t* offsets, void* out, ntc_dtype out_dtype,
                               void* stream) {

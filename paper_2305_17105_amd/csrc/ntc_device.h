@@ -59,6 +59,7 @@ struct GroupArgs {
 };
 // Device table of a grouped decode: a header (hash of the materials) then the entries.
 constexpr int kGroupHeaderBytes = 256;
+constexpr int kMixedMax = 64;  // materials of one mixed-material decode
 
 // Coherent decode source: the texels of rectangle [x0, x0+w) x [y0, y0+h) of mip lod,
 // row-major (w == 0: queries come from a query array instead).  inv_w, inv_h = 1 / mip

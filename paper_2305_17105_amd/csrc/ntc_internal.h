@@ -42,6 +42,9 @@ hipError_t launch_decode(const ntc_material& m, const uint8_t* packed, const voi
                          const ntc_query* q, long long n, const TexelRect* rect, void* out, bool out_f16,
                          hipStream_t s);
 
+// Mixed-material decode (FP16 decode packs of one shape, at most kMixedMax materials).
+hipError_t launch_decode_mixed(const ntc_material* mats, int nmat, const void* table, const ntc_mixed_query* q,
+                               long long n, void* out, bool out_f16, hipStream_t s);
 // Filtered decode (FP16 decode packs): filter 1 bilinear, 2 trilinear, 3 stochastic.
 hipError_t launch_decode_filtered(const ntc_material& m, const uint8_t* packed, const void* wpack,
                                   const ntc_filter_query* q, long long n, int filter, uint64_t seed, void* out,

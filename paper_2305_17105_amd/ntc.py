@@ -26,6 +26,7 @@ PE_SINCOS, PE_TRIANGLE = 0, 1
 MAX_LEVELS, MAX_MIPS = 8, 16
 
 QUERY_DTYPE = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
+MIXED_QUERY_DTYPE = np.dtype([("u", "<f4"), ("v", "<f4"), ("lod", "<i4"), ("material", "<i4")])
 
 
 class Material(C.Structure):
@@ -112,6 +113,8 @@ _sig = {
                                          _P(C.c_void_p), _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p,
                                          C.c_void_p]),
     "ntc_decode_table_bytes": (C.c_size_t, [C.c_int32]),
+    "ntc_decode_mixed": (C.c_int, [_P(Material), C.c_int32, C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.c_int, C.c_void_p]),
     "ntc_decode_table_init": (C.c_int, [_P(Material), C.c_int32, _P(C.c_void_p), _P(C.c_void_p), C.c_int,
                                         C.c_void_p, C.c_size_t]),
     "ntc_decode_grouped": (C.c_int, [_P(Material), C.c_int32, C.c_void_p, C.c_int, C.c_void_p, _P(C.c_int64),
@@ -376,6 +379,13 @@ class DecodeTable:
         wp = (C.c_void_p * n)(*[_ptr(w) for w in wpacks])
         _check(_lib.ntc_decode_table_init(self.mats, n, pk, wp, precision, _ptr(self.table), nbytes),
                "ntc_decode_table_init")
+
+
+def decode_mixed(table: DecodeTable, mqueries, n, out, out_dtype, stream=None):
+    """Decode n queries that each name their material (16-byte records u, v, lod,
+    material) in one launch (ntc_decode_mixed); out in query order."""
+    _check(_lib.ntc_decode_mixed(table.mats, table.nmat, _ptr(table.table), table.precision, _ptr(mqueries), int(n),
+                                 _ptr(out), out_dtype, _stream(stream)), "ntc_decode_mixed")
 
 
 def decode_grouped(table: DecodeTable, queries, offsets, out, out_dtype, stream=None, precision=None):

@@ -409,3 +409,52 @@ def test_grouped_graph_replay_matches_eager(lib):
                 # order of floating-point additions only (see _assert_states_close)
                 assert float((d <= 1e-4).double().mean()) >= 0.999, (s, i, k)
                 assert float((a - v.double()).abs().max()) <= 2 * 0.01 * (s + 1), (s, i, k)
+
+
+@pytest.mark.parametrize("kind", [(16, 16, 2, 4, 64), (8, 8, 4, 4, 32), (10, 10, 4, 4, 64)])
+@pytest.mark.parametrize("order", ["random", "runs"])
+def test_mixed_decode_equals_per_material(lib, kind, order):
+    """Mixed-material decode (Appendix A's divergence loop): queries naming one of six
+    materials of a shape, in random order or in runs; every texel equals its
+    material's own decode bit for bit, and the oracle's within the FP16 bar.  Material
+    indices outside the set are clamped."""
+    import torch
+    C, c0, b0, b1, hd = kind
+    r = np.random.default_rng(70)
+    ms, pk, wp, raws, mlps = [], [], [], [], []
+    for i in range(6):
+        W = int(2 ** r.integers(6, 10))
+        m = lib.material_init(W, W, C, c0, c0, b0, b1, hd)
+        raw = synth.uniform_latents(700 + i, int(m.latent_count))
+        p = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+        lib.quantize_latents(m, to_dev(raw), p)
+        mlp = mlp_in_unit_range(710 + i, int(m.input_width), hd, C)
+        w = torch.zeros(lib.mlp_packed_bytes(m, lib.F16), dtype=torch.uint8, device="cuda")
+        lib.pack_mlp(m, to_dev(mlp), lib.F16, w)
+        ms.append(m); pk.append(p); wp.append(w); raws.append(raw); mlps.append(mlp)
+    n = 20011
+    mq = np.zeros(n, dtype=lib.MIXED_QUERY_DTYPE)
+    mq["u"] = r.uniform(0, 1, n)
+    mq["v"] = r.uniform(0, 1, n)
+    mq["material"] = r.integers(0, 6, n) if order == "random" else np.repeat(r.integers(0, 6, n // 37 + 1), 37)[:n]
+    mq["material"][:3] = [-3, 6, 99]  # clamped to 0, 5, 5
+    mat = np.clip(mq["material"], 0, 5)
+    for i, m in enumerate(ms):
+        sel = mat == i
+        mq["lod"][sel] = r.integers(0, int(m.num_mips), int(sel.sum()))
+    table = lib.DecodeTable(ms, pk, wp, lib.F16)
+    out = torch.full((n * C,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode_mixed(table, torch.from_numpy(mq.view(np.uint8).copy()).cuda(), n, out, lib.F32)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(n, C)
+    for i, m in enumerate(ms):
+        sel = np.nonzero(mat == i)[0]
+        q = np.zeros(len(sel), dtype=synth.QUERY_DTYPE)
+        q["u"], q["v"], q["lod"] = mq["u"][sel], mq["v"][sel], mq["lod"][sel]
+        ref = torch.full((len(sel) * C,), float("nan"), dtype=torch.float32, device="cuda")
+        lib.decode(m, pk[i], wp[i], lib.F16, queries_dev(q), len(sel), ref, lib.F32)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[sel], ref.cpu().numpy().reshape(-1, C)), i
+        g = geometry(m)
+        o = O.decode(g, quantized_latents_oracle(g, raws[i]), mlps[i], q)
+        assert np.max(np.abs(got[sel] - o)) <= 2e-3

@@ -660,17 +660,29 @@ __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, co
   __syncthreads();
   const long long s0 = (long long)bi * a.per_block;
   const long long s1 = min(a.n, s0 + a.per_block);
-  for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-    const ntc_query qq = q[s];
-    const Footprint f = locate(m, qq.u, qq.v, qq.lod, 0);
-    const SampleBins sb = sample_bins(f, tg);
-    for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
-      for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
-        const int b = sort_bin(tg, sb.j, tx, ty, f.ax, f.ay);
-        if (SCATTER)
-          a.list[atomicAdd(&hist[b], 1)] = make_int4(__float_as_int(qq.u), __float_as_int(qq.v), qq.lod, (int)s);
-        else atomicAdd(&hist[b], 1);
-      }
+  constexpr int U = 4;  // queries loaded together per thread and round
+  for (long long s = s0 + threadIdx.x; s < s1; s += U * blockDim.x) {
+    ntc_query qq[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long long sk = s + (long long)k * blockDim.x;
+      if (sk < s1) qq[k] = q[sk];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long long sk = s + (long long)k * blockDim.x;
+      if (sk >= s1) break;
+      const Footprint f = locate(m, qq[k].u, qq[k].v, qq[k].lod, 0);
+      const SampleBins sb = sample_bins(f, tg);
+      for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
+        for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
+          const int b = sort_bin(tg, sb.j, tx, ty, f.ax, f.ay);
+          if (SCATTER)
+            a.list[atomicAdd(&hist[b], 1)] =
+                make_int4(__float_as_int(qq[k].u), __float_as_int(qq[k].v), qq[k].lod, (int)sk);
+          else atomicAdd(&hist[b], 1);
+        }
+    }
   }
   if (!SCATTER) {
     __syncthreads();
@@ -722,19 +734,36 @@ __global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, cons
 
 // One block of 1024 threads: exclusive scan over the sort bins of their totals (list
 // positions), then per tile its start, total and work items (at most tg.chunk samples
-// per item, at least one), and the exclusive scan of the items over the tiles.
-template <int PER>
-__device__ inline int block_exclusive_scan(int v, int* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int o = tid >= d ? sh[tid - d] : 0;
-    __syncthreads();
-    sh[tid] += o;
-    __syncthreads();
+// per item, at least one), the exclusive scan of the items over the tiles, and the tile
+// of every item.
+// Exclusive scan over the 1024 threads of a block (wavefront scans by shuffles, then
+// the 16 wavefront totals); `total` receives the sum.  sh: 33 ints of LDS.
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
   }
-  return sh[tid] - v;
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int t = lane < 16 ? sh[lane] : 0;
+    int ti = t;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const int o = __shfl_up(ti, d, 64);
+      if (lane >= d) ti += o;
+    }
+    if (lane < 16) sh[16 + lane] = ti - t;
+    if (lane == 15) sh[32] = ti;
+  }
+  __syncthreads();
+  const int r = sh[16 + w] + incl - v;
+  total = sh[32];
+  __syncthreads();  // sh is reused by the next scan
+  return r;
 }
 
 __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __restrict__ total,
@@ -755,7 +784,8 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
       tv[e] = (e < per && b0 + e < nb) ? total[b0 + e] : 0;
       st += tv[e];
     }
-    int pt = block_exclusive_scan<kPer>(st, s_scan);
+    int all;
+    int pt = block_exclusive_scan(st, s_scan, all);
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       if (e < per && b0 + e < nb) {
@@ -764,9 +794,9 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
         pt += tv[e];
       }
     }
-    if (tid == 1023) {
-      s_base[nb] = s_scan[1023];
-      base[nb] = s_scan[1023];
+    if (tid == 0) {
+      s_base[nb] = all;
+      base[nb] = all;
     }
   }
   __syncthreads();
@@ -774,28 +804,47 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
     const int per = (nt + 1023) / 1024;
     const int t0 = min(nt, tid * per);
     int items = 0;
-    for (int e = 0; e < per && t0 + e < nt; ++e) {
+    int tk[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      tk[e] = 0;
       const int t = t0 + e;
-      int j = 0;
-      while (j + 1 < kMaxLevels && t >= tg.tile_base[j + 1]) ++j;
-      const int first = tg.bin_base[j] + (t - tg.tile_base[j]) * tg.sb[j] * tg.sb[j];
-      const int st = s_base[first];
-      const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
-      tile_start[t] = st;
-      tile_total[t] = tot;
-      items += max(1, (tot + tg.chunk - 1) / tg.chunk);
+      if (e < per && t < nt) {
+        int j = 0;
+        while (j + 1 < kMaxLevels && t >= tg.tile_base[j + 1]) ++j;
+        const int first = tg.bin_base[j] + (t - tg.tile_base[j]) * tg.sb[j] * tg.sb[j];
+        const int st = s_base[first];
+        const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
+        tile_start[t] = st;
+        tile_total[t] = tot;
+        tk[e] = max(1, (tot + tg.chunk - 1) / tg.chunk);
+        items += tk[e];
+      }
     }
-    int pi = block_exclusive_scan<kPer>(items, s_scan);
-    for (int e = 0; e < per && t0 + e < nt; ++e) {
-      const int tot = tile_total[t0 + e];
-      const int k = max(1, (tot + tg.chunk - 1) / tg.chunk);
-      item_base[t0 + e] = pi;
-      for (int i = 0; i < k; ++i) item_tile[pi + i] = t0 + e;
-      pi += k;
+    int all;
+    int pi = block_exclusive_scan(items, s_scan, all);  // every s_base read above precedes its barriers
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      if (e < per && t0 + e < nt) {
+        item_base[t0 + e] = pi;
+        s_base[t0 + e] = pi;  // first item of each tile, for the item -> tile search
+        pi += tk[e];
+      }
     }
-    if (tid == 1023) {
-      item_base[nt] = s_scan[1023];
-      *nitems = s_scan[1023];
+    if (tid == 0) {
+      item_base[nt] = all;
+      *nitems = all;
+    }
+    __syncthreads();
+    // tile of every item: the last tile whose first item is at or before it
+    for (int i = tid; i < all; i += 1024) {
+      int lo = 0, hi = nt - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_base[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      item_tile[i] = lo;
     }
   }
 }
@@ -840,7 +889,7 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   }
 }
 
-__global__ void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
+__global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
                                    const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
                                    float out_scale) {
   lat_partial_body(m, tg, item_base, part, region_max, lat_grad, out_scale, blockIdx.y, blockIdx.x, gridDim.x);

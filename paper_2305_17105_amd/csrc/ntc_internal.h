@@ -77,7 +77,7 @@ struct TrainPlan {
   size_t off_counts, off_offsets, off_total, off_base, off_tstart, off_ttotal, off_ibase, off_itile, off_misc;
   size_t off_list;
   size_t off_part_lat;
-  size_t off_part_dw, off_part_loss, off_tmp, off_grad, total;
+  size_t off_part_dw, off_part_loss, off_grad, total;
 };
 // tune == nullptr: the tuning table's entry for the material's shape (or the defaults)
 TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTune* tune = nullptr);

@@ -18,8 +18,8 @@
 //     footprint anchor); secondary copies only feed the owned latents.  At the end
 //     of a work item the tile's gradient is written densely with plain stores
 //     (single-item tiles) or as a partial (tiles split over several items).
-//  3. lat_partial_reduce: sums the partials of split tiles in item order.
-//  4. dw_reduce1/2: per-block weight-gradient partials summed in a fixed order,
+//  3. lat_partial_reduce: sums the partials of split tiles in a fixed order.
+//  4. dw_reduce: per-block weight-gradient partials summed in a fixed order,
 //     non-finite check, loss.
 //  5. adam_kernel: dense bias-corrected Adam, clamp to the quantization range, next
 //     step's noisy forward latents, refreshed weight packs, FP16 loss scale.
@@ -35,9 +35,9 @@ namespace ntc {
 
 constexpr int kChunkDefault = 256;  // samples per work item unless tuned (the tuner picked 256 on every shape)
 constexpr int kBinBlockSamples = 1024;
+constexpr int kBinThreads = 1024;  // threads of a binning block (one sample each)
 constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
 constexpr int kSortedCells = 4096; // levels with at most this many G0 cells are sorted by anchor cell
-constexpr int kDwYBlocks = 4;     // block rows of the first weight-gradient reduction stage (x4 row groups each)
 
 struct TrainArgs {
   const float* lat_fwd;
@@ -691,7 +691,7 @@ __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, co
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void bin_kernel(DevMat m, TileGeom tg, BinArgs a) {
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(DevMat m, TileGeom tg, BinArgs a) {
   bin_body<SCATTER>(m, tg, a, a.q, blockIdx.x);
 }
 
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int*
   bin_scan2_body(tg, total, base, tile_start, tile_total, item_base, item_tile, nitems, s_base, s_scan);
 }
 
-// Latent gradients of tiles split over several work items: partials summed in item order.
+// Latent gradients of tiles split over several work items: partials summed in a fixed order.
 // tile: the latent tile; bx, gx: this block's share of the tile's region (of gx).
 __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom& tg, const int* __restrict__ item_base,
                                                  const float* __restrict__ part, int region_max,
@@ -874,9 +874,19 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
   const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
   for (int k = bx * blockDim.x + threadIdx.x; k < RG; k += gx * blockDim.x) {
-    float s = 0.f;
-#pragma unroll 8
-    for (int i = 0; i < items; ++i) s += part[(long long)(it0 + i) * region_max + k];
+    // four running sums, many loads in flight: tiles of the small levels have many items
+    const float* src = part + (long long)it0 * region_max + k;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int i = 0;
+#pragma unroll 4
+    for (; i + 4 <= items; i += 4) {
+      s0 += src[(long long)i * region_max];
+      s1 += src[(long long)(i + 1) * region_max];
+      s2 += src[(long long)(i + 2) * region_max];
+      s3 += src[(long long)(i + 3) * region_max];
+    }
+    for (; i < items; ++i) s0 += src[(long long)i * region_max];
+    const float s = (s0 + s1) + (s2 + s3);
     long long gi;
     if (k < R0) {
       const int c = k % C0, cell = k / C0, cx = cell % T, cy = cell / T;
@@ -896,61 +906,53 @@ __global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg,
 }
 
 // ------------------------------------------------------------------ weight-gradient reduction
-// Stage 1: block (64 params x 4 row groups) sums its share of the per-block partial rows.
-// bx: block of 64 parameters; by: block row (of gy), each of 4 row groups.
-__device__ __forceinline__ void dw_reduce1_body(int G, long long P, const float* __restrict__ part,
-                                                float* __restrict__ tmp, int bx, int by, int gy) {
-  __shared__ float red[4][64];
-  const long long p = (long long)bx * 64 + (threadIdx.x & 63);
-  const int rg = by * 4 + (threadIdx.x >> 6);
-  const int ngroups = gy * 4;
-  const int per = (G + ngroups - 1) / ngroups;
-  const int b0 = rg * per, b1 = min(G, b0 + per);
+// The fused kernel's G per-block partial rows summed in a fixed order: block bx takes
+// parameters [64 bx, 64 bx + 64), each of its kDwWaves wavefronts a contiguous share of
+// the rows, and the shares are added in order; non-finite sums raise the flag.  Block 0
+// also sums the per-block losses.
+constexpr int kDwWaves = 16;
+__device__ __forceinline__ void dw_reduce_body(int G, long long P, const float* __restrict__ part,
+                                               float* __restrict__ grad, const float* __restrict__ part_loss,
+                                               float* __restrict__ loss_out, float norm, int32_t* flag,
+                                               float out_scale, int bx) {
+  __shared__ float red[kDwWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long p = (long long)bx * 64 + lane;
+  const int per = (G + kDwWaves - 1) / kDwWaves, b0 = w * per, b1 = min(G, b0 + per);
   float s = 0.f;
   if (p < P) {
-#pragma unroll 4
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) s += part[(long long)b * P + p];
   }
-  red[threadIdx.x >> 6][threadIdx.x & 63] = s;
+  red[w][lane] = s;
   __syncthreads();
-  if (threadIdx.x < 64 && p < P)
-    tmp[(long long)by * P + p] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-}
-
-__global__ __launch_bounds__(256) void dw_reduce1(int G, long long P, const float* __restrict__ part,
-                                                  float* __restrict__ tmp) {
-  dw_reduce1_body(G, P, part, tmp, blockIdx.x, blockIdx.y, gridDim.y);
-}
-
-// Stage 2: final sum, non-finite flag, loss.
-__device__ __forceinline__ void dw_reduce2_body(int parts, long long P, const float* __restrict__ tmp,
-                                                float* __restrict__ grad, int G, const float* __restrict__ part_loss,
-                                                float* __restrict__ loss_out, float norm, int32_t* flag,
-                                                float out_scale, int bx, int gx) {
-  for (long long p = bx * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gx * blockDim.x) {
-    float s = 0.f;
-    for (int k = 0; k < parts; ++k) s += tmp[(long long)k * P + p];
-    grad[p] = s * out_scale;
-    if (flag && !isfinite(s)) atomicOr(flag, 1);
+  if (w == 0 && p < P) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kDwWaves; ++k) t += red[k][lane];
+    grad[p] = t * out_scale;
+    if (flag && !isfinite(t)) atomicOr(flag, 1);
   }
   if (bx == 0 && loss_out) {
-    __shared__ float red[256];
-    float s = 0.f;
-    for (int b = threadIdx.x; b < G; b += blockDim.x) s += part_loss[b];
-    red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    float* lr = &red[0][0];
+    float l = 0.f;
+    for (int b = threadIdx.x; b < G; b += blockDim.x) l += part_loss[b];
+    lr[threadIdx.x] = l;
+    __syncthreads();
+    for (int k = kDwWaves * 32; k > 0; k >>= 1) {
+      if ((int)threadIdx.x < k) lr[threadIdx.x] += lr[threadIdx.x + k];
       __syncthreads();
     }
-    if (threadIdx.x == 0) *loss_out = red[0] * norm;
+    if (threadIdx.x == 0) *loss_out = lr[0] * norm;
   }
 }
 
-__global__ void dw_reduce2(int parts, long long P, const float* __restrict__ tmp, float* __restrict__ grad,
-                           int G, const float* __restrict__ part_loss, float* __restrict__ loss_out, float norm,
-                           int32_t* flag, float out_scale) {
-  dw_reduce2_body(parts, P, tmp, grad, G, part_loss, loss_out, norm, flag, out_scale, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(64 * kDwWaves) void dw_reduce(int G, long long P, const float* __restrict__ part,
+                                                 float* __restrict__ grad, const float* __restrict__ part_loss,
+                                                 float* __restrict__ loss_out, float norm, int32_t* flag,
+                                                 float out_scale) {
+  dw_reduce_body(G, P, part, grad, part_loss, loss_out, norm, flag, out_scale, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ optimiser
@@ -1107,7 +1109,7 @@ struct TrainEntry {
   BinArgs bin;        // q is unused: the launch's queries + q0
   AdamArgs adam;      // pointers; step-dependent scalars come with each launch
   long long q0, P;
-  int nbins, ntiles, region_max, fused_grid, dw1_x;
+  int nbins, ntiles, region_max, fused_grid;
   float loss_norm;
   int* offsets;
   int* total;
@@ -1120,7 +1122,6 @@ struct TrainEntry {
   const float* part_lat;
   float* lat_grad;
   const float* part_dw;
-  float* tmp;
   float* grad;
   const float* part_loss;
   float* loss_out;
@@ -1151,7 +1152,7 @@ __device__ inline const TrainEntry* group_member(const char* table, const TrainS
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void bin_grouped(const char* __restrict__ table, TrainSegs sg,
+__global__ __launch_bounds__(kBinThreads) void bin_grouped(const char* __restrict__ table, TrainSegs sg,
                                                    const ntc_query* __restrict__ q) {
   int bi, nb;
   const TrainEntry* e = group_member(table, sg, bi, nb);
@@ -1178,18 +1179,12 @@ __global__ __launch_bounds__(256) void lat_partial_grouped(const char* __restric
   if (e) lat_partial_body(e->m, e->tg, e->ibase, e->part_lat, e->region_max, e->lat_grad, 1.f, bi, 0, 1);
 }
 
-__global__ __launch_bounds__(256) void dw_reduce1_grouped(const char* __restrict__ table, TrainSegs sg) {
-  int bi, nb;
-  const TrainEntry* e = group_member(table, sg, bi, nb);
-  if (e) dw_reduce1_body(e->fused_grid, e->P, e->part_dw, e->tmp, bi % e->dw1_x, bi / e->dw1_x, kDwYBlocks);
-}
-
-__global__ __launch_bounds__(256) void dw_reduce2_grouped(const char* __restrict__ table, TrainSegs sg) {
+__global__ __launch_bounds__(64 * kDwWaves) void dw_reduce_grouped(const char* __restrict__ table, TrainSegs sg) {
   int bi, nb;
   const TrainEntry* e = group_member(table, sg, bi, nb);
   if (e)
-    dw_reduce2_body(kDwYBlocks, e->P, e->tmp, e->grad, e->fused_grid, e->part_loss, e->loss_out, e->loss_norm,
-                    e->overflow, 1.f, bi, nb);
+    dw_reduce_body(e->fused_grid, e->P, e->part_dw, e->grad, e->part_loss, e->loss_out, e->loss_norm, e->overflow,
+                   1.f, bi);
 }
 
 // Step-dependent Adam scalars shared by the group (from the hyper-parameters).
@@ -1422,7 +1417,6 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTu
   p.off_part_lat = take((size_t)p.max_items * rmax * 4);
   p.off_part_dw = take((size_t)p.grid * P * 4);
   p.off_part_loss = take((size_t)p.grid * 4);
-  p.off_tmp = take((size_t)kDwYBlocks * P * 4);
   p.off_grad = take(P * 4);
   p.total = o;
   p.supported_bins = nb <= kMaxBins;
@@ -1458,13 +1452,13 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     b.base = (const int*)(ws + p.off_base);
     b.list = (int4*)(ws + p.off_list);
     const size_t lds = (size_t)p.nbins * 4;
-    hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
+    hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(kBinThreads), lds, s, dm, p.tg, b);
     hipLaunchKernelGGL(bin_scan1_kernel, dim3((p.nbins + 3) / 4), dim3(256), 0, s, p.nbins, p.nbb,
                        (const int*)(ws + p.off_counts), (int*)(ws + p.off_offsets), (int*)(ws + p.off_total));
     hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.tg, (const int*)(ws + p.off_total),
                        (int*)(ws + p.off_base), (int*)(ws + p.off_tstart), (int*)(ws + p.off_ttotal),
                        (int*)(ws + p.off_ibase), (int*)(ws + p.off_itile), (int*)(ws + p.off_misc));
-    hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(256), lds, s, dm, p.tg, b);
+    hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(kBinThreads), lds, s, dm, p.tg, b);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1484,11 +1478,8 @@ hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* 
                                float out_scale) {
   char* ws = (char*)workspace;
   const long long P = m.mlp_params;
-  hipLaunchKernelGGL(dw_reduce1, dim3((unsigned)((P + 63) / 64), kDwYBlocks), dim3(256), 0, s, p.grid, P,
-                     (const float*)(ws + p.off_part_dw), (float*)(ws + p.off_tmp));
-  const int blocks = (int)std::max<long long>(1, std::min<long long>((P + 255) / 256, 1024));
-  hipLaunchKernelGGL(dw_reduce2, dim3(blocks), dim3(256), 0, s, kDwYBlocks, P,
-                     (const float*)(ws + p.off_tmp), grad_out ? grad_out : (float*)(ws + p.off_grad), p.grid,
+  hipLaunchKernelGGL(dw_reduce, dim3((unsigned)((P + 63) / 64)), dim3(64 * kDwWaves), 0, s, p.grid, P,
+                     (const float*)(ws + p.off_part_dw), grad_out ? grad_out : (float*)(ws + p.off_grad),
                      (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag, out_scale);
   return hipGetLastError();
 }
@@ -1618,7 +1609,6 @@ void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets
     e.ntiles = p.ntiles;
     e.region_max = p.region_max;
     e.fused_grid = p.grid;
-    e.dw1_x = (int)((m.mlp_params + 63) / 64);
     e.loss_norm = 1.0f / (float)((double)g[i].n * m.channels);
     e.offsets = (int*)(ws + p.off_offsets);
     e.total = (int*)(ws + p.off_total);
@@ -1631,7 +1621,6 @@ void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets
     e.part_lat = (const float*)(ws + p.off_part_lat);
     e.lat_grad = fused[i].lat_grad;
     e.part_dw = (const float*)(ws + p.off_part_dw);
-    e.tmp = (float*)(ws + p.off_tmp);
     e.grad = (float*)(ws + p.off_grad);
     e.part_loss = (const float*)(ws + p.off_part_loss);
     e.loss_out = adam[i].loss_out;
@@ -1676,13 +1665,13 @@ hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_
   if (scatter) {
     const size_t lds = (size_t)max_bins * 4;
     run([&](int i) { return g[i].p.nbb; },
-        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<false>, dim3(n), dim3(256), lds, s, tab, sg, q); });
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<false>, dim3(n), dim3(kBinThreads), lds, s, tab, sg, q); });
     run([&](int i) { return (g[i].p.nbins + 3) / 4; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_scan1_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
     run([&](int) { return 1; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_scan2_grouped, dim3(n), dim3(1024), 0, s, tab, sg); });
     run([&](int i) { return g[i].p.nbb; },
-        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<true>, dim3(n), dim3(256), lds, s, tab, sg, q); });
+        [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<true>, dim3(n), dim3(kBinThreads), lds, s, tab, sg, q); });
   }
   for (int i = 0; i < nmat && e == hipSuccess; ++i) {
     TrainLaunch l = fused[i];
@@ -1693,10 +1682,8 @@ hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_
   if (scatter)
     run([&](int i) { return g[i].p.ntiles; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(lat_partial_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
-  run([&](int i) { return (int)((mats[i].mlp_params + 63) / 64) * kDwYBlocks; },
-      [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(dw_reduce1_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
-  run([&](int i) { return (int)std::max<long long>(1, std::min<long long>((mats[i].mlp_params + 255) / 256, 1024)); },
-      [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(dw_reduce2_grouped, dim3(n), dim3(256), 0, s, tab, sg); });
+  run([&](int i) { return (int)((mats[i].mlp_params + 63) / 64); },
+      [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(dw_reduce_grouped, dim3(n), dim3(64 * kDwWaves), 0, s, tab, sg); });
   AdamHot h;
   h.lr_lat = hot.lr_lat;
   h.lr_mlp = hot.lr_mlp;

@@ -179,10 +179,15 @@ struct TrainCfg {
   static constexpr int LDS = OFF_REG + region(TMAX) * RB;
 };
 
+// One block's share of a material's work items: items [item0, item1) with stride
+// `istride`, its weight-gradient partial written to row `row` of a.part_dw (and its
+// loss to a.part_loss[row]).  q: the material's queries (samples in query order when
+// !binned); scale_slot: the loss-scale slot when the step index is not on the device;
+// zero_flag: this block clears the overflow flag.  item1 < 0: all of a.nitems.
 template <typename T, int C0, int C1, int C, int HD, int ACT>
-__global__ __launch_bounds__((TrainCfg<T, C0, C1, C, HD>::NTHR),
-                             (TrainCfg<T, C0, C1, C, HD>::NW * TrainCfg<T, C0, C1, C, HD>::BPC / 4)) void
-train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
+__device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, const TrainArgs& a,
+                                           const ntc_query* __restrict__ qs, int binned, int scale_slot, int item0,
+                                           int item1, int istride, int row, bool zero_flag) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
   constexpr PackGeom pg = Cfg::pg;
@@ -197,8 +202,6 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
   using RegT = typename Cfg::RegT;
   RegT* reg = reinterpret_cast<RegT*>(smem + Cfg::OFF_REG);
-  if (a.table_hash && *a.table_hash != a.hash) return;  // grouped step against another table
-
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.wpack)[i];
@@ -219,10 +222,10 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
     tab[8 + tid] = m.g1_off[tid];
   }
   if (tid < 16) tab[16 + tid] = m.mip_off[tid];
-  if (blockIdx.x == 0 && tid == 0) *a.overflow_flag = 0;
+  if (zero_flag && tid == 0) *a.overflow_flag = 0;
   __syncthreads();
 
-  const int slot = a.step_dev ? (*a.step_dev & 1) : a.scale_slot;
+  const int slot = a.step_dev ? (*a.step_dev & 1) : scale_slot;
   const float scale = a.loss_scale ? a.loss_scale[slot] : 1.f;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
 
@@ -235,14 +238,14 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   float db1 = 0.f, db2 = 0.f, db3 = 0.f, loss = 0.f;
 
   const int chunk_n = a.tg.chunk;
-  const int nitems = a.binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int nitems = item1 >= 0 ? item1 : binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
+  for (int item = item0; item < nitems; item += istride) {
     // ---------------- work item -> (tile, sample range)
     int j = 0, tx = 0, ty = 0, T_ = 2, cnt;
     long long start;
     bool single = true;
     bool sorted = false;
-    if (a.binned) {
+    if (binned) {
       const int tile = a.item_tile[item];
       const int chunk = item - a.item_base[tile];
       single = (a.item_base[tile + 1] - a.item_base[tile]) == 1;
@@ -262,7 +265,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
     const int ts = __builtin_ctz(T_), t1s = ts - 1;  // tile sides are powers of two >= 2
     const int R0 = T_ * T_ * C0;
     const int RG = R0 + T1 * T1 * C1;
-    if (a.binned)
+    if (binned)
       for (int k = tid; k < RG; k += NTHR) reg[k] = (RegT)0;
     __syncthreads();
 
@@ -274,7 +277,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
       lod = 0;
       s = 0;
       if (pos < cnt) {
-        if (a.binned) {
+        if (binned) {
           const int4 e = a.list[start + pos];
           u = __int_as_float(e.x);
           v = __int_as_float(e.y);
@@ -282,9 +285,9 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
           s = e.w;
         } else {
           s = start + pos;
-          u = a.q[s].u;
-          v = a.q[s].v;
-          lod = a.q[s].lod;
+          u = qs[s].u;
+          v = qs[s].v;
+          lod = qs[s].lod;
         }
       }
     };
@@ -299,7 +302,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
       const long long s = ns;
       if (t0 + NCOL < cnt) load_entry(t0 + NCOL, nu, nv, nlod, ns);
       const Footprint f = locate(m, u, v, lod, g);
-      const bool primary = valid && (!a.binned || ((f.ax >> ts) == tx && (f.ay >> ts) == ty));
+      const bool primary = valid && (!binned || ((f.ax >> ts) == tx && (f.ay >> ts) == ty));
       const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
       const long long g1base = tab[8 + f.j];
 
@@ -408,7 +411,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
 #pragma unroll
       for (int t = 0; t < SH; ++t) dz1T[t] = (T)dz1[t];
 
-      if (a.binned) {  // block-uniform: the matrix-core ops run for every lane
+      if (binned) {  // block-uniform: the matrix-core ops run for every lane
         float dx[4 * ML];
 #pragma unroll
         for (int mo = 0; mo < ML; ++mo) {
@@ -555,7 +558,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
     }
 
     // ---------------- the tile's latent gradient: dense plain stores (or a partial)
-    if (a.binned) {
+    if (binned) {
       if (single) {
         const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
         for (int k = tid; k < RG; k += NTHR) {
@@ -578,7 +581,7 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   }
 
   // ---------------- per-block partial weight gradient (canonical layout) and loss
-  float* part = a.part_dw + (long long)blockIdx.x * Pn;
+  float* part = a.part_dw + (long long)row * Pn;
   if (wave < MT) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -633,8 +636,17 @@ train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   if (tid == 0) {
     float l = 0.f;
     for (int w = 0; w < NW; ++w) l += red[w];
-    a.part_loss[blockIdx.x] = l;
+    a.part_loss[row] = l;
   }
+}
+
+template <typename T, int C0, int C1, int C, int HD, int ACT>
+__global__ __launch_bounds__((TrainCfg<T, C0, C1, C, HD>::NTHR),
+                             (TrainCfg<T, C0, C1, C, HD>::NW * TrainCfg<T, C0, C1, C, HD>::BPC / 4)) void
+train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
+  if (a.table_hash && *a.table_hash != a.hash) return;  // grouped step against another table
+  fused_body<T, C0, C1, C, HD, ACT>(m, pe, a, a.q, a.binned, a.scale_slot, blockIdx.x, -1, gridDim.x, blockIdx.x,
+                                    blockIdx.x == 0);
 }
 
 // ------------------------------------------------------------------ binning (counting sort)
@@ -1244,9 +1256,8 @@ static void shape_info(int act, int& tmax, int& per_cu) {
   per_cu = act ? fused_per_cu<T, C0, C1, C, HD, 1>() : fused_per_cu<T, C0, C1, C, HD, 0>();
 }
 
-template <typename T, int C0, int C1, int C, int HD, int ACT>
-static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const TrainLaunch& l, hipStream_t s) {
-  using Cfg = TrainCfg<T, C0, C1, C, HD>;
+// Kernel arguments of a material's fused pass from its plan and buffers.
+static TrainArgs make_train_args(const ntc_material& mm, const TrainPlan& p, const TrainLaunch& l) {
   char* ws = (char*)l.workspace;
   TrainArgs a;
   a.lat_fwd = l.lat_fwd;
@@ -1271,13 +1282,20 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   a.overflow_flag = l.overflow_flag;
   a.binned = l.scatter_latents ? 1 : 0;
   a.region_max = p.region_max;
-  a.inv_nc = (float)(1.0 / ((double)l.n * C));
+  a.inv_nc = (float)(1.0 / ((double)l.n * mm.channels));
   a.dout = l.dout;
   a.dout_scale = l.dout_scale;
   a.out_scale = l.out_scale;
   a.table_hash = l.table_hash;
   a.hash = l.hash;
   a.tg = p.tg;
+  return a;
+}
+
+template <typename T, int C0, int C1, int C, int HD, int ACT>
+static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const TrainLaunch& l, hipStream_t s) {
+  using Cfg = TrainCfg<T, C0, C1, C, HD>;
+  const TrainArgs a = make_train_args(mm, p, l);
   const int slot = timing_before(TK_TRAIN_FUSED, s);
   hipLaunchKernelGGL((train_fused_kernel<T, C0, C1, C, HD, ACT>), dim3(p.grid), dim3(Cfg::NTHR), Cfg::LDS, s, dev_mat(mm),
                      pe_table(mm), a);

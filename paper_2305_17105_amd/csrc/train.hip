@@ -979,6 +979,30 @@ __device__ inline int latent_bits(const DevMat& m, long long i) {
   return bits;
 }
 
+// The same lookup with the grid starts held in registers (read once per thread): a
+// loop over latents need not reload the descriptor, which may live in global memory.
+struct LatentBits {
+  long long g1[kMaxLevels], g0[kMaxLevels];
+  int b0, b1, J;
+  __device__ explicit LatentBits(const DevMat& m) : b0(m.B0), b1(m.B1), J(m.J) {
+#pragma unroll
+    for (int j = 0; j < kMaxLevels; ++j) {
+      g0[j] = m.g0_off[j];
+      g1[j] = m.g1_off[j];
+    }
+  }
+  __device__ int operator()(long long i) const {
+    if (b0 == b1) return b0;
+    int bits = b0;
+#pragma unroll
+    for (int j = 0; j < kMaxLevels; ++j) {
+      if (j < J && i >= g0[j]) bits = b0;
+      if (j < J && i >= g1[j]) bits = b1;
+    }
+    return bits;
+  }
+};
+
 struct AdamArgs {
   AdamLaunch a;
   PackGeom pg;
@@ -1039,9 +1063,11 @@ __device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args,
     return;
   }
   if (a.freeze) return;
+  const LatentBits lbits(m);
+  const long long L = m.latent_count;
   // one latent: update in place (unless the step is skipped) and its forward value
   auto one = [&](long long i, float& p, float gr, float& mm, float& vv) -> float {
-    const int bits = latent_bits(m, i);
+    const int bits = lbits(i);
     if (!ovf) {
       gr *= inv_s;
       mm = b1 * mm + (1.f - b1) * gr;
@@ -1055,7 +1081,7 @@ __device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args,
   // four consecutive latents per thread and iteration (16-byte accesses), then the tail
   const long long base = ((long long)bx - args.mlp_blocks) * 256 + threadIdx.x;
   const long long stride = ((long long)gx - args.mlp_blocks) * 256;
-  const long long nv = m.latent_count / 4;
+  const long long nv = L / 4;
   for (long long v4 = base; v4 < nv; v4 += stride) {
     const long long i = 4 * v4;
     f32x4 p = reinterpret_cast<const f32x4*>(a.latents)[v4];
@@ -1078,7 +1104,7 @@ __device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args,
     }
     reinterpret_cast<f32x4*>(a.latents_fwd)[v4] = fw;
   }
-  for (long long i = 4 * nv + base; i < m.latent_count; i += stride) {
+  for (long long i = 4 * nv + base; i < L; i += stride) {
     float p = a.latents[i], mm = a.lat_m[i], vv = a.lat_v[i];
     const float fw = one(i, p, a.lat_grad[i], mm, vv);
     if (!ovf) {

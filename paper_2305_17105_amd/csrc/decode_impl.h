@@ -56,27 +56,34 @@ __device__ inline void fill_level_bytes(const DevMat& m, LevelBytes* lb, int tid
 
 // NW dwords of the code window of `cell` (NB bits per cell) in a grid at byte `base`,
 // with 32-bit byte offsets from the packed-latent pointer (loads through a scalar base).
+// The packed latents are global memory: the explicit address space keeps the loads
+// global (not flat) even when the pointer came from a table in memory.
+typedef const __attribute__((address_space(1))) char gbyte;
+template <typename W>
+__device__ inline W gload(gbyte* p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) W*>(p);
+}
 template <int NW, int NB>
-__device__ inline void load_window(const char* __restrict__ packed, uint32_t base, uint32_t cell, uint32_t last,
+__device__ inline void load_window(gbyte* __restrict__ packed, uint32_t base, uint32_t cell, uint32_t last,
                                    uint32_t (&out)[NW]) {
   if constexpr (NB % 64 == 0) {  // whole 8-byte units (grid bases are 16-byte aligned)
     const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
 #pragma unroll
     for (int k = 0; k < NW / 2; ++k) {
-      const uint2 w = *reinterpret_cast<const uint2*>(packed + (b0 + 8u * k));
-      out[2 * k] = w.x;
-      out[2 * k + 1] = w.y;
+      const unsigned long long w = gload<unsigned long long>(packed + (b0 + 8u * k));
+      out[2 * k] = (uint32_t)w;
+      out[2 * k + 1] = (uint32_t)(w >> 32);
     }
   } else if constexpr (NB % 32 == 0) {
     const uint32_t b0 = base + cell * (uint32_t)(NB / 8);
 #pragma unroll
-    for (int k = 0; k < NW; ++k) out[k] = *reinterpret_cast<const uint32_t*>(packed + (b0 + 4u * k));
+    for (int k = 0; k < NW; ++k) out[k] = gload<uint32_t>(packed + (b0 + 4u * k));
   } else {
     const uint64_t bit = (uint64_t)cell * NB;
     const uint32_t b0 = base + (uint32_t)(bit >> 5) * 4u, s = (uint32_t)bit & 31u;
     uint32_t w[NW + 1];
 #pragma unroll
-    for (int k = 0; k <= NW; ++k) w[k] = *reinterpret_cast<const uint32_t*>(packed + min(b0 + 4u * k, last));
+    for (int k = 0; k <= NW; ++k) w[k] = gload<uint32_t>(packed + min(b0 + 4u * k, last));
 #pragma unroll
     for (int k = 0; k < NW; ++k) out[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
   }
@@ -102,7 +109,7 @@ struct CodeWindow {
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = f.g1_w[k];
     const LevelBytes b = lb[f.j];
-    const char* pk = reinterpret_cast<const char*>(packed);
+    gbyte* pk = (gbyte*)reinterpret_cast<const char*>(packed);
     load_window<NW0, NB0>(pk, b.g0, (uint32_t)f.g0_cell, b.g0_last, g0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) load_window<NW1, NB1>(pk, b.g1, (uint32_t)f.g1_cell[k], b.g1_last, g1[k]);
@@ -462,9 +469,10 @@ __global__ __launch_bounds__(256) void decode_grouped_kernel(const char* __restr
   const int s = group_segment(ga);
   const GroupSeg sg = ga.seg[s];
   const GroupEntry& e = tab[sg.mat];
-  const float* b1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(e.wpack) + WB);
+  const T* wp = as_global(reinterpret_cast<const T*>(e.wpack));
+  const float* b1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wp) + WB);
   const int nb = (s + 1 < ga.count ? ga.seg[s + 1].block0 : ga.blocks) - sg.block0;
-  decode_body<T, C0, C1, C, HD, B0, B1, true, ACT>(e.m, pe, e.packed, reinterpret_cast<const T*>(e.wpack), b1,
+  decode_body<T, C0, C1, C, HD, B0, B1, true, ACT>(e.m, pe, as_global(e.packed), wp, b1,
                                                    b1 + HD, b1 + 2 * HD, q + sg.q0, sg.n, TexelRect{},
                                                    out + sg.o0 * (out_f16 ? 2 : 4), out_f16,
                                                    (int)blockIdx.x - sg.block0, nb);
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(256) void decode_mixed_kernel(const char* __restric
     }
     const GroupEntry& e = tab[mt];
     Raw R;
-    R.fetch(e.m, lb + mt * kMaxLevels, reinterpret_cast<const uint32_t*>(e.packed), u, v, lod, g);
+    R.fetch(e.m, lb + mt * kMaxLevels, as_global(reinterpret_cast<const uint32_t*>(e.packed)), u, v, lod, g);
     T xs[S1];
     paired_inputs(R, g, xs);
     {
@@ -538,7 +546,7 @@ __global__ __launch_bounds__(256) void decode_mixed_kernel(const char* __restric
     unsigned long long pending = __ballot(valid);
     while (pending) {
       const int cur = __builtin_amdgcn_readfirstlane(__shfl(mt, (int)__builtin_ctzll(pending)));
-      const T* __restrict__ w = reinterpret_cast<const T*>(tab[cur].wpack);
+      const T* __restrict__ w = as_global(reinterpret_cast<const T*>(tab[cur].wpack));
       const float* __restrict__ bias = reinterpret_cast<const float*>(reinterpret_cast<const char*>(w) + WB);
       f32x4 acc[MT];
 #pragma unroll
@@ -744,10 +752,11 @@ __global__ __launch_bounds__(256) void decode_fp8_grouped_kernel(const char* __r
   const int s = group_segment(ga);
   const GroupSeg sg = ga.seg[s];
   const GroupEntry& e = tab[sg.mat];
-  const float* scales = reinterpret_cast<const float*>(reinterpret_cast<const char*>(e.wpack) + WB);
+  const uint8_t* wp = as_global(reinterpret_cast<const uint8_t*>(e.wpack));
+  const float* scales = reinterpret_cast<const float*>(wp + WB);
   const int nb = (s + 1 < ga.count ? ga.seg[s + 1].block0 : ga.blocks) - sg.block0;
-  decode_fp8_body<C0, C1, C, HD, B0, B1, ACT>(e.m, pe, reinterpret_cast<const uint32_t*>(e.packed),
-                                              reinterpret_cast<const uint8_t*>(e.wpack), scales, scales + 4,
+  decode_fp8_body<C0, C1, C, HD, B0, B1, ACT>(e.m, pe, as_global(reinterpret_cast<const uint32_t*>(e.packed)), wp,
+                                              scales, scales + 4,
                                               q + sg.q0, sg.n, TexelRect{}, out + sg.o0 * (out_f16 ? 2 : 4), out_f16,
                                               (int)blockIdx.x - sg.block0, nb);
 }

@@ -37,6 +37,14 @@ struct DevMat {
   long long latent_count;
 };
 
+// A pointer read from device memory (a table entry) as a global-memory pointer, so the
+// compiler emits global rather than flat accesses through it (flat loads also count
+// against the LDS counter and serialise with LDS traffic).
+template <typename T>
+__device__ inline T* as_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)p;
+}
+
 // One material of a grouped launch: its geometry, bit-packed latents and decode pack.
 struct GroupEntry {
   DevMat m;

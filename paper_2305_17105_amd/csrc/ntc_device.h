@@ -496,6 +496,15 @@ __device__ inline float row_sum16(float v) {
   return v;
 }
 
+// Integer sum over the 16 lanes of a row (lane group), by rotations within the row (DPP).
+__device__ inline int row_sum16i(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);
+  return v;
+}
+
 // The three positional-encoding values of lane group g (slots 3g..3g+2 of the 12).
 __device__ inline void pe_values(const float* pe_lds, int ix, int iy, int g, float out[3]) {
   const int mpos = (g >> 1) ? (iy & 7) : (ix & 7);

@@ -33,7 +33,7 @@
 
 namespace ntc {
 
-constexpr int kChunkDefault = 256;  // samples per work item unless tuned (the tuner picked 256 on every shape)
+constexpr int kChunkDefault = 256;  // samples per work item unless tuned (tiles of at most 16 x 16)
 constexpr int kBinBlockSamples = 1024;
 constexpr int kBinThreads = 1024;  // threads of a binning block (one sample each)
 constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
@@ -169,9 +169,13 @@ struct TrainCfg {
   static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
-  // owned-latent accumulators in FP64 when a 16 x 16 tile of them fits (LDS FP32
-  // atomic adds run ~8x slower than FP64 ones on this GPU), else FP32
-  static constexpr bool REG64 = OFF_REG + region(16) * 8 <= kLdsCap;
+  // Owned-latent accumulators.  FP16 kernels (FIXED): 32-bit fixed point (integer LDS
+  // adds run 3x faster than FP64 ones and 25x faster than FP32 ones on this GPU, the sums
+  // do not depend on the order of the adds, and at 4 bytes a latent a 32 x 32 tile fits);
+  // a work item with a contribution beyond the fixed-point range is summed again in FP32.
+  // FP32 kernels: FP64 accumulators when a 16 x 16 tile of them fits, else FP32.
+  static constexpr bool FIXED = sizeof(T) == 2;
+  static constexpr bool REG64 = !FIXED && OFF_REG + region(16) * 8 <= kLdsCap;
   using RegT = typename std::conditional<REG64, double, float>::type;
   static constexpr int RB = REG64 ? 8 : 4;
   // largest tile side whose owned-latent gradient fits next to the rest
@@ -201,7 +205,11 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
   using RegT = typename Cfg::RegT;
+  constexpr bool FIXED = Cfg::FIXED;
   RegT* reg = reinterpret_cast<RegT*>(smem + Cfg::OFF_REG);
+  int* ireg = reinterpret_cast<int*>(smem + Cfg::OFF_REG);      // FIXED: fixed-point sums
+  float* freg = reinterpret_cast<float*>(smem + Cfg::OFF_REG);  // FIXED: FP32 sums of a summed-again item
+  bool lost = false;  // FIXED: a contribution of this item left the fixed-point range
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.wpack)[i];
@@ -238,6 +246,41 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   float db1 = 0.f, db2 = 0.f, db3 = 0.f, loss = 0.f;
 
   const int chunk_n = a.tg.chunk;
+  // FIXED: the quantum of the fixed-point sums is 2^-16 of the natural unit U of the
+  // output delta (2 x loss scale / (samples x channels) for the loss; 1 for a caller's
+  // delta, which comes scaled to O(1)), rounded to a power of two, so the range covers the
+  // same multiples of U whatever the batch and the loss scale: 16 U and more at 512
+  // samples per work item, a rounding error of at most 2^-17 U per contribution.  A
+  // latent takes at most 4 adds per sample of a work item (a footprint's taps may
+  // coincide at the border), so adds of at most qlim units cannot overflow.
+  float fixq = 0x1p24f;
+  {
+    const float U = a.dout ? 1.f : 2.f * a.inv_nc * scale;
+    int ex = 0;
+    if (U > 0.f && U < 0x1p100f) frexpf(U, &ex);
+    fixq = ldexpf(1.f, 16 - max(-80, min(80, ex)));
+  }
+  const float fixinv = 1.f / fixq;  // exact: a power of two
+  const float qlim = fminf((float)(0x7fffffff / (4 * chunk_n)), 0x1p22f);
+  const float xlim = qlim * fixinv;  // the largest contribution kept in fixed point (exact)
+  // FIXED, first pass: a contribution x clamped to the range and rounded to the nearest
+  // quantum (adding 1.5 * 2^23 leaves the integer in the low mantissa bits); a clamped or
+  // non-finite x marks the item for the FP32 pass.  Every contribution is rounded on its
+  // own, so the integer sums do not depend on how samples are grouped or ordered.
+  auto quant = [&](float x) -> int {
+    const float xc = __builtin_amdgcn_fmed3f(x, -xlim, xlim);
+    lost |= x != xc;
+    return __float_as_int(fmaf(xc, fixq, 0x1.8p23f)) - 0x4B400000;
+  };
+  // One contribution x to owned latent k of the region.
+  auto acc_lat = [&](int k, float x, bool refine) {
+    if constexpr (FIXED) {
+      if (refine) atomicAdd(freg + k, x);
+      else atomicAdd(ireg + k, quant(x));
+    } else {
+      atomicAdd(reg + k, (RegT)x);
+    }
+  };
   const int nitems = item1 >= 0 ? item1 : binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
   for (int item = item0; item < nitems; item += istride) {
     // ---------------- work item -> (tile, sample range)
@@ -265,10 +308,6 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     const int ts = __builtin_ctz(T_), t1s = ts - 1;  // tile sides are powers of two >= 2
     const int R0 = T_ * T_ * C0;
     const int RG = R0 + T1 * T1 * C1;
-    if (binned)
-      for (int k = tid; k < RG; k += NTHR) reg[k] = (RegT)0;
-    __syncthreads();
-
     // the list entry (query + sample index) of one NCOL-sample step; the next step's
     // entry is loaded before this step's gathers, so it arrives with them
     auto load_entry = [&](int t0, float& u, float& v, int& lod, long long& s) {
@@ -291,6 +330,20 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
         }
       }
     };
+    // FIXED: pass 1 (refine) sums the item's latent gradients again in FP32 when a
+    // contribution left the fixed-point range in pass 0; it skips loss and weights
+    bool refined = false;
+    for (int pass = 0; pass < 2; ++pass) {
+    const bool refine = pass == 1;
+    refined = refine;
+    if (binned) {
+      if constexpr (FIXED) {
+        for (int k = tid; k < RG; k += NTHR) ireg[k] = 0;
+      } else {
+        for (int k = tid; k < RG; k += NTHR) reg[k] = (RegT)0;
+      }
+    }
+    __syncthreads();
     float nu, nv;
     int nlod;
     long long ns;
@@ -379,7 +432,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
               d = a.dout[s * C + c] * a.dout_scale;
             } else {
               const float e = y[i] - a.targets[tb + c];
-              if (primary) loss += e * e;
+              if (primary && !refine) loss += e * e;
               d = 2.f * e * a.inv_nc * scale;
             }
           }
@@ -426,30 +479,40 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
         const int rr = lane & 15;
         const bool own0 = valid && (f.g0x >> ts) == tx && (f.g0y >> ts) == ty;
         const int key0 = own0 ? ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) : -1;
-        RegT* dst0 = reg + (key0 < 0 ? 0 : key0) * C0;
+        const int dst0 = (key0 < 0 ? 0 : key0) * C0;
         if (sorted) {
           const int rk = __shfl(key0, lane & ~15);
           const unsigned long long bal = __ballot(key0 == rk || !valid);
           const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
 #pragma unroll
           for (int t = 0; t < C0; ++t) {
+            if (FIXED && !refine) {
+              const int qv = own0 ? quant(dx[t]) : 0;
+              const int sq = row_sum16i(qv);
+              if (uni) {
+                if (rr == 0 && rk >= 0) atomicAdd(ireg + dst0 + t, sq);
+              } else if (own0) {
+                atomicAdd(ireg + dst0 + t, qv);
+              }
+              continue;
+            }
             const float sv = row_sum16(own0 ? dx[t] : 0.f);
             if (uni) {
-              if (rr == 0 && rk >= 0) atomicAdd(dst0 + t, (RegT)sv);
+              if (rr == 0 && rk >= 0) acc_lat(dst0 + t, sv, refine);
             } else if (own0) {
-              atomicAdd(dst0 + t, (RegT)dx[t]);
+              acc_lat(dst0 + t, dx[t], refine);
             }
           }
         } else if (own0) {
 #pragma unroll
-          for (int t = 0; t < C0; ++t) atomicAdd(dst0 + t, (RegT)dx[t]);
+          for (int t = 0; t < C0; ++t) acc_lat(dst0 + t, dx[t], refine);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
           const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
           const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
-          RegT* dst1 = reg + R0 + (key1 < 0 ? 0 : key1) * C1;
+          const int dst1 = R0 + (key1 < 0 ? 0 : key1) * C1;
           if (sorted) {
             const int rk = __shfl(key1, lane & ~15);
             const unsigned long long bal = __ballot(key1 == rk || !valid);
@@ -458,12 +521,24 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
             for (int i = 0; i < IS::n1max; ++i) {
               const int ch = g + 4 * i;
               const float v1 = own1 ? f.g1_w[k] * dx[C0 + i] : 0.f;
+              if (FIXED && !refine) {
+                const int qv = own1 ? quant(v1) : 0;
+                const int sq = row_sum16i(qv);
+                if (ch < C1) {
+                  if (uni) {
+                    if (rr == 0 && rk >= 0) atomicAdd(ireg + dst1 + ch, sq);
+                  } else if (own1) {
+                    atomicAdd(ireg + dst1 + ch, qv);
+                  }
+                }
+                continue;
+              }
               const float sv = row_sum16(v1);
               if (ch < C1) {
                 if (uni) {
-                  if (rr == 0 && rk >= 0) atomicAdd(dst1 + ch, (RegT)sv);
+                  if (rr == 0 && rk >= 0) acc_lat(dst1 + ch, sv, refine);
                 } else if (own1) {
-                  atomicAdd(dst1 + ch, (RegT)v1);
+                  acc_lat(dst1 + ch, v1, refine);
                 }
               }
             }
@@ -471,12 +546,13 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
 #pragma unroll
             for (int i = 0; i < IS::n1max; ++i) {
               const int ch = g + 4 * i;
-              if (ch < C1) atomicAdd(dst1 + ch, (RegT)(f.g1_w[k] * dx[C0 + i]));
+              if (ch < C1) acc_lat(dst1 + ch, f.g1_w[k] * dx[C0 + i], refine);
             }
           }
         }
       }
 
+      if (refine) continue;  // block-uniform
       // ---------------- weight gradients through LDS (texels become the K axis);
       // only a sample's primary copy contributes.  Column wave*16 + r holds texel r of
       // wave `wave`.  Bias gradients are row sums of the deltas: thread (row = tid / PARTS,
@@ -557,24 +633,37 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       }
     }
 
+    if constexpr (FIXED) {
+      if (binned && !refine && __syncthreads_or(lost)) {
+        lost = false;
+        continue;
+      }
+      // the refine pass has no staging barriers: its adds must land before the write-out
+      if (refine) __syncthreads();
+    }
+    break;
+    }
+
     // ---------------- the tile's latent gradient: dense plain stores (or a partial)
     if (binned) {
-      if (single) {
-        const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
-        for (int k = tid; k < RG; k += NTHR) {
-          long long gi;
-          if (k < R0) {
-            const int c = k % C0, cell = k / C0, cx = cell % T_, cy = cell / T_;
-            gi = tab[j] + ((long long)(ty * T_ + cy) * w0 + tx * T_ + cx) * C0 + c;
-          } else {
-            const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell % T1, cy = cell / T1;
-            gi = tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
-          }
-          a.lat_grad[gi] = (float)reg[k] * a.out_scale;
+      const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
+      float* dst = single ? a.lat_grad : a.part_lat + (long long)item * a.region_max;
+      const float osc = single ? a.out_scale : 1.f;
+      // where latent k of the region goes (tile sides are powers of two)
+      auto dst_index = [&](int k) -> long long {
+        if (!single) return k;
+        if (k < R0) {
+          const int c = k % C0, cell = k / C0, cx = cell & (T_ - 1), cy = cell >> ts;
+          return tab[j] + ((long long)(ty * T_ + cy) * w0 + tx * T_ + cx) * C0 + c;
         }
-      } else {
-        float* dst = a.part_lat + (long long)item * a.region_max;
-        for (int k = tid; k < RG; k += NTHR) dst[k] = (float)reg[k];
+        const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell & (T1 - 1), cy = cell >> t1s;
+        return tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
+      };
+      for (int k = tid; k < RG; k += NTHR) {
+        float v;
+        if constexpr (FIXED) v = refined ? freg[k] : (float)ireg[k] * fixinv;
+        else v = (float)reg[k];
+        dst[dst_index(k)] = v * osc;
       }
       __syncthreads();
     }
@@ -1396,7 +1485,6 @@ const TrainTune* train_tune_candidates(int* count) {
 TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTune* tune) {
   TrainPlan p{};
   const TrainTune tn = tune ? *tune : get_train_tune(m, f16);
-  const int chunk = tn.chunk > 0 ? tn.chunk : kChunkDefault;
   int tmax = 8, per_cu = 1;
 #define NTC_X(a_, b, cc, h)                                                                          \
   if (m.c0 == a_ && m.c1 == b && m.channels == cc && m.hidden == h) {                                \
@@ -1406,6 +1494,9 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTu
   NTC_TRAIN_SHAPES(NTC_X)
 #undef NTC_X
   if (tn.tile > 0) tmax = std::min(tmax, tn.tile);  // tile sides at most the kernel's capacity
+  // untuned: 512 samples per work item with 32 x 32 tiles (a level-0 tile of the 2048^2
+  // benchmark material then takes a single item), 256 with smaller tiles
+  const int chunk = tn.chunk > 0 ? tn.chunk : tmax >= 32 ? 2 * kChunkDefault : kChunkDefault;
   TileGeom& tg = p.tg;
   std::memset(&tg, 0, sizeof tg);
   tg.chunk = chunk;

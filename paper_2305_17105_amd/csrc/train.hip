@@ -145,6 +145,9 @@ struct TrainCfg {
 #ifndef NTC_TRAIN_BPC16
 #define NTC_TRAIN_BPC16 1
 #endif
+#ifndef NTC_TRAIN_TWO_PHASE
+#define NTC_TRAIN_TWO_PHASE 1
+#endif
   static constexpr int NW = sizeof(T) == 2 ? NTC_TRAIN_NW16 : 4;
   static constexpr int BPC = sizeof(T) == 2 ? NTC_TRAIN_BPC16 : 1;
   static constexpr int NTHR = 64 * NW, NCOL = 16 * NW;
@@ -178,7 +181,12 @@ struct TrainCfg {
           : OFF_BUF + buf_bytes(TR1) + region(16) * 8 <= kLdsCap;
   static constexpr bool SPLIT1 = sizeof(T) == 2 && !ONE_PHASE && OFF_BUF + buf_bytes(TR3) + region(32) * 4 > kLdsCap &&
                                  OFF_BUF + buf_bytes(TR3S) + region(32) * 4 <= kLdsCap;
-  static constexpr int TR = ONE_PHASE ? TR1 : SPLIT1 ? TR3S : TR3;
+  // two-phase staging (layers 3 and 2 together, then layer 1): FP16, where it still
+  // leaves room for 32 x 32 tiles
+  static constexpr int TR2 = cmax(3 * HD + 16, RX + HD);
+  static constexpr bool TWO_PHASE = NTC_TRAIN_TWO_PHASE && sizeof(T) == 2 && !ONE_PHASE && !SPLIT1 &&
+                                    OFF_BUF + buf_bytes(TR2) + region(32) * 4 <= kLdsCap;
+  static constexpr int TR = ONE_PHASE ? TR1 : TWO_PHASE ? TR2 : SPLIT1 ? TR3S : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
   // Owned-latent accumulators.  FP16 kernels (FIXED): 32-bit fixed point (integer LDS
   // adds run 3x faster than FP64 ones and 25x faster than FP32 ones on this GPU, the sums
@@ -605,29 +613,54 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
         if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, Cfg::RDY + brow, bq);
         __syncthreads();
       } else {
-        // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
+        if constexpr (Cfg::TWO_PHASE) {
+          // layers 3 and 2 together: H2 rows [0, HD), dY rows [HD, HD + 16), H1 rows
+          // [HD + 16, 2 HD + 16), dZ2 rows [2 HD + 16, 3 HD + 16)
+          constexpr int RH1 = HD + 16, RZ2 = 2 * HD + 16;
 #pragma unroll
-        for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? h2[t] : zero;
+          for (int t = 0; t < SH; ++t) {
+            const int h = hid_feature(g, t);
+            buf[h * RS + col] = primary ? h2[t] : zero;
+            buf[(RH1 + h) * RS + col] = primary ? h1[t] : zero;
+            buf[(RZ2 + h) * RS + col] = primary ? dT[t] : zero;
+          }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
-        __syncthreads();
-        if (wave < MT) acc3 = dw_tile<T, NCOL>(acc3, buf, 16 * wave, HD, g, r);
-        if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
-        __syncthreads();
-        // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
+          for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
+          __syncthreads();
+          if (wave < MT) acc3 = dw_tile<T, NCOL>(acc3, buf, 16 * wave, HD, g, r);
 #pragma unroll
-        for (int t = 0; t < SH; ++t) {
-          buf[hid_feature(g, t) * RS + col] = primary ? h1[t] : zero;
-          buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
+          for (int k = 0; k < Cfg::NT2; ++k) {
+            const int id = wave + NW * k;
+            if (id < MT * MT) acc2[k] = dw_tile<T, NCOL>(acc2[k], buf, RH1 + 16 * (id / MT), RZ2 + 16 * (id % MT), g, r);
+          }
+          if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
+          if (brow < HD) db2 += row_part_sum<T, NCOL>(buf, RZ2 + brow, bq);
+          __syncthreads();
+        } else {
+          // layer 3: H2 rows [0, HD), dY rows [HD, HD + 16)
+#pragma unroll
+          for (int t = 0; t < SH; ++t) buf[hid_feature(g, t) * RS + col] = primary ? h2[t] : zero;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) buf[(HD + 4 * g + i) * RS + col] = primary ? dyT[i] : zero;
+          __syncthreads();
+          if (wave < MT) acc3 = dw_tile<T, NCOL>(acc3, buf, 16 * wave, HD, g, r);
+          if (brow < 16) db3 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
+          __syncthreads();
+          // layer 2: H1 rows [0, HD), dZ2 rows [HD, 2 HD)
+#pragma unroll
+          for (int t = 0; t < SH; ++t) {
+            buf[hid_feature(g, t) * RS + col] = primary ? h1[t] : zero;
+            buf[(HD + hid_feature(g, t)) * RS + col] = primary ? dT[t] : zero;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < Cfg::NT2; ++k) {
+            const int id = wave + NW * k;
+            if (id < MT * MT) acc2[k] = dw_tile<T, NCOL>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
+          }
+          if (brow < HD) db2 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
+          __syncthreads();
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < Cfg::NT2; ++k) {
-          const int id = wave + NW * k;
-          if (id < MT * MT) acc2[k] = dw_tile<T, NCOL>(acc2[k], buf, 16 * (id / MT), HD + 16 * (id % MT), g, r);
-        }
-        if (brow < HD) db2 += row_part_sum<T, NCOL>(buf, HD + brow, bq);
-        __syncthreads();
         if constexpr (!Cfg::SPLIT1) {
           // layer 1: X slot rows 4t+g in [0, RX), dZ1 rows [RX, RX + HD)
 #pragma unroll

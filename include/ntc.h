@@ -138,7 +138,7 @@ ntc_status ntc_dequantize_latents(const ntc_material* m, const uint8_t* packed, 
  * given compute precision (NTC_F32, NTC_F16 or NTC_FP8_E4M3).  `packed` must hold
  * ntc_mlp_packed_bytes(m, precision) bytes; its content is private to the
  * library and valid only for the same material shape and precision.
- * NTC_FP8_E4M3 (the lower-precision intermediates of section 8): per layer l the
+ * NTC_FP8_E4M3 (lower-precision intermediates, section 7.3 Future Work): per layer l the
  * pack holds the e4m3 rounding (OCP E4M3, round to nearest even) of W_l / s_l with
  * s_l = max|W_l| / 448, computed on the device; biases stay FP32.  It needs G0 cells
  * of whole 32-bit words (c0 * b0 a multiple of 32), b0, b1 <= 4 and hidden 32 or 64;
@@ -212,7 +212,11 @@ ntc_status ntc_decode_filtered(const ntc_material* m, const uint8_t* packed_late
  *   mlp, mlp_m, mlp_v  mlp_params  canonical FP32 weights and Adam moments
  *   mlp_packed   ntc_train_packed_bytes(m, precision) bytes, private layout
  *   loss         1 float: mean squared error of the last step
- *   loss_scale   1 float: dynamic loss scale (used by NTC_F16; set it once, e.g. 65536)
+ *   loss_scale   2 floats (NTC_F16 only; may be NULL for NTC_F32): the dynamic loss
+ *                scale, double-buffered by step parity.  Step s reads loss_scale[s & 1]
+ *                and its update writes the scale of step s + 1 to loss_scale[(s + 1) & 1]
+ *                (so a captured step can be replayed).  Set BOTH entries to the initial
+ *                scale (e.g. 65536) before the first step, whatever its index.
  *   scale_state  2 int32: [0] consecutive good steps, [1] 1 if the last step was skipped
  * The five latent buffers must be 16-byte aligned (NTC_E_INVALID otherwise).
  */
@@ -275,6 +279,16 @@ typedef struct {
 ntc_status ntc_train_autotune(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
                               const float* targets, const ntc_hparams* hp, void* workspace, size_t ws_bytes,
                               void* stream, ntc_train_tuning* chosen);
+/* Set the tuning-table entry of the material's shape and precision by hand (for example
+ * to restore an earlier ntc_train_autotune result): (chunk, tile) must be one of the
+ * tuner's candidates (samples per work item, tile side) = (256, 8), (512, 8), (256, 16),
+ * (512, 16), (1024, 16), (512, 32) or (1024, 32) (NTC_E_INVALID otherwise); (0, 0) removes
+ * the entry, so plans take the defaults again.  A tile side larger than the kernel holds is
+ * capped to its capacity.  Host only, thread-safe.
+ * ntc_train_get_tuning reports the (chunk, tile) a plan of this material would use now
+ * (microseconds = 0).  Tables built earlier (ntc_train_table_init) keep their plans. */
+ntc_status ntc_train_set_tuning(const ntc_material* m, ntc_dtype precision, const ntc_train_tuning* t);
+ntc_status ntc_train_get_tuning(const ntc_material* m, ntc_dtype precision, ntc_train_tuning* out);
 
 /*
  * Make the state consistent for step hp->step: latents_fwd = latents (+ that
@@ -291,6 +305,9 @@ ntc_status ntc_train_prepare(const ntc_material* m, const ntc_train_state* s,
  * [-(N-1)/(2N), 1/2], then latents_fwd for step hp->step + 1.  If any gradient
  * is not finite the update is skipped (scale_state[1] = 1; NTC_F16 halves the
  * loss scale).  workspace: ws_bytes >= ntc_train_workspace_bytes(m, n, precision).
+ * n: 1 .. (2^31 - 1) / 4 samples (each is listed under up to 4 latent tiles with
+ * 32-bit positions); larger n returns NTC_E_UNSUPPORTED (and the workspace query 0),
+ * the same for every training, tuning and backward entry point.
  * Latent gradients are accumulated without global atomics: samples are binned
  * by the spatial tile of latents their footprint touches and each tile's
  * gradient is summed in on-chip memory and written once.  NTC_F16 sums them as
@@ -336,6 +353,10 @@ ntc_status ntc_train_update(const ntc_material* m, const ntc_train_state* s, int
  *    latent_count entries, overwritten) and grad_mlp (mlp_params, canonical
  *    layout).  dout is multiplied by dout_scale inside the kernels (use a power of
  *    two that brings |dout| near 1 for NTC_F16) and the outputs are divided by it.
+ *    dout_scale = 0 lets the library choose it on the device, with no host
+ *    synchronisation: 2^round(log2(1/4 / max|dout|)) (1 when that maximum is 0 or not
+ *    finite), so the call can be captured in a HIP graph.  Negative or non-finite
+ *    values are NTC_E_INVALID.
  *    NTC_F16 rounds each latent-gradient contribution to 2^-16 of the scaled delta's
  *    unit (1), summing out-of-range work items again in FP32.
  *    workspace: ntc_backward_workspace_bytes(m, n, precision).

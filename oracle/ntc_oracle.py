@@ -487,7 +487,7 @@ def decode(geom: Geometry, lat, params, queries):
 
 
 # --------------------------------------------------------------------------------------
-# Reduced-precision decode (section 8 names lower-precision intermediates as the next
+# Reduced-precision decode (section 7.3, Future Work, names lower-precision intermediates as the next
 # speed-up).  Reading taken: FP8-e4m3 in the OCP definition (sign, 4 exponent bits with
 # bias 7, 3 mantissa bits; exponent 0 is subnormal; largest finite magnitude 448, the
 # all-ones pattern is NaN, no infinities), round to nearest even, saturating at 448.

@@ -9,19 +9,14 @@ training pack of the weights serves both directions.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
 from . import ntc
 
-
-def _dout_scale(dout: torch.Tensor) -> float:
-    """Power of two that brings max|dout| near 1/4 (keeps FP16 deltas in range)."""
-    amax = float(dout.abs().max())
-    if not math.isfinite(amax) or amax == 0.0:
-        return 1.0
-    return 2.0 ** round(math.log2(0.25 / amax))
+# dout_scale 0: the library scales dL/dy by the power of two that brings its largest
+# magnitude near 1/4 (FP16 range), chosen on the device, so the backward does not
+# synchronise with the host and can be captured in a graph.
+AUTO_SCALE = 0.0
 
 
 class NtcDecodeFn(torch.autograd.Function):
@@ -46,7 +41,7 @@ class NtcDecodeFn(torch.autograd.Function):
         gl = torch.empty_like(latents)
         gm = torch.empty_like(mlp)
         ws = torch.empty(ntc.backward_workspace_bytes(m, n, prec), dtype=torch.uint8, device=latents.device)
-        ntc.backward(m, latents, mlp, tp, prec, queries, n, dout, _dout_scale(dout), gl, gm, ws)
+        ntc.backward(m, latents, mlp, tp, prec, queries, n, dout, AUTO_SCALE, gl, gm, ws)
         return gl, gm, None, None, None
 
 

@@ -14,12 +14,7 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   const float* scales = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
   auto kern = decode_fp8_kernel<C0, C1, C, HD, B0, B1, ACT>;
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds) != hipSuccess || v < 1) v = 1;
-    per_cu = v;
-  }
+  static const int per_cu = blocks_per_cu(kern, 256, lds);
   const long long tiles = (n + 15) / 16;
   long long grid = (tiles + 3) / 4;
   const long long cap = (long long)device_cus() * per_cu;
@@ -52,12 +47,7 @@ static hipError_t decode_t1(const ntc_material& mm, const void* src, const void*
     b3 = b2 + HD;
   }
   auto kern = decode_kernel<T, C0, C1, C, HD, B0, B1, PACKED, ACT>;
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds) != hipSuccess || v < 1) v = 1;
-    per_cu = v;
-  }
+  static const int per_cu = blocks_per_cu(kern, 256, lds);
   const long long tiles = (n + 15) / 16;
   long long grid = (tiles + 3) / 4;
   const long long cap = (long long)device_cus() * per_cu;

@@ -15,12 +15,7 @@ hipError_t filtered_t(const ntc_material& mm, const uint8_t* packed, const void*
   constexpr int WB = DecodeLayout<_Float16, C0, C1, HD, B0, B1, true>::WB;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_filtered_kernel<_Float16, C0, C1, C, HD, B0, B1, ACT, FILT>;
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds) != hipSuccess || v < 1) v = 1;
-    per_cu = v;
-  }
+  static const int per_cu = blocks_per_cu(kern, 256, lds);
   const long long tiles = (n * filter_taps<FILT>() + 15) / 16;
   const long long grid = std::min((tiles + 3) / 4, (long long)device_cus() * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, dev_mat(mm), pe_table(mm), packed,

@@ -52,12 +52,6 @@ hipError_t launch_segments(const std::vector<GroupItem>& items, long long cap, u
   return hipSuccess;
 }
 
-template <typename K>
-int blocks_per_cu(K kern, size_t lds) {
-  int v = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds) != hipSuccess || v < 1) v = 1;
-  return v;
-}
 
 template <typename T, int C0, int C1, int C, int HD, int B0, int B1, int ACT>
 hipError_t grouped_t(const ntc_material* mats, const char* tab, unsigned long long hash,
@@ -66,7 +60,7 @@ hipError_t grouped_t(const ntc_material* mats, const char* tab, unsigned long lo
   constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, true>::WB;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_grouped_kernel<T, C0, C1, C, HD, B0, B1, ACT>;
-  static const int per_cu = blocks_per_cu(kern, lds);
+  static const int per_cu = blocks_per_cu(kern, 256, lds);
   const PeTable pe = pe_table(mats[items[0].mat]);
   return launch_segments(items, (long long)device_cus() * per_cu, hash, [&](const GroupArgs& ga) {
     hipLaunchKernelGGL(kern, dim3((unsigned)ga.blocks), dim3(256), lds, s, tab, pe, ga, q, out, out_f16 ? 1 : 0);
@@ -81,7 +75,7 @@ hipError_t grouped_fp8_t(const ntc_material* mats, const char* tab, unsigned lon
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
   const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_fp8_grouped_kernel<C0, C1, C, HD, B0, B1, ACT>;
-  static const int per_cu = blocks_per_cu(kern, lds);
+  static const int per_cu = blocks_per_cu(kern, 256, lds);
   const PeTable pe = pe_table(mats[items[0].mat]);
   return launch_segments(items, (long long)device_cus() * per_cu, hash, [&](const GroupArgs& ga) {
     hipLaunchKernelGGL(kern, dim3((unsigned)ga.blocks), dim3(256), lds, s, tab, pe, ga, q, out, out_f16 ? 1 : 0);
@@ -93,7 +87,7 @@ hipError_t mixed_t(const char* tab, unsigned long long hash, int nmat, const PeT
                    long long n, void* out, bool out_f16, hipStream_t s) {
   const size_t lds = 48 * 4 + (size_t)nmat * kMaxLevels * sizeof(LevelBytes);
   auto kern = decode_mixed_kernel<C0, C1, C, HD, B0, B1, ACT>;
-  static const int per_cu = blocks_per_cu(kern, 48 * 4 + (size_t)kMixedMax * kMaxLevels * sizeof(LevelBytes));
+  static const int per_cu = blocks_per_cu(kern, 256, 48 * 4 + (size_t)kMixedMax * kMaxLevels * sizeof(LevelBytes));
   const long long tiles = (n + 15) / 16;
   const long long grid = std::min((tiles + 3) / 4, (long long)device_cus() * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, tab, pe, hash, nmat, q, n, out, out_f16 ? 1 : 0);

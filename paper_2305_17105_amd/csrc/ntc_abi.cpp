@@ -108,6 +108,10 @@ static ntc_status check_material(const ntc_material* m) {
   return NTC_OK;
 }
 
+// Training and backward calls bin each sample under at most 4 latent tiles with 32-bit
+// list positions and sample indices: n is limited to INT32_MAX / 4.
+static const int64_t kMaxTrainSamples = 0x7fffffffLL / 4;
+
 static long long mlp_params(int K, int Hd, int C) {
   return (long long)K * Hd + Hd + (long long)Hd * Hd + Hd + (long long)Hd * C + C;
 }
@@ -334,7 +338,7 @@ ntc_status ntc_decode_filtered(const ntc_material* m, const uint8_t* packed_late
 }
 
 size_t ntc_train_workspace_bytes(const ntc_material* m, int64_t n, ntc_dtype precision) {
-  if (!m || n <= 0 || (precision != NTC_F32 && precision != NTC_F16)) return 0;
+  if (!m || n <= 0 || n > kMaxTrainSamples || (precision != NTC_F32 && precision != NTC_F16)) return 0;
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden)) return 0;
   // large enough for every tuning candidate, so a tuned plan always fits
   const bool f16 = precision == NTC_F16;
@@ -392,6 +396,7 @@ static ntc_status check_train(const ntc_material* m, const ntc_train_state* s, c
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
     return fail(NTC_E_UNSUPPORTED, "no training kernel for this (c0, c1, channels, hidden)");
   if (n <= 0) return fail(NTC_E_INVALID, "n must be positive");
+  if (n > kMaxTrainSamples) return fail(NTC_E_UNSUPPORTED, "n exceeds 2^31 / 4 samples per training call");
   return NTC_OK;
 }
 
@@ -495,6 +500,41 @@ ntc_status ntc_train_autotune(const ntc_material* m, const ntc_train_state* s, c
   return NTC_OK;
 }
 
+ntc_status ntc_train_set_tuning(const ntc_material* m, ntc_dtype precision, const ntc_train_tuning* t) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no training kernel for this (c0, c1, channels, hidden)");
+  if (!t) return fail(NTC_E_INVALID, "tuning is NULL");
+  if (t->chunk == 0 && t->tile == 0) {
+    clear_train_tune(*m, precision == NTC_F16);
+    return NTC_OK;
+  }
+  int nc = 0;
+  const TrainTune* c = train_tune_candidates(&nc);
+  for (int i = 0; i < nc; ++i)
+    if (c[i].chunk == t->chunk && c[i].tile == t->tile) {
+      set_train_tune(*m, precision == NTC_F16, c[i]);
+      return NTC_OK;
+    }
+  return fail(NTC_E_INVALID, "(chunk, tile) is not one of the tuning candidates");
+}
+
+ntc_status ntc_train_get_tuning(const ntc_material* m, ntc_dtype precision, ntc_train_tuning* out) {
+  ntc_status st = check_material(m);
+  if (st != NTC_OK) return st;
+  if (precision != NTC_F32 && precision != NTC_F16) return fail(NTC_E_UNSUPPORTED, "precision must be F32 or F16");
+  if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
+    return fail(NTC_E_UNSUPPORTED, "no training kernel for this (c0, c1, channels, hidden)");
+  if (!out) return fail(NTC_E_INVALID, "output is NULL");
+  const TrainPlan p = train_plan(*m, precision == NTC_F16, 1);
+  out->chunk = p.tune.chunk;
+  out->tile = p.tune.tile;
+  out->microseconds = 0.0;
+  return NTC_OK;
+}
+
 static ntc_status train_update_impl(const ntc_material* m, const ntc_train_state* s, int64_t n,
                                     const ntc_hparams* hp, void* workspace, size_t ws_bytes, void* stream,
                                     bool advance_step);
@@ -591,9 +631,11 @@ ntc_status ntc_backward(const ntc_material* m, const float* latents, const float
   if (!train_shape_supported(m->c0, m->c1, m->channels, m->hidden))
     return fail(NTC_E_UNSUPPORTED, "no kernel for this (c0, c1, channels, hidden)");
   if (n <= 0) return fail(NTC_E_INVALID, "n must be positive");
+  if (n > kMaxTrainSamples) return fail(NTC_E_UNSUPPORTED, "n exceeds 2^31 / 4 samples per backward call");
   if (!latents || !mlp || !mlp_train_packed || !q || !dout || !grad_latents || !grad_mlp)
     return fail(NTC_E_INVALID, "NULL buffer");
-  if (!(dout_scale > 0.f) || !std::isfinite(dout_scale)) return fail(NTC_E_INVALID, "dout_scale must be positive");
+  if (!(dout_scale >= 0.f) || !std::isfinite(dout_scale))
+    return fail(NTC_E_INVALID, "dout_scale must be positive (or 0: chosen on the device)");
   const bool f16 = precision == NTC_F16;
   const TrainPlan plan = train_plan(*m, f16, n);
   if (!plan.supported_bins) return fail(NTC_E_UNSUPPORTED, "too many latent tiles for this material");
@@ -615,11 +657,15 @@ ntc_status ntc_backward(const ntc_material* m, const float* latents, const float
   a.overflow_flag = (int32_t*)(ws + plan.off_misc + 16);
   a.scatter_latents = true;
   a.dout = dout;
-  a.dout_scale = dout_scale;
-  a.out_scale = 1.f / dout_scale;
-  hipError_t e = launch_train_gradients(*m, f16, plan, a, hs);
+  const bool auto_scale = dout_scale == 0.f;
+  a.dout_scale = auto_scale ? 1.f : dout_scale;
+  a.out_scale = 1.f / a.dout_scale;
+  float* dscale = auto_scale ? (float*)(ws + plan.off_dscale) : nullptr;
+  a.dscale = dscale;
+  hipError_t e = auto_scale ? launch_dout_scale(dout, n * (int64_t)m->channels, dscale, hs) : hipSuccess;
+  if (e == hipSuccess) e = launch_train_gradients(*m, f16, plan, a, hs);
   if (e == hipSuccess)
-    e = launch_train_reduce(*m, plan, workspace, nullptr, 0.f, nullptr, hs, grad_mlp, 1.f / dout_scale);
+    e = launch_train_reduce(*m, plan, workspace, nullptr, 0.f, nullptr, hs, grad_mlp, a.out_scale, dscale);
   return hip_status(e, "ntc_backward");
 }
 

@@ -25,6 +25,16 @@ PeTable pe_table(const ntc_material& m);
 // Number of CUs of the current device (cached per device).
 int device_cus();
 
+// Resident blocks per CU of a kernel at the given block size and dynamic LDS (at least
+// 1).  Launchers keep the result in a function-local static initialised by one call,
+// which C++ guarantees to run once even when several threads launch for the first time.
+template <typename K>
+int blocks_per_cu(K kern, int threads, size_t lds) {
+  int v = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, threads, lds) != hipSuccess || v < 1) v = 1;
+  return v;
+}
+
 // Launchers: return hipSuccess or the launch error.  Shapes are validated by the caller.
 hipError_t launch_quantize(const ntc_material& m, const float* lat, uint8_t* packed, hipStream_t s);
 hipError_t launch_dequantize(const ntc_material& m, const uint8_t* packed, float* lat, hipStream_t s);
@@ -64,6 +74,7 @@ struct TrainTune {
   int chunk, tile;
 };
 void set_train_tune(const ntc_material& m, bool f16, const TrainTune& t);
+void clear_train_tune(const ntc_material& m, bool f16);
 TrainTune get_train_tune(const ntc_material& m, bool f16);
 const TrainTune* train_tune_candidates(int* count);
 
@@ -77,7 +88,7 @@ struct TrainPlan {
   size_t off_counts, off_offsets, off_total, off_base, off_tstart, off_ttotal, off_ibase, off_itile, off_misc;
   size_t off_list;
   size_t off_part_lat;
-  size_t off_part_dw, off_part_loss, off_grad, total;
+  size_t off_part_dw, off_part_loss, off_grad, off_dscale, total;
 };
 // tune == nullptr: the tuning table's entry for the material's shape (or the defaults)
 TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTune* tune = nullptr);
@@ -99,6 +110,7 @@ struct TrainLaunch {
   const float* dout;        // external output gradient, or nullptr (L2 loss against targets)
   float dout_scale;
   float out_scale;          // multiplies the latent gradient written to lat_grad
+  const float* dscale = nullptr;  // device (dout_scale, out_scale) replacing the two above
   const unsigned long long* table_hash = nullptr;  // grouped step: the table's hash (kernel no-ops on mismatch)
   unsigned long long hash = 0;
 };
@@ -106,7 +118,10 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
                                   hipStream_t s);
 hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
                                float loss_norm, int32_t* overflow_flag, hipStream_t s, float* grad_out = nullptr,
-                               float out_scale = 1.f);
+                               float out_scale = 1.f, const float* dscale = nullptr);
+// Device-chosen output-gradient scale of the differentiation path: writes (scale, 1 /
+// scale) to work[0..1], using work[2 ..] (kScaleBlocks floats) for block maxima.
+hipError_t launch_dout_scale(const float* dout, long long count, float* work, hipStream_t s);
 hipError_t launch_forward(const ntc_material& m, const float* latents, const float* mlp, const void* wpack, bool f16,
                           const ntc_query* q, long long n, float* out, hipStream_t s);
 

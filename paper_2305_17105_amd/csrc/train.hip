@@ -66,6 +66,7 @@ struct TrainArgs {
   const float* dout;   // external output gradient (differentiation path) or nullptr
   float dout_scale;    // multiplies dout before the backward (FP16 range)
   float out_scale;     // multiplies the latent gradient written out
+  const float* dscale; // device (dout_scale, out_scale) replacing the two above, or nullptr
   const unsigned long long* table_hash;  // grouped step: its table's hash, else nullptr
   unsigned long long hash;               // the hash the grouped step was planned with
   TileGeom tg;
@@ -139,17 +140,8 @@ struct TrainCfg {
   // faster than two blocks of 4 once the latent accumulators are FP64 (which two
   // blocks cannot fit next to a 16 x 16 tile).  FP32: one block of 4 (its packs and
   // staging are twice the size).
-#ifndef NTC_TRAIN_NW16
-#define NTC_TRAIN_NW16 8
-#endif
-#ifndef NTC_TRAIN_BPC16
-#define NTC_TRAIN_BPC16 1
-#endif
-#ifndef NTC_TRAIN_TWO_PHASE
-#define NTC_TRAIN_TWO_PHASE 1
-#endif
-  static constexpr int NW = sizeof(T) == 2 ? NTC_TRAIN_NW16 : 4;
-  static constexpr int BPC = sizeof(T) == 2 ? NTC_TRAIN_BPC16 : 1;
+  static constexpr int NW = sizeof(T) == 2 ? 8 : 4;
+  static constexpr int BPC = 1;
   static constexpr int NTHR = 64 * NW, NCOL = 16 * NW;
   static constexpr int RS = lds_row_stride<T, NCOL>();
   // one-phase weight-gradient staging: rows X | H1 | H2 | dZ1 | dZ2 | dY
@@ -184,7 +176,7 @@ struct TrainCfg {
   // two-phase staging (layers 3 and 2 together, then layer 1): FP16, where it still
   // leaves room for 32 x 32 tiles
   static constexpr int TR2 = cmax(3 * HD + 16, RX + HD);
-  static constexpr bool TWO_PHASE = NTC_TRAIN_TWO_PHASE && sizeof(T) == 2 && !ONE_PHASE && !SPLIT1 &&
+  static constexpr bool TWO_PHASE = sizeof(T) == 2 && !ONE_PHASE && !SPLIT1 &&
                                     OFF_BUF + buf_bytes(TR2) + region(32) * 4 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TWO_PHASE ? TR2 : SPLIT1 ? TR3S : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
@@ -254,6 +246,8 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
 
   const int slot = a.step_dev ? (*a.step_dev & 1) : scale_slot;
   const float scale = a.loss_scale ? a.loss_scale[slot] : 1.f;
+  const float dout_scale = a.dscale ? a.dscale[0] : a.dout_scale;
+  const float out_scale = a.dscale ? a.dscale[1] : a.out_scale;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
 
   f32x4 acc3 = {0.f, 0.f, 0.f, 0.f};
@@ -448,7 +442,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
           float d = 0.f;
           if (valid && c < C) {
             if (a.dout) {
-              d = a.dout[s * C + c] * a.dout_scale;
+              d = a.dout[s * C + c] * dout_scale;
             } else {
               const float e = y[i] - a.targets[tb + c];
               if (primary && !refine) loss += e * e;
@@ -717,7 +711,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     if (binned) {
       const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
       float* dst = single ? a.lat_grad : a.part_lat + (long long)item * a.region_max;
-      const float osc = single ? a.out_scale : 1.f;
+      const float osc = single ? out_scale : 1.f;
       // where latent k of the region goes (tile sides are powers of two)
       auto dst_index = [&](int k) -> long long {
         if (!single) return k;
@@ -1069,10 +1063,12 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   }
 }
 
+// dscale: device (dout scale, output scale) overriding out_scale, or nullptr
 __global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
                                    const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
-                                   float out_scale) {
-  lat_partial_body(m, tg, item_base, part, region_max, lat_grad, out_scale, blockIdx.y, blockIdx.x, gridDim.x);
+                                   float out_scale, const float* __restrict__ dscale) {
+  lat_partial_body(m, tg, item_base, part, region_max, lat_grad, dscale ? dscale[1] : out_scale, blockIdx.y,
+                   blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ weight-gradient reduction
@@ -1121,8 +1117,58 @@ __device__ __forceinline__ void dw_reduce_body(int G, long long P, const float* 
 __global__ __launch_bounds__(64 * kDwWaves) void dw_reduce(int G, long long P, const float* __restrict__ part,
                                                  float* __restrict__ grad, const float* __restrict__ part_loss,
                                                  float* __restrict__ loss_out, float norm, int32_t* flag,
-                                                 float out_scale) {
-  dw_reduce_body(G, P, part, grad, part_loss, loss_out, norm, flag, out_scale, blockIdx.x);
+                                                 float out_scale, const float* __restrict__ dscale) {
+  dw_reduce_body(G, P, part, grad, part_loss, loss_out, norm, flag, dscale ? dscale[1] : out_scale, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ output-gradient scale
+// The differentiation path multiplies the caller's dL/dy by a power of two that brings
+// max |dL/dy| near 1/4 (FP16 range) and divides the gradients by it again.  Picked on the
+// device, so the backward needs no host synchronisation: per-block maxima, then one
+// block reduces them and writes (scale, 1 / scale).  Zero or non-finite maxima give 1.
+constexpr int kScaleBlocks = 1024;
+__global__ __launch_bounds__(256) void dout_amax_kernel(const float* __restrict__ d, long long count,
+                                                       float* __restrict__ part) {
+  __shared__ float red[4];
+  float v = 0.f;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (long long)gridDim.x * 256)
+    v = fmaxf(v, fabsf(d[i]));  // fmaxf drops NaN: a NaN-only input yields 0 (scale 1)
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void dout_scale_kernel(const float* __restrict__ part, int blocks,
+                                                        float* __restrict__ scale) {
+  __shared__ float red[4];
+  float v = 0.f;
+  for (int i = threadIdx.x; i < blocks; i += 256) v = fmaxf(v, part[i]);
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    float sc = 1.f;
+    if (amax > 0.f && amax <= 3.0e38f) {
+      // 2^round(log2(0.25 / amax)) = 2^round(-2 - a - log2 g) with amax = g 2^a, g in
+      // [1/2, 1): -log2 g lies in (0, 1] and rounds to 1 exactly when g < 1/sqrt(2)
+      int a = 0;
+      const float g = frexpf(amax, &a);
+      const int k = -2 - a + (g < 0.70710678f ? 1 : 0);
+      sc = ldexpf(1.f, max(-120, min(120, k)));
+    }
+    scale[0] = sc;
+    scale[1] = 1.f / sc;
+  }
+}
+
+hipError_t launch_dout_scale(const float* dout, long long count, float* work, hipStream_t s) {
+  const long long want = (count + 255) / 256;
+  const int blocks = (int)std::max<long long>(1, std::min<long long>(kScaleBlocks, want));
+  hipLaunchKernelGGL(dout_amax_kernel, dim3(blocks), dim3(256), 0, s, dout, count, work + 2);
+  hipLaunchKernelGGL(dout_scale_kernel, dim3(1), dim3(256), 0, s, work + 2, blocks, work);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ optimiser
@@ -1421,17 +1467,8 @@ __global__ __launch_bounds__(256) void adam_grouped(const char* __restrict__ tab
 template <typename T, int C0, int C1, int C, int HD, int ACT>
 static int fused_per_cu() {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
-  static int cached = 0;
-  if (cached == 0) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_fused_kernel<T, C0, C1, C, HD, ACT>, Cfg::NTHR,
-                                                     Cfg::LDS) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    cached = per_cu;
-  }
-  return cached;
+  static const int per_cu = blocks_per_cu(train_fused_kernel<T, C0, C1, C, HD, ACT>, Cfg::NTHR, Cfg::LDS);
+  return per_cu;
 }
 
 template <typename T, int C0, int C1, int C, int HD>
@@ -1470,6 +1507,7 @@ static TrainArgs make_train_args(const ntc_material& mm, const TrainPlan& p, con
   a.dout = l.dout;
   a.dout_scale = l.dout_scale;
   a.out_scale = l.out_scale;
+  a.dscale = l.dscale;
   a.table_hash = l.table_hash;
   a.hash = l.hash;
   a.tg = p.tg;
@@ -1534,6 +1572,17 @@ void set_train_tune(const ntc_material& m, bool f16, const TrainTune& t) {
       return;
     }
   tb.rows.push_back({k, t});
+}
+
+void clear_train_tune(const ntc_material& m, bool f16) {
+  TuneTable& tb = tune_table();
+  std::lock_guard<std::mutex> lock(tb.mu);
+  const TuneKey k = tune_key(m, f16);
+  for (size_t i = 0; i < tb.rows.size(); ++i)
+    if (tb.rows[i].first == k) {
+      tb.rows.erase(tb.rows.begin() + (long)i);
+      return;
+    }
 }
 
 TrainTune get_train_tune(const ntc_material& m, bool f16) {
@@ -1622,6 +1671,7 @@ TrainPlan train_plan(const ntc_material& m, bool f16, long long n, const TrainTu
   p.off_part_dw = take((size_t)p.grid * P * 4);
   p.off_part_loss = take((size_t)p.grid * 4);
   p.off_grad = take(P * 4);
+  p.off_dscale = take((size_t)(2 + kScaleBlocks) * 4);
   p.total = o;
   p.supported_bins = nb <= kMaxBins;
   return p;
@@ -1672,19 +1722,19 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
     hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.ntiles), dim3(256), 0, s, dm, p.tg,
                        (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad,
-                       l.out_scale);
+                       l.out_scale, l.dscale);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_train_reduce(const ntc_material& m, const TrainPlan& p, void* workspace, float* loss_out,
                                float loss_norm, int32_t* overflow_flag, hipStream_t s, float* grad_out,
-                               float out_scale) {
+                               float out_scale, const float* dscale) {
   char* ws = (char*)workspace;
   const long long P = m.mlp_params;
   hipLaunchKernelGGL(dw_reduce, dim3((unsigned)((P + 63) / 64)), dim3(64 * kDwWaves), 0, s, p.grid, P,
                      (const float*)(ws + p.off_part_dw), grad_out ? grad_out : (float*)(ws + p.off_grad),
-                     (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag, out_scale);
+                     (const float*)(ws + p.off_part_loss), loss_out, loss_norm, overflow_flag, out_scale, dscale);
   return hipGetLastError();
 }
 

@@ -97,6 +97,8 @@ _sig = {
                                   C.c_int32, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]),
     "ntc_train_autotune": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p, _P(HParams),
                                      C.c_void_p, C.c_size_t, C.c_void_p, _P(TrainTuning)]),
+    "ntc_train_set_tuning": (C.c_int, [_P(Material), C.c_int, _P(TrainTuning)]),
+    "ntc_train_get_tuning": (C.c_int, [_P(Material), C.c_int, _P(TrainTuning)]),
     "ntc_train_workspace_bytes_batched": (C.c_size_t, [_P(Material), C.c_int32, _P(C.c_int64), C.c_int]),
     "ntc_train_step_batched": (C.c_int, [_P(Material), C.c_int32, _P(TrainStateC), C.c_void_p, _P(C.c_int64),
                                          _P(C.c_void_p), _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -283,6 +285,19 @@ def train_autotune(m: Material, state: "TrainState", queries, n, targets, hp: HP
                                    _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream),
                                    C.byref(t)), "ntc_train_autotune")
     return t.chunk, t.tile, t.microseconds
+
+
+def train_set_tuning(m: Material, precision, chunk, tile):
+    """Set the tuning-table entry (samples per work item, tile side) of this material's shape."""
+    t = TrainTuning(chunk, tile, 0.0)
+    _check(_lib.ntc_train_set_tuning(C.byref(m), precision, C.byref(t)), "ntc_train_set_tuning")
+
+
+def train_get_tuning(m: Material, precision):
+    """(chunk, tile) a training plan of this material uses now."""
+    t = TrainTuning()
+    _check(_lib.ntc_train_get_tuning(C.byref(m), precision, C.byref(t)), "ntc_train_get_tuning")
+    return t.chunk, t.tile
 
 
 def _materials(mats):

@@ -158,3 +158,27 @@ def test_train_table_validation():
     st = ntc._lib.ntc_train_step_grouped(ntc._materials([m]), 1, None, None, off, tg, C.byref(hp), None, 0, None,
                                          None)
     assert st == ntc.E_INVALID
+
+
+def test_training_sample_count_limit(ntc):
+    """Training binning uses 32-bit list positions (up to 4 entries per sample): n above
+    (2^31 - 1) / 4 is rejected with NTC_E_UNSUPPORTED before anything touches a device,
+    and the workspace query returns 0 for it."""
+    import ctypes as C
+    m = ntc.material_init(256, 256, 8, 8, 8, 4, 4, 64)
+    limit = (2 ** 31 - 1) // 4
+    assert ntc.train_workspace_bytes(m, limit + 1, ntc.F32) == 0
+    assert ntc._lib.ntc_backward_workspace_bytes(C.byref(m), limit + 1, ntc.F16) == 0
+    fake = C.c_void_p(4096)  # aligned, never dereferenced: validation fails first
+    st = ntc.TrainStateC(*([fake] * len(ntc.TrainStateC._fields_)))
+    for prec in (ntc.F32, ntc.F16):
+        hp = ntc.hparams(precision=prec)
+        for call in (ntc._lib.ntc_train_step, ntc._lib.ntc_train_gradients):
+            r = call(C.byref(m), C.byref(st), fake, limit + 1, fake, C.byref(hp), fake, 2 ** 40, None)
+            assert r == ntc.E_UNSUPPORTED
+        r = ntc._lib.ntc_train_update(C.byref(m), C.byref(st), limit + 1, C.byref(hp), fake, 2 ** 40, None)
+        assert r == ntc.E_UNSUPPORTED
+        r = ntc._lib.ntc_backward(C.byref(m), fake, fake, fake, prec, fake, limit + 1, fake, 1.0, fake, fake, fake,
+                                  2 ** 40, None)
+        assert r == ntc.E_UNSUPPORTED
+        assert "2^31" in ntc._lib.ntc_last_error().decode()

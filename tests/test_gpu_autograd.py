@@ -5,7 +5,7 @@ parameters."""
 import numpy as np
 import pytest
 
-from _helpers import geometry, queries_dev, rel_err, to_dev
+from _helpers import geometry, mlp_in_unit_range, queries_dev, rel_err, to_dev
 from oracle import ntc_oracle as O
 from paper_2305_17105_amd import synth
 
@@ -68,7 +68,7 @@ def test_autograd_matches_oracle(setup, prec):
         for v in errs.values():
             assert v <= 1e-3
     else:
-        assert yerr <= 2e-2  # raw Xavier outputs are O(1); FP16 inputs and activations
+        assert yerr <= 2e-2  # raw Xavier outputs are O(1): 2e-3 applies to outputs in [0, 1] (below)
         for v in errs.values():
             assert v <= 2e-2
         # with the ReLU decisions taken in FP16 (as the kernel takes them) the
@@ -77,7 +77,53 @@ def test_autograd_matches_oracle(setup, prec):
         derrs = {"latents": rel_err(gl, gl_d), "mlp": rel_err(gm, gp_d)}
         print("f16 vs decision-matched oracle:", {k: f"{v:.2e}" for k, v in derrs.items()})
         for v in derrs.values():
-            assert v <= 5e-3
+            assert v <= 1e-3
+
+
+def test_autograd_fp16_outputs_in_unit_range(setup):
+    """The FP16 forward on a network whose outputs lie near [0, 1] (damped output layer,
+    b3 = 1/2): within 2e-3 max-abs of the float64 oracle."""
+    import torch
+    from paper_2305_17105_amd.autograd import ntc_decode_fn
+    ntc, m, g, lat, _, q, _ = setup
+    mlp = mlp_in_unit_range(32, g.K, g.Hd, g.C)
+    with torch.no_grad():
+        y = ntc_decode_fn(m, to_dev(lat), to_dev(mlp), queries_dev(q), ntc.F16)
+    yref = O.decode(g, lat.astype(np.float64), mlp, q)
+    err = np.max(np.abs(y.cpu().numpy().astype(np.float64) - yref))
+    print(f"f16 forward on [0,1] outputs: max-abs err {err:.2e} (outputs in [{yref.min():.2f}, {yref.max():.2f}])")
+    assert err <= 2e-3
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_backward_device_scale_equals_explicit(setup, prec):
+    """dout_scale = 0 picks 2^round(log2(1/4 / max|dout|)) on the device; the result is
+    bit-identical to passing that power of two from the host."""
+    import math
+    import torch
+    ntc, m, g, lat, mlp, q, _ = setup
+    P = ntc.F32 if prec == "f32" else ntc.F16
+    n = len(q)
+    dout = torch.from_numpy(np.random.default_rng(5).normal(0, 3e-4, n * g.C).astype(np.float32)).cuda()
+    tp = torch.zeros(ntc.train_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    tl, tm = to_dev(lat), to_dev(mlp)
+    ntc.pack_mlp_train(m, tm, P, tp)
+    ws = torch.zeros(ntc.backward_workspace_bytes(m, n, P), dtype=torch.uint8, device="cuda")
+    qd = queries_dev(q)
+    amax = float(dout.abs().max())
+    host_scale = 2.0 ** round(math.log2(0.25 / amax))
+    res = []
+    for sc in (0.0, host_scale):
+        gl, gm = torch.empty_like(tl), torch.empty_like(tm)
+        ntc.backward(m, tl, tm, tp, P, qd, n, dout, sc, gl, gm, ws)
+        torch.cuda.synchronize()
+        res.append((gl.cpu().numpy(), gm.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    # a zero dout gets scale 1 and zero gradients
+    gl, gm = torch.empty_like(tl), torch.empty_like(tm)
+    ntc.backward(m, tl, tm, tp, P, qd, n, torch.zeros_like(dout), 0.0, gl, gm, ws)
+    torch.cuda.synchronize()
+    assert not gl.cpu().numpy().any() and not gm.cpu().numpy().any()
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])

@@ -189,10 +189,76 @@ def test_decode_fp8_parity(lib, shape):
     # The e4m3 oracle rounds the same values; a value within FP32 rounding of an e4m3
     # midpoint may round the other way (one e4m3 step of one hidden unit), so a few
     # outputs differ by up to ~1e-2 while almost all agree to FP32 accumulation order.
+    # The float64 distance is the cost of e4m3 itself; the stated 1e-2 bar against
+    # float64 is checked (and not met) in test_decode_fp8_stated_bar.
     assert e8.mean() <= 2e-5 and np.quantile(e8, 0.99) <= 1e-3 and e8.max() <= 2e-2
-    # Against float64 the e4m3 rounding of weights and hidden activations itself costs
-    # up to ~2.5e-2 on these outputs (measured error budget in the design notes)
-    assert e64.max() <= 3e-2 and e64.mean() <= 5e-3
+
+
+def _trained_fixture(lib):
+    """The 256^2 x 16 material trained by the oracle (tests/golden/make_trained_decode_fixture.py):
+    its packed latents and network, as device tensors, plus the oracle geometry."""
+    import os
+    import torch
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "trained_decode_256x16.npz"))
+    W, C, c0, c1, b0, b1, hd = (int(v) for v in z["shape"])
+    m = lib.material_init(W, W, C, c0, c1, b0, b1, hd)
+    g = geometry(m)
+    assert len(z["packed"]) == int(m.packed_bytes)
+    packed = torch.from_numpy(z["packed"].copy()).cuda()
+    return m, g, packed, z["mlp"].astype(np.float32), O.dequantize_packed(g, z["packed"])
+
+
+def _decode_with(lib, m, packed, mlp, P, q):
+    import torch
+    n, C = len(q), int(m.channels)
+    wp = torch.zeros(lib.mlp_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp(m, to_dev(mlp), P, wp)
+    out = torch.full((n * C,), float("nan"), dtype=torch.float32, device="cuda")
+    lib.decode(m, packed, wp, P, queries_dev(q), n, out, lib.F32)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64).reshape(n, C)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "fp8"])
+def test_decode_trained_weights(lib, prec):
+    """Decode parity on a network trained by the oracle (outputs in [0, 1]): FP32 <= 1e-5 and
+    FP16 <= 2e-3 max-abs against float64; FP8 against the oracle's e4m3 arithmetic."""
+    m, g, packed, mlp, lat = _trained_fixture(lib)
+    q = synth.random_queries(91, 40009, g.M)
+    P = {"f32": lib.F32, "f16": lib.F16, "fp8": lib.FP8_E4M3}[prec]
+    got = _decode_with(lib, m, packed, mlp, P, q)
+    ref = O.decode(g, lat, mlp, q)
+    e64 = np.abs(got - ref)
+    print(f"trained weights {prec}: outputs in [{ref.min():.3f}, {ref.max():.3f}], vs float64 max {e64.max():.3e} "
+          f"mean {e64.mean():.2e} (PSNR of the decode against float64 {O.psnr([ref], [got]):.1f} dB)")
+    if prec == "fp8":
+        e8 = np.abs(got - O.decode_fp8(g, lat, mlp, q))
+        print(f"  vs e4m3 oracle max {e8.max():.3e} mean {e8.mean():.2e}")
+        assert e8.mean() <= 2e-5 and np.quantile(e8, 0.99) <= 1e-3 and e8.max() <= 3e-2
+    else:
+        assert e64.max() <= {"f32": 1e-5, "f16": 2e-3}[prec]
+
+
+@pytest.mark.xfail(strict=True, reason="plain e4m3 (3 mantissa bits) rounding of weights and activations costs "
+                                       "2.2e-2 (unit-range Xavier) and 6.6e-2 (oracle-trained) max-abs against "
+                                       "float64; no per-layer scaling brings it under 1e-2 (design notes, FP8)")
+@pytest.mark.parametrize("weights", ["unit_range_xavier", "oracle_trained"])
+def test_decode_fp8_stated_bar(lib, weights):
+    """The stated FP8 decode bar: <= 1e-2 max-abs against float64 on outputs in [0, 1]."""
+    if weights == "oracle_trained":
+        m, g, packed, mlp, lat = _trained_fixture(lib)
+    else:
+        m = lib.material_init(512, 512, 16, 16, 16, 2, 4, 64)
+        g = geometry(m)
+        raw = synth.uniform_latents(11, int(m.latent_count))
+        packed = _packed(lib, m, raw)
+        mlp = mlp_in_unit_range(11, g.K, 64, 16)
+        lat = quantized_latents_oracle(g, raw)
+    q = synth.random_queries(92, 40009, g.M)
+    got = _decode_with(lib, m, packed, mlp, lib.FP8_E4M3, q)
+    err = np.abs(got - O.decode(g, lat, mlp, q))
+    print(f"fp8 vs float64 ({weights}): max {err.max():.3e} mean {err.mean():.2e}")
+    assert err.max() <= 1e-2
 
 
 def test_fp8_unsupported_shapes_rejected(lib):
@@ -231,10 +297,15 @@ def test_decode_tile_equals_query_decode(lib, prec):
     lib.decode(m, packed, wp, P, queries_dev(q), w * h, b, lib.F32)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
-    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q).ravel()
-    err = np.max(np.abs(a.cpu().numpy() - ref))
+    lat = quantized_latents_oracle(g, raw)
+    if prec == "fp8":  # the e4m3 arithmetic the FP8 path claims (see test_decode_fp8_parity)
+        e8 = np.abs(a.cpu().numpy() - O.decode_fp8(g, lat, mlp, q).ravel())
+        print(f"decode_tile fp8: vs e4m3 oracle max {e8.max():.3e} mean {e8.mean():.2e}")
+        assert e8.mean() <= 2e-5 and np.quantile(e8, 0.99) <= 1e-3 and e8.max() <= 2e-2
+        return
+    err = np.max(np.abs(a.cpu().numpy() - O.decode(g, lat, mlp, q).ravel()))
     print(f"decode_tile {prec}: max-abs err {err:.3e} vs float64")
-    assert err <= {"f32": 1e-5, "f16": 2e-3, "fp8": 3e-2}[prec]
+    assert err <= {"f32": 1e-5, "f16": 2e-3}[prec]
 
 
 def test_decode_edge_coordinates(lib):
@@ -287,10 +358,15 @@ def test_decode_full_size_sampled(lib, prec):
     torch.cuda.synchronize()
     pick = synth.random_param_indices(8, 65536, n)
     got = out.view(n, 16)[torch.from_numpy(pick).cuda()].float().cpu().numpy().astype(np.float64)
-    ref = O.decode(g, quantized_latents_oracle(g, raw), mlp, q[pick])
-    err = np.max(np.abs(got - ref))
+    lat = quantized_latents_oracle(g, raw)
+    if prec == "fp8":  # against the e4m3 arithmetic; FP16 output rounding adds <= 2^-12 on [0, 1]
+        e8 = np.abs(got - O.decode_fp8(g, lat, mlp, q[pick]))
+        print(f"full-size decode fp8 (FP16 output): vs e4m3 oracle max {e8.max():.3e} mean {e8.mean():.2e}")
+        assert e8.mean() <= 2e-4 and np.quantile(e8, 0.99) <= 1e-3 and e8.max() <= 2e-2
+        return
+    err = np.max(np.abs(got - O.decode(g, lat, mlp, q[pick])))
     print(f"full-size decode {prec} (FP16 output): max-abs err {err:.3e} on {len(pick)} sampled queries")
-    assert err <= {"f32": 1e-3, "f16": 3e-3, "fp8": 3e-2}[prec]  # includes the FP16 rounding of the output
+    assert err <= {"f32": 1e-3, "f16": 3e-3}[prec]  # includes the FP16 rounding of the output
 
 
 FSHAPES = [  # W, C, c0, c1, b0, b1, hidden, n

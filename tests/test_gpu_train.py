@@ -6,7 +6,8 @@ the parameters unchanged and sets the first Adam moment to (1 - beta1) * gradien
 import numpy as np
 import pytest
 
-from _helpers import geometry, queries_dev, quantized_latents_oracle, rel_err, to_dev
+from _helpers import queries_dev, rel_err, to_dev
+from _trainrun import Run, check_grads as _check_grads, grad_groups as _grad_groups, ohp as _ohp
 from oracle import ntc_oracle as O
 from paper_2305_17105_amd import synth
 
@@ -19,81 +20,6 @@ def lib():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2305_17105_amd import ntc
     return ntc
-
-
-class Run:
-    """One material with its GPU training state and the matching oracle state."""
-
-    def __init__(self, lib, W, C, c0, c1, b0, b1, hd, mips, n, lod, seed=0, prec=None, posenc=0, lod_input=0,
-                 loss_scale=65536.0):
-        import torch
-        self.lib = lib
-        self.prec = lib.F32 if prec is None else prec
-        self.m = lib.material_init(W, W, C, c0, c1, b0, b1, hd, num_mips=mips, posenc=posenc, lod_input=lod_input)
-        self.g = geometry(self.m)
-        g = self.g
-        raw = synth.uniform_latents(seed, int(self.m.latent_count))
-        packed = torch.zeros(int(self.m.packed_bytes), dtype=torch.uint8, device="cuda")
-        lib.quantize_latents(self.m, to_dev(raw), packed)
-        lat = torch.zeros(int(self.m.latent_count), dtype=torch.float32, device="cuda")
-        lib.dequantize_latents(self.m, packed, lat)
-        self.mlp = synth.xavier_mlp(seed, g.K, hd, C)
-        self.state = lib.TrainState(self.m, lat, to_dev(self.mlp), self.prec, loss_scale=loss_scale)
-        self.q = synth.random_queries(seed, n, g.M, lod)
-        self.qd = queries_dev(self.q)
-        self.n = n
-        self.mips, tflat = synth.target_chain(seed, 0, W, W, C, g.M)
-        self.targets = tflat
-        self.td = to_dev(tflat)
-        self.ws = torch.zeros(lib.train_workspace_bytes(self.m, n, self.prec), dtype=torch.uint8, device="cuda")
-        P = O.mlp_param_count(g.K, hd, C)
-        self.ostate = dict(latents=quantized_latents_oracle(g, raw), mlp=self.mlp.astype(np.float64),
-                           lat_m=np.zeros(g.latent_count), lat_v=np.zeros(g.latent_count),
-                           mlp_m=np.zeros(P), mlp_v=np.zeros(P))
-
-    def hp(self, **kw):
-        return self.lib.hparams(precision=self.prec, **kw)
-
-    def step(self, hp, q=None, n=None, targets=None):
-        qd = self.qd if q is None else queries_dev(q)
-        self.lib.train_step(self.m, self.state, qd, self.n if n is None else n,
-                            self.td if targets is None else targets, hp, self.ws)
-
-    def get(self, name):
-        import torch
-        torch.cuda.synchronize()
-        return getattr(self.state, name).cpu().numpy().astype(np.float64)
-
-
-def _ohp(hp):
-    return dict(lr_latent=hp.lr_latent, lr_mlp=hp.lr_mlp, beta1=hp.beta1, beta2=hp.beta2, eps=hp.eps,
-                seed=hp.noise_seed, step=hp.step, noise=bool(hp.noise), freeze_latents=bool(hp.freeze_latents))
-
-
-def _grad_groups(g, gp):
-    W1, b1, W2, b2, W3, b3 = O.mlp_split(gp, g.K, g.Hd, g.C)
-    return dict(W1=W1, b1=b1, W2=W2, b2=b2, W3=W3, b3=b3)
-
-
-def _check_grads(run, hp, tol=1e-3):
-    g = run.g
-    lat_fwd = run.ostate["latents"]
-    if hp.noise and not hp.freeze_latents:
-        lat_fwd = lat_fwd + O.noise_values(g, hp.noise_seed, hp.step)
-    L, gp, gl, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, run.targets)
-    b1 = hp.beta1
-    gp_gpu = run.get("mlp_m") / (1 - b1)
-    gl_gpu = run.get("lat_m") / (1 - b1)
-    loss = run.get("loss")[0]
-    errs = {k: rel_err(_grad_groups(g, gp_gpu)[k], v) for k, v in _grad_groups(g, gp).items()}
-    errs["latents"] = rel_err(gl_gpu, gl)
-    # the dense latent-gradient buffer holds the same gradient (every entry written)
-    errs["lat_grad"] = rel_err(run.get("lat_grad"), gl)
-    print("gradient rel errors:", {k: f"{v:.2e}" for k, v in errs.items()}, f"loss {loss:.6e} vs {L:.6e}")
-    assert abs(loss - L) <= 1e-5 * abs(L)
-    for k, v in errs.items():
-        assert v <= tol, (k, v)
-    return L, gp, gl
 
 
 CONFIGS = {  # W, C, c0, c1, b0, b1, hidden, mips, n, lod
@@ -259,7 +185,7 @@ def test_gradients_fp16(lib, name, lod_input):
     derrs = {"mlp": rel_err(gp_gpu, gp_d), "latents": rel_err(gl_gpu, gl_d)}
     print("fp16 vs decision-matched oracle:", {k: f"{v:.2e}" for k, v in derrs.items()})
     for v in derrs.values():
-        assert v <= 5e-3
+        assert v <= 1e-3
 
 
 @pytest.mark.parametrize("offset", [0.0, 64.0])
@@ -281,7 +207,7 @@ def test_gradients_fp16_fixed_point_range(lib, offset):
     err = rel_err(run.get("lat_grad") / run.get("loss_scale")[0], gl_d)
     perr = rel_err(run.get("mlp_m") / (1 - hp.beta1), gp_d)
     print(f"target offset {offset}: latent gradient rel err {err:.2e}, MLP gradient rel err {perr:.2e}")
-    assert err <= 5e-3 and perr <= 5e-3
+    assert err <= 1e-3 and perr <= 1e-3
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
@@ -305,6 +231,13 @@ def test_full_size_gradients(lib, prec):
     assert abs(loss - L) <= (1e-5 if prec == "f32" else 2e-3) * L
     for k, v in errs.items():
         assert v <= tol, (k, v)
+    if prec == "f16":  # with the ReLU decisions taken in FP16: rounding error only
+        _, gp_d, gl_d, _ = O.loss_and_grads(g, lat_fwd, run.ostate["mlp"], run.q, run.targets, decisions="fp16")
+        derrs = {"mlp": rel_err(run.get("mlp_m") / (1 - hp.beta1), gp_d),
+                 "lat_grad": rel_err(run.get("lat_grad") / scale, gl_d)}
+        print("full-size fp16 vs decision-matched oracle:", {k: f"{v:.2e}" for k, v in derrs.items()})
+        for v in derrs.values():
+            assert v <= 1e-3
 
 
 @pytest.mark.parametrize("W,side,crops", [(2048, 256, 8), (64, 32, 3), (256, 100, 2)])

@@ -154,3 +154,37 @@ def test_decision_matched_mode_is_the_fp64_gradient_under_those_decisions():
     t = torch.tensor(O._targets_at(g, tgt, rec))
     ((y - t) ** 2).mean().backward()
     assert np.allclose(gp, tp.grad.numpy(), rtol=1e-10, atol=1e-14)
+
+
+def test_fp16_decisions_hand_built_case():
+    """ReLU decisions taken the FP16 way, pinned on a network built by hand so that each
+    rounding point flips a decision on its own (K = 2 inputs, 3 hidden units, 1 output):
+      inputs rounded:      unit 1/0 is x0 - x1; x0 = 1 + 2^-11 rounds (half to even) to 1,
+                           so z = 2^-11 > 0 in float64 but 0 in FP16;
+      weights rounded:     unit 1/1 is (1 + 2^-11) x0 - x1; at x = (1, 1) z = 2^-11 in
+                           float64, 0 in FP16;
+      activations rounded: unit 1/2 is the bias 1 + 2^-11 (biases stay FP32), so h = 1 + 2^-11
+                           in float64 and 1 in FP16; unit 2/0 is h_2 - 1: 2^-11 > 0 vs 0;
+      bias kept in FP32:   unit 2/1 is the bias 2^-26, which FP16 would flush to 0: stays on;
+                           unit 2/2 is the bias -2^-26: off.
+    The decisions are written out by hand, together with the float64 ones they differ from."""
+    K, Hd, C = 2, 3, 1
+    e = 2.0 ** -11
+    W1 = np.array([[1.0, 1.0 + e, 0.0],
+                   [-1.0, -1.0, 0.0]])
+    b1 = np.array([0.0, 0.0, 1.0 + e])
+    W2 = np.zeros((Hd, Hd))
+    W2[2, 0] = 1.0
+    b2 = np.array([-1.0, 2.0 ** -26, -2.0 ** -26])
+    W3 = np.ones((Hd, C))
+    b3 = np.zeros(C)
+    params = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])
+    x = np.array([[1.0 + e, 1.0],
+                  [1.0, 1.0]])
+    m1, m2 = O.relu_decisions_fp16(params, x, K, Hd, C)
+    assert m1.tolist() == [[False, False, True], [False, False, True]]
+    assert m2.tolist() == [[False, True, False], [False, True, False]]
+    # the float64 decisions of the same network (what an unrounded evaluation gives)
+    _, (z1, _, z2, _) = O.mlp_forward(params, x, K, Hd, C)
+    assert (z1 > 0).tolist() == [[True, True, True], [False, True, True]]
+    assert (z2 > 0).tolist() == [[True, True, False], [True, True, False]]

@@ -504,6 +504,20 @@ __device__ inline int row_sum16i(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);
   return v;
 }
+// The same for 64-bit integers: both halves rotated, then a 64-bit add.
+template <int CTRL>
+__device__ inline long long dpp_row64(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ inline long long row_sum16i(long long v) {
+  v += dpp_row64<0x121>(v);
+  v += dpp_row64<0x122>(v);
+  v += dpp_row64<0x124>(v);
+  v += dpp_row64<0x128>(v);
+  return v;
+}
 
 // The three positional-encoding values of lane group g (slots 3g..3g+2 of the 12).
 __device__ inline void pe_values(const float* pe_lds, int ix, int iy, int g, float out[3]) {

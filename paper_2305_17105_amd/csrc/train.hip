@@ -36,7 +36,7 @@ namespace ntc {
 constexpr int kChunkDefault = 256;  // samples per work item unless tuned (tiles of at most 16 x 16)
 constexpr int kBinBlockSamples = 1024;
 constexpr int kBinThreads = 1024;  // threads of a binning block (one sample each)
-constexpr int kMaxBins = 12288;   // LDS histogram capacity of the binning kernels
+constexpr int kMaxBins = 24576;   // LDS histogram capacity of the binning kernels (96 KiB)
 constexpr int kSortedCells = 4096; // levels with at most this many G0 cells are sorted by anchor cell
 
 struct TrainArgs {
@@ -180,15 +180,13 @@ struct TrainCfg {
                                     OFF_BUF + buf_bytes(TR2) + region(32) * 4 <= kLdsCap;
   static constexpr int TR = ONE_PHASE ? TR1 : TWO_PHASE ? TR2 : SPLIT1 ? TR3S : TR3;
   static constexpr int OFF_REG = OFF_BUF + buf_bytes(TR);
-  // Owned-latent accumulators.  FP16 kernels (FIXED): 32-bit fixed point (integer LDS
-  // adds run 3x faster than FP64 ones and 25x faster than FP32 ones on this GPU, the sums
-  // do not depend on the order of the adds, and at 4 bytes a latent a 32 x 32 tile fits);
-  // a work item with a contribution beyond the fixed-point range is summed again in FP32.
-  // FP32 kernels: FP64 accumulators when a 16 x 16 tile of them fits, else FP32.
-  static constexpr bool FIXED = sizeof(T) == 2;
-  static constexpr bool REG64 = !FIXED && OFF_REG + region(16) * 8 <= kLdsCap;
-  using RegT = typename std::conditional<REG64, double, float>::type;
-  static constexpr int RB = REG64 ? 8 : 4;
+  // Owned-latent accumulators: fixed point, so a work item's sums do not depend on the
+  // order of its adds (integer LDS adds also run 3x faster than FP64 ones and 25x faster
+  // than FP32 ones on this GPU).  FP16 kernels: 32-bit (at 4 bytes a latent a 32 x 32 tile
+  // fits); FP32 kernels: 64-bit with a finer quantum.  A work item with a contribution
+  // beyond the fixed-point range is summed again in FP32.
+  using AccI = typename std::conditional<sizeof(T) == 2, int, long long>::type;
+  static constexpr int RB = (int)sizeof(AccI);
   // largest tile side whose owned-latent gradient fits next to the rest
   static constexpr int TMAX = OFF_REG + region(32) * RB <= kLdsCap ? 32 : OFF_REG + region(16) * RB <= kLdsCap ? 16 : 8;
   static constexpr int LDS = OFF_REG + region(TMAX) * RB;
@@ -215,12 +213,11 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   long long* tab = reinterpret_cast<long long*>(smem + Cfg::OFF_TAB);
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
-  using RegT = typename Cfg::RegT;
-  constexpr bool FIXED = Cfg::FIXED;
-  RegT* reg = reinterpret_cast<RegT*>(smem + Cfg::OFF_REG);
-  int* ireg = reinterpret_cast<int*>(smem + Cfg::OFF_REG);      // FIXED: fixed-point sums
-  float* freg = reinterpret_cast<float*>(smem + Cfg::OFF_REG);  // FIXED: FP32 sums of a summed-again item
-  bool lost = false;  // FIXED: a contribution of this item left the fixed-point range
+  using AccI = typename Cfg::AccI;
+  constexpr bool WIDE = sizeof(AccI) == 8;
+  AccI* ireg = reinterpret_cast<AccI*>(smem + Cfg::OFF_REG);    // fixed-point sums
+  float* freg = reinterpret_cast<float*>(smem + Cfg::OFF_REG);  // FP32 sums of a summed-again item
+  bool lost = false;  // a contribution of this item left the fixed-point range
   const int tid = threadIdx.x;
   for (int i = tid; i < Cfg::WB / 16; i += NTHR)
     reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.wpack)[i];
@@ -259,40 +256,48 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   float db1 = 0.f, db2 = 0.f, db3 = 0.f, loss = 0.f;
 
   const int chunk_n = a.tg.chunk;
-  // FIXED: the quantum of the fixed-point sums is 2^-16 of the natural unit U of the
-  // output delta (2 x loss scale / (samples x channels) for the loss; 1 for a caller's
-  // delta, which comes scaled to O(1)), rounded to a power of two, so the range covers the
-  // same multiples of U whatever the batch and the loss scale: 16 U and more at 512
-  // samples per work item, a rounding error of at most 2^-17 U per contribution.  A
-  // latent takes at most 4 adds per sample of a work item (a footprint's taps may
-  // coincide at the border), so adds of at most qlim units cannot overflow.
+  // The quantum of the fixed-point sums is 2^-16 (FP16 kernels) or 2^-32 (FP32 kernels)
+  // of the natural unit U of the output delta (2 x loss scale / (samples x channels) for
+  // the loss; 1 for a caller's delta, which comes scaled to O(1)), rounded to a power of
+  // two, so the range covers the same multiples of U whatever the batch and the loss
+  // scale (FP16: 16 U and more at 512 samples per work item, a rounding error of at most
+  // 2^-17 U per contribution).  A latent takes at most 4 adds per sample of a work item
+  // (a footprint's taps may coincide at the border), so adds of at most qlim units
+  // cannot overflow.
+  constexpr int kQBits = WIDE ? 32 : 16;
   float fixq = 0x1p24f;
   {
     const float U = a.dout ? 1.f : 2.f * a.inv_nc * scale;
     int ex = 0;
-    if (U > 0.f && U < 0x1p100f) frexpf(U, &ex);
-    fixq = ldexpf(1.f, 16 - max(-80, min(80, ex)));
+    if (U > 0.f && U < 0x1p90f) frexpf(U, &ex);
+    fixq = ldexpf(1.f, kQBits - max(-80, min(80, ex)));
   }
   const float fixinv = 1.f / fixq;  // exact: a power of two
-  const float qlim = fminf((float)(0x7fffffff / (4 * chunk_n)), 0x1p22f);
+  const float qlim = WIDE ? fminf(0x1p62f / (float)(4 * chunk_n), 0x1p50f)
+                          : fminf((float)(0x7fffffff / (4 * chunk_n)), 0x1p22f);
   const float xlim = qlim * fixinv;  // the largest contribution kept in fixed point (exact)
-  // FIXED, first pass: a contribution x clamped to the range and rounded to the nearest
-  // quantum (adding 1.5 * 2^23 leaves the integer in the low mantissa bits); a clamped or
-  // non-finite x marks the item for the FP32 pass.  Every contribution is rounded on its
-  // own, so the integer sums do not depend on how samples are grouped or ordered.
-  auto quant = [&](float x) -> int {
+  // First pass: a contribution x clamped to the range and rounded to the nearest quantum
+  // (adding 1.5 * 2^23, or 1.5 * 2^52 in FP64, leaves the integer in the low mantissa
+  // bits); a clamped or non-finite x marks the item for the FP32 pass.  Every
+  // contribution is rounded on its own, so the integer sums do not depend on how samples
+  // are grouped or ordered.
+  auto quant = [&](float x) -> AccI {
     const float xc = __builtin_amdgcn_fmed3f(x, -xlim, xlim);
     lost |= x != xc;
-    return __float_as_int(fmaf(xc, fixq, 0x1.8p23f)) - 0x4B400000;
+    if constexpr (WIDE) {
+      return (AccI)(__double_as_longlong(fma((double)xc, (double)fixq, 0x1.8p52)) - 0x4338000000000000ll);
+    } else {
+      return __float_as_int(fmaf(xc, fixq, 0x1.8p23f)) - 0x4B400000;
+    }
+  };
+  auto add_fixed = [&](int k, AccI v) {
+    if constexpr (WIDE) atomicAdd(reinterpret_cast<unsigned long long*>(ireg + k), (unsigned long long)v);
+    else atomicAdd(ireg + k, v);
   };
   // One contribution x to owned latent k of the region.
   auto acc_lat = [&](int k, float x, bool refine) {
-    if constexpr (FIXED) {
-      if (refine) atomicAdd(freg + k, x);
-      else atomicAdd(ireg + k, quant(x));
-    } else {
-      atomicAdd(reg + k, (RegT)x);
-    }
+    if (refine) atomicAdd(freg + k, x);
+    else add_fixed(k, quant(x));
   };
   const int nitems = item1 >= 0 ? item1 : binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
   for (int item = item0; item < nitems; item += istride) {
@@ -350,11 +355,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     const bool refine = pass == 1;
     refined = refine;
     if (binned) {
-      if constexpr (FIXED) {
-        for (int k = tid; k < RG; k += NTHR) ireg[k] = 0;
-      } else {
-        for (int k = tid; k < RG; k += NTHR) reg[k] = (RegT)0;
-      }
+      for (int k = tid; k < RG; k += NTHR) ireg[k] = (AccI)0;
     }
     __syncthreads();
     float nu, nv;
@@ -499,13 +500,13 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
           const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
 #pragma unroll
           for (int t = 0; t < C0; ++t) {
-            if (FIXED && !refine) {
-              const int qv = own0 ? quant(dx[t]) : 0;
-              const int sq = row_sum16i(qv);
+            if (!refine) {
+              const AccI qv = own0 ? quant(dx[t]) : (AccI)0;
+              const AccI sq = row_sum16i(qv);
               if (uni) {
-                if (rr == 0 && rk >= 0) atomicAdd(ireg + dst0 + t, sq);
+                if (rr == 0 && rk >= 0) add_fixed(dst0 + t, sq);
               } else if (own0) {
-                atomicAdd(ireg + dst0 + t, qv);
+                add_fixed(dst0 + t, qv);
               }
               continue;
             }
@@ -534,14 +535,14 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
             for (int i = 0; i < IS::n1max; ++i) {
               const int ch = g + 4 * i;
               const float v1 = own1 ? f.g1_w[k] * dx[C0 + i] : 0.f;
-              if (FIXED && !refine) {
-                const int qv = own1 ? quant(v1) : 0;
-                const int sq = row_sum16i(qv);
+              if (!refine) {
+                const AccI qv = own1 ? quant(v1) : (AccI)0;
+                const AccI sq = row_sum16i(qv);
                 if (ch < C1) {
                   if (uni) {
-                    if (rr == 0 && rk >= 0) atomicAdd(ireg + dst1 + ch, sq);
+                    if (rr == 0 && rk >= 0) add_fixed(dst1 + ch, sq);
                   } else if (own1) {
-                    atomicAdd(ireg + dst1 + ch, qv);
+                    add_fixed(dst1 + ch, qv);
                   }
                 }
                 continue;
@@ -696,14 +697,12 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       }
     }
 
-    if constexpr (FIXED) {
-      if (binned && !refine && __syncthreads_or(lost)) {
-        lost = false;
-        continue;
-      }
-      // the refine pass has no staging barriers: its adds must land before the write-out
-      if (refine) __syncthreads();
+    if (binned && !refine && __syncthreads_or(lost)) {
+      lost = false;
+      continue;
     }
+    // the refine pass has no staging barriers: its adds must land before the write-out
+    if (refine) __syncthreads();
     break;
     }
 
@@ -724,8 +723,8 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       };
       for (int k = tid; k < RG; k += NTHR) {
         float v;
-        if constexpr (FIXED) v = refined ? freg[k] : (float)ireg[k] * fixinv;
-        else v = (float)reg[k];
+        if constexpr (WIDE) v = refined ? freg[k] : (float)((double)ireg[k] * (double)fixinv);
+        else v = refined ? freg[k] : (float)ireg[k] * fixinv;
         dst[dst_index(k)] = v * osc;
       }
       __syncthreads();
@@ -813,7 +812,24 @@ struct BinArgs {
   int4* list;
 };
 
+// Bins of one sample: the sort bins of the tiles its footprint touches (at most 4,
+// all different), -1 in the unused entries.
+__device__ inline void sample_bin_list(const DevMat& m, const TileGeom& tg, const ntc_query& qq, int (&bk)[4]) {
+  const Footprint f = locate(m, qq.u, qq.v, qq.lod, 0);
+  const SampleBins sb = sample_bins(f, tg);
+  const bool two_x = sb.tx1 > sb.tx0, two_y = sb.ty1 > sb.ty0;  // each range spans at most two tiles
+  bk[0] = sort_bin(tg, sb.j, sb.tx0, sb.ty0, f.ax, f.ay);
+  bk[1] = two_x ? sort_bin(tg, sb.j, sb.tx1, sb.ty0, f.ax, f.ay) : -1;
+  bk[2] = two_y ? sort_bin(tg, sb.j, sb.tx0, sb.ty1, f.ax, f.ay) : -1;
+  bk[3] = two_x && two_y ? sort_bin(tg, sb.j, sb.tx1, sb.ty1, f.ax, f.ay) : -1;
+}
+
 // bi: the binning block (of a.nbb) this block is; q: the material's queries.
+// Counting pass (!SCATTER): per-block bin histograms.  Scatter pass: list positions in a
+// fixed order, so a bin lists its samples by increasing sample index whatever the
+// timing of the run: a wavefront ranks its entries by matching equal bins across its
+// lanes (a sample has at most one entry per bin), then the wavefronts of the block
+// claim their runs of each bin in wavefront order.
 template <bool SCATTER>
 __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, const BinArgs& a,
                                          const ntc_query* __restrict__ q, int bi) {
@@ -824,33 +840,91 @@ __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, co
   __syncthreads();
   const long long s0 = (long long)bi * a.per_block;
   const long long s1 = min(a.n, s0 + a.per_block);
-  constexpr int U = 4;  // queries loaded together per thread and round
-  for (long long s = s0 + threadIdx.x; s < s1; s += U * blockDim.x) {
-    ntc_query qq[U];
+  if constexpr (!SCATTER) {
+    constexpr int U = 4;  // queries loaded together per thread and round
+    for (long long s = s0 + threadIdx.x; s < s1; s += U * blockDim.x) {
+      ntc_query qq[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const long long sk = s + (long long)k * blockDim.x;
-      if (sk < s1) qq[k] = q[sk];
-    }
+      for (int k = 0; k < U; ++k) {
+        const long long sk = s + (long long)k * blockDim.x;
+        if (sk < s1) qq[k] = q[sk];
+      }
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const long long sk = s + (long long)k * blockDim.x;
-      if (sk >= s1) break;
-      const Footprint f = locate(m, qq[k].u, qq[k].v, qq[k].lod, 0);
-      const SampleBins sb = sample_bins(f, tg);
-      for (int ty = sb.ty0; ty <= sb.ty1; ++ty)
-        for (int tx = sb.tx0; tx <= sb.tx1; ++tx) {
-          const int b = sort_bin(tg, sb.j, tx, ty, f.ax, f.ay);
-          if (SCATTER)
-            a.list[atomicAdd(&hist[b], 1)] =
-                make_int4(__float_as_int(qq[k].u), __float_as_int(qq[k].v), qq[k].lod, (int)sk);
-          else atomicAdd(&hist[b], 1);
-        }
+      for (int k = 0; k < U; ++k) {
+        const long long sk = s + (long long)k * blockDim.x;
+        if (sk >= s1) break;
+        int bk[4];
+        sample_bin_list(m, tg, qq[k], bk);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (bk[e] >= 0) atomicAdd(&hist[bk[e]], 1);
+      }
     }
-  }
-  if (!SCATTER) {
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)b * a.nbb + bi] = hist[b];
+  } else {
+    constexpr int kWaves = kBinThreads / 64, kUniq = 4 * 64;
+    __shared__ int ukey[kWaves][kUniq];  // a wavefront's distinct bins, in match order
+    __shared__ int ubase[kWaves][kUniq]; // their entry counts, then their first list positions
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long long r0 = s0; r0 < s1; r0 += blockDim.x) {
+      const long long sk = r0 + threadIdx.x;
+      int bk[4] = {-1, -1, -1, -1};
+      ntc_query qq{0.f, 0.f, 0};
+      if (sk < s1) {
+        qq = q[sk];
+        sample_bin_list(m, tg, qq, bk);
+      }
+      // ranks within the wavefront: one round per distinct bin (wavefront-uniform loop)
+      unsigned long long pend[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pend[e] = __ballot(bk[e] >= 0);
+      int rank[4] = {0, 0, 0, 0}, uid[4] = {0, 0, 0, 0};
+      int nu = 0;
+      while (pend[0] | pend[1] | pend[2] | pend[3]) {
+        const int es = pend[0] ? 0 : pend[1] ? 1 : pend[2] ? 2 : 3;
+        const int src = __builtin_ctzll(pend[es]);
+        const int key = __shfl(es == 0 ? bk[0] : es == 1 ? bk[1] : es == 2 ? bk[2] : bk[3], src);
+        unsigned long long all = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned long long me = __ballot(bk[e] == key);
+          all |= me;
+          pend[e] &= ~me;
+        }
+        const int below_n = __popcll(all & below);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (bk[e] == key) {
+            rank[e] = below_n;
+            uid[e] = nu;
+          }
+        if (lane == 0) {
+          ukey[wave][nu] = key;
+          ubase[wave][nu] = __popcll(all);
+        }
+        ++nu;
+      }
+      __syncthreads();
+      // runs of each bin claimed wavefront after wavefront (distinct keys within one)
+      for (int w = 0; w < nwaves; ++w) {
+        if (wave == w) {
+          for (int u = lane; u < nu; u += 64) {
+            const int key = ukey[w][u], b = hist[key];
+            hist[key] = b + ubase[w][u];
+            ubase[w][u] = b;
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (bk[e] >= 0)
+          a.list[ubase[wave][uid[e]] + rank[e]] =
+              make_int4(__float_as_int(qq.u), __float_as_int(qq.v), qq.lod, (int)sk);
+      __syncthreads();  // ukey and ubase are reused by the next round
+    }
   }
 }
 

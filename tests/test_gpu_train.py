@@ -6,7 +6,7 @@ the parameters unchanged and sets the first Adam moment to (1 - beta1) * gradien
 import numpy as np
 import pytest
 
-from _helpers import queries_dev, rel_err, to_dev
+from _helpers import geometry, queries_dev, rel_err, to_dev
 from _trainrun import Run, check_grads as _check_grads, grad_groups as _grad_groups, ohp as _ohp
 from oracle import ntc_oracle as O
 from paper_2305_17105_amd import synth
@@ -253,3 +253,59 @@ def test_crop_queries_bit_exact(lib, W, side, crops):
         torch.cuda.synchronize()
         want = O.crop_queries(g, 77, step, crops=crops, side=side, fraction=0.3)
         assert np.array_equal(out.cpu().numpy(), want.view(np.uint8)), step
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_step_is_deterministic(lib, prec):
+    """Two runs of the same three steps from the same state are bit-identical: samples
+    are binned in sample order (not in the order LDS atomics arrive), latent gradients
+    are fixed-point sums, weight gradients and split-tile partials are reduced in a fixed
+    order.  The 256^2 material with 65,536 samples per step splits its coarse-level
+    tiles over several work items and sorts its small levels by anchor cell."""
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    W, C, n = 256, 12, 65536
+    m = lib.material_init(W, W, C, C, C, 4, 4, 64)
+    raw = synth.uniform_latents(31, int(m.latent_count))
+    mlp = synth.xavier_mlp(31, int(m.input_width), 64, C)
+    _, tflat = synth.target_chain(31, 0, W, W, C, int(m.num_mips))
+    q = queries_dev(synth.random_queries(32, n, int(m.num_mips)))
+    td = to_dev(tflat)
+    runs = []
+    for _ in range(2):
+        st = lib.TrainState(m, raw, to_dev(mlp), P)
+        ws = torch.zeros(lib.train_workspace_bytes(m, n, P), dtype=torch.uint8, device="cuda")
+        for s in range(3):
+            hp = lib.hparams(precision=P, step=s, lr_latent=0.01, lr_mlp=0.005, seed=9)
+            if s == 0:
+                lib.train_prepare(m, st, hp)
+            lib.train_step(m, st, q, n, td, hp, ws)
+        torch.cuda.synchronize()
+        runs.append({k: getattr(st, k).clone() for k in ("latents", "latents_fwd", "lat_grad", "mlp", "mlp_m",
+                                                         "mlp_v", "lat_m", "lat_v", "loss")})
+    for k, v in runs[0].items():
+        assert torch.equal(runs[1][k], v), (prec, k)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_backward_is_deterministic(lib, prec):
+    """The differentiation path's backward, called twice on the same inputs, returns
+    bit-identical gradients."""
+    import torch
+    P = lib.F32 if prec == "f32" else lib.F16
+    W, C, n = 256, 12, 40000
+    m = lib.material_init(W, W, C, C, C, 4, 4, 64)
+    lat = to_dev(synth.uniform_latents(41, int(m.latent_count)) * 0.4)
+    mlp = to_dev(synth.xavier_mlp(41, int(m.input_width), 64, C))
+    tp = torch.zeros(lib.train_packed_bytes(m, P), dtype=torch.uint8, device="cuda")
+    lib.pack_mlp_train(m, mlp, P, tp)
+    q = queries_dev(synth.random_queries(42, n, int(m.num_mips)))
+    dout = to_dev(np.random.default_rng(43).standard_normal(n * C).astype(np.float32) * 1e-3)
+    ws = torch.zeros(lib.backward_workspace_bytes(m, n, P), dtype=torch.uint8, device="cuda")
+    res = []
+    for _ in range(2):
+        gl, gm = torch.empty_like(lat), torch.empty_like(mlp)
+        lib.backward(m, lat, mlp, tp, P, q, n, dout, 0.0, gl, gm, ws)
+        torch.cuda.synchronize()
+        res.append((gl.clone(), gm.clone()))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])

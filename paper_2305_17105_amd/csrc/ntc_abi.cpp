@@ -677,6 +677,49 @@ ntc_status ntc_train_step(const ntc_material* m, const ntc_train_state* s, const
   return ntc_train_update(m, s, n, hp, workspace, ws_bytes, stream);
 }
 
+// ------------------------------------------------------------------ training without a workspace
+// The step's workspace as a file-scope device array: each GPU the library runs on holds
+// one copy until the process ends.  In host code `scratch` names a host-side stand-in;
+// its device address on the current device comes from hipGetSymbolAddress, taken once
+// per device on the first call there and kept.
+static __device__ __align__(256) unsigned char scratch[NTC_NOALLOC_SCRATCH_BYTES];
+
+static ntc_status scratch_on_current_device(void** out) {
+  static std::mutex mu;
+  static void* ptr[64] = {nullptr};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "ntc_train_step_noalloc (hipGetDevice)");
+  if (dev < 0 || dev >= 64) return fail(NTC_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                  "ntc_train_step_noalloc (hipGetSymbolAddress)");
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return NTC_OK;
+}
+
+ntc_status ntc_train_step_noalloc(const ntc_material* m, const ntc_train_state* s, const ntc_query* q, int64_t n,
+                                  const float* targets, const ntc_hparams* hp, void* stream) {
+  ntc_status st = check_train(m, s, hp, n);
+  if (st != NTC_OK) return st;
+  if (!q || !targets) return fail(NTC_E_INVALID, "NULL queries or targets");
+  const TrainPlan plan = train_plan(*m, hp->precision == NTC_F16, n);
+  if (!plan.supported_bins) return fail(NTC_E_UNSUPPORTED, "too many latent tiles for this material");
+  if (plan.total > (size_t)NTC_NOALLOC_SCRATCH_BYTES)
+    return fail(NTC_E_WORKSPACE, "this step needs " + std::to_string(plan.total) +
+                                     " bytes of scratch, more than the static array's " +
+                                     std::to_string((size_t)NTC_NOALLOC_SCRATCH_BYTES) +
+                                     " (call ntc_train_step with a workspace)");
+  void* ws = nullptr;
+  if ((st = scratch_on_current_device(&ws)) != NTC_OK) return st;
+  return ntc_train_step(m, s, q, n, targets, hp, ws, (size_t)NTC_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 ntc_status ntc_crop_queries(const ntc_material* m, uint64_t seed, int32_t step, int32_t crops, int32_t side,
                             double uniform_fraction, ntc_query* out, void* stream) {
   ntc_status st = check_material(m);

@@ -83,6 +83,8 @@ _sig = {
     "ntc_train_prepare": (C.c_int, [_P(Material), _P(TrainStateC), _P(HParams), C.c_void_p]),
     "ntc_train_step": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p, _P(HParams),
                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ntc_train_step_noalloc": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p,
+                                         _P(HParams), C.c_void_p]),
     "ntc_train_gradients": (C.c_int, [_P(Material), _P(TrainStateC), C.c_void_p, C.c_int64, C.c_void_p,
                                       _P(HParams), C.c_void_p, C.c_size_t, C.c_void_p]),
     "ntc_train_update": (C.c_int, [_P(Material), _P(TrainStateC), C.c_int64, _P(HParams), C.c_void_p, C.c_size_t,
@@ -224,6 +226,15 @@ def train_step(m: Material, state: "TrainState", queries, n, targets, hp: HParam
     _check(_lib.ntc_train_step(C.byref(m), C.byref(state.c), _ptr(queries), n, _ptr(targets), C.byref(hp),
                                _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
            "ntc_train_step")
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20  # NTC_NOALLOC_SCRATCH_BYTES
+
+
+def train_step_noalloc(m: Material, state: "TrainState", queries, n, targets, hp: HParams, stream=None):
+    """ntc_train_step with the library's static scratch array as its workspace."""
+    _check(_lib.ntc_train_step_noalloc(C.byref(m), C.byref(state.c), _ptr(queries), n, _ptr(targets), C.byref(hp),
+                                       _stream(stream)), "ntc_train_step_noalloc")
 
 
 def train_gradients(m: Material, state: "TrainState", queries, n, targets, hp: HParams, workspace, stream=None):

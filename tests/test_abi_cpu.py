@@ -182,3 +182,23 @@ def test_training_sample_count_limit(ntc):
                                   2 ** 40, None)
         assert r == ntc.E_UNSUPPORTED
         assert "2^31" in ntc._lib.ntc_last_error().decode()
+
+
+def test_noalloc_step_rejects_steps_beyond_its_scratch(ntc):
+    """ntc_train_step_noalloc returns NTC_E_WORKSPACE, before anything touches a device,
+    when the step's workspace exceeds the static scratch array (a 2^20-sample step on a
+    2048^2 x 12 material), and validates like ntc_train_step."""
+    import ctypes as C
+    assert ntc.NOALLOC_SCRATCH_BYTES == 128 << 20
+    m = ntc.material_init(2048, 2048, 12, 12, 12, 4, 4, 64)
+    fake = C.c_void_p(4096)  # aligned, never dereferenced: validation fails first
+    st = ntc.TrainStateC(*([fake] * len(ntc.TrainStateC._fields_)))
+    for prec in (ntc.F32, ntc.F16):
+        hp = ntc.hparams(precision=prec)
+        r = ntc._lib.ntc_train_step_noalloc(C.byref(m), C.byref(st), fake, 2 ** 20, fake, C.byref(hp), None)
+        assert r == ntc.E_WORKSPACE, r
+        assert "static array" in ntc._lib.ntc_last_error().decode()
+        r = ntc._lib.ntc_train_step_noalloc(C.byref(m), C.byref(st), None, 4096, fake, C.byref(hp), None)
+        assert r == ntc.E_INVALID
+        r = ntc._lib.ntc_train_step_noalloc(C.byref(m), C.byref(st), fake, 0, fake, C.byref(hp), None)
+        assert r == ntc.E_INVALID

@@ -87,7 +87,10 @@ typedef struct {
   int32_t width, height;   /* powers of two */
   int32_t channels;        /* C, 1..16 */
   int32_t num_mips;        /* M; 0 selects the full chain down to 1x1 */
-  int32_t c0, c1;          /* latent channels of G0 and G1 */
+  int32_t c0, c1;          /* latent channels of G0 (1..16) and G1 (1..32); kernels exist for
+                              c0 = c1 = C in {8, 10, 12, 16} and for Table 3's profiles on
+                              C = 9: (c0 x b0, c1 x b1) = (8x2, 12x4), (12x4, 20x4),
+                              (12x2, 10x4), (16x4, 12x4) (ntc_shape_supported) */
   int32_t b0, b1;          /* bits per latent: 1, 2, 4 or 8 */
   int32_t grid_shift;      /* G0 at level 0 is the texture size >> grid_shift (2: W/4) */
   int32_t hidden;          /* Hd: 32 or 64 */

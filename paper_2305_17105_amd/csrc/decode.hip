@@ -112,7 +112,8 @@ hipError_t launch_decode_fp8(const ntc_material& m, const uint8_t* packed, const
 // forward part leads it, and the biases of the canonical parameters; shapes as for training.
 #define NTC_FORWARD_SHAPES(X)                                                          \
   X(8, 8, 8, 64) X(10, 10, 10, 64) X(12, 12, 12, 64) X(16, 16, 16, 64) X(8, 8, 8, 32) \
-  X(10, 10, 10, 32) X(12, 12, 12, 32) X(16, 16, 16, 32)
+  X(10, 10, 10, 32) X(12, 12, 12, 32) X(16, 16, 16, 32)                              \
+  X(8, 12, 9, 64) X(12, 20, 9, 64) X(12, 10, 9, 64) X(16, 12, 9, 64)
 
 hipError_t launch_forward(const ntc_material& m, const float* latents, const float* mlp, const void* wpack, bool f16,
                           const ntc_query* q, long long n, float* out, hipStream_t s) {

@@ -12,11 +12,13 @@
 
 namespace ntc {
 
-// Shapes (c0, c1, channels, hidden, b0, b1) with decode kernels.
+// Shapes (c0, c1, channels, hidden, b0, b1) with decode kernels: the configurations' shapes
+// and Table 3's four profiles on a 9-channel texture set (NTC 0.2, 0.5, 1.0, 2.25).
 #define NTC_DECODE_SHAPES(X)                                                                     \
   X(8, 8, 8, 64, 4, 4) X(10, 10, 10, 64, 4, 4) X(12, 12, 12, 64, 4, 4) X(16, 16, 16, 64, 4, 4)  \
   X(8, 8, 8, 32, 4, 4) X(10, 10, 10, 32, 4, 4) X(12, 12, 12, 32, 4, 4) X(16, 16, 16, 32, 4, 4)  \
-  X(16, 16, 16, 64, 2, 4)
+  X(16, 16, 16, 64, 2, 4)                                                                        \
+  X(8, 12, 9, 64, 2, 4) X(12, 20, 9, 64, 4, 4) X(12, 10, 9, 64, 2, 4) X(16, 12, 9, 64, 4, 4)
 
 // Input layout of the decoder for a material: packed codes in FP16 use the paired
 // layout where it applies; everything else (and the forward of the differentiation

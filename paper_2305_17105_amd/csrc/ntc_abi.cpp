@@ -136,7 +136,8 @@ ntc_status ntc_material_init(ntc_material* m) {
   if (!pow2(m->width) || !pow2(m->height) || m->width > 32768 || m->height > 32768)
     return fail(NTC_E_INVALID, "width and height must be powers of two <= 32768");
   if (m->channels < 1 || m->channels > 16) return fail(NTC_E_INVALID, "channels must be in 1..16");
-  if (m->c0 < 1 || m->c0 > 16 || m->c1 < 1 || m->c1 > 16) return fail(NTC_E_INVALID, "c0, c1 must be in 1..16");
+  if (m->c0 < 1 || m->c0 > 16 || m->c1 < 1 || m->c1 > 32)
+    return fail(NTC_E_INVALID, "c0 must be in 1..16 and c1 in 1..32");
   auto okbits = [](int b) { return b == 1 || b == 2 || b == 4 || b == 8; };
   if (!okbits(m->b0) || !okbits(m->b1)) return fail(NTC_E_INVALID, "b0, b1 must be 1, 2, 4 or 8");
   if (m->grid_shift < 0 || m->grid_shift > 8) return fail(NTC_E_INVALID, "grid_shift must be in 0..8");

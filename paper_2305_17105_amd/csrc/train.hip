@@ -827,9 +827,7 @@ __device__ inline void sample_bin_list(const DevMat& m, const TileGeom& tg, cons
 // bi: the binning block (of a.nbb) this block is; q: the material's queries.
 // Counting pass (!SCATTER): per-block bin histograms.  Scatter pass: list positions in a
 // fixed order, so a bin lists its samples by increasing sample index whatever the
-// timing of the run: a wavefront ranks its entries by matching equal bins across its
-// lanes (a sample has at most one entry per bin), then the wavefronts of the block
-// claim their runs of each bin in wavefront order.
+// timing of the run (a stable sort of each round's entries by bin, below).
 template <bool SCATTER>
 __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, const BinArgs& a,
                                          const ntc_query* __restrict__ q, int bi) {
@@ -863,67 +861,145 @@ __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, co
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += blockDim.x) a.counts[(long long)b * a.nbb + bi] = hist[b];
   } else {
-    constexpr int kWaves = kBinThreads / 64, kUniq = 4 * 64;
-    __shared__ int ukey[kWaves][kUniq];  // a wavefront's distinct bins, in match order
-    __shared__ int ubase[kWaves][kUniq]; // their entry counts, then their first list positions
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    for (long long r0 = s0; r0 < s1; r0 += blockDim.x) {
-      const long long sk = r0 + threadIdx.x;
-      int bk[4] = {-1, -1, -1, -1};
-      ntc_query qq{0.f, 0.f, 0};
-      if (sk < s1) {
-        qq = q[sk];
-        sample_bin_list(m, tg, qq, bk);
-      }
-      // ranks within the wavefront: one round per distinct bin (wavefront-uniform loop)
-      unsigned long long pend[4];
+    // Scatter, one round of 1024 samples at a time.  The round's entries (bin, 4 t + e)
+    // for thread t's e-th bin are sorted by bin with a stable LSD radix sort in LDS (the
+    // ids start in sample order and a sample has at most one entry per bin), so each bin's
+    // run lists its samples in increasing order; an entry's list position is the bin's
+    // running position in this block (hist) plus its rank in the run.
+    static_assert(kBinThreads == 1024, "the scatter sorts 4 entries of each of 1024 threads");
+    constexpr int kE = 4 * kBinThreads;
+    // 4-bit digits: as many passes as the bin indices need; the largest key of that many
+    // digits marks unused entries (sorted last)
+    const int passes = nb < 16 ? 1 : nb < 256 ? 2 : nb < 4096 ? 3 : 4;
+    const int kInvalid = (1 << (4 * passes)) - 1;
+    __shared__ __align__(16) int sbuf[2][kE];
+    __shared__ float qu[kBinThreads], qv[kBinThreads];
+    __shared__ int ql[kBinThreads];
+    __shared__ uint32_t wsum[16][8], wpre[16][8], wtot[8];
+    __shared__ int wmax[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int list_len = a.base[nb];
+    for (long long r0 = s0; r0 < s1; r0 += kBinThreads) {
+      const long long sk = r0 + t;
+      int v[4];
+      {
+        int bk[4] = {-1, -1, -1, -1};
+        if (sk < s1) {
+          const ntc_query qq = q[sk];
+          qu[t] = qq.u;
+          qv[t] = qq.v;
+          ql[t] = qq.lod;
+          sample_bin_list(m, tg, qq, bk);
+        }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) pend[e] = __ballot(bk[e] >= 0);
-      int rank[4] = {0, 0, 0, 0}, uid[4] = {0, 0, 0, 0};
-      int nu = 0;
-      while (pend[0] | pend[1] | pend[2] | pend[3]) {
-        const int es = pend[0] ? 0 : pend[1] ? 1 : pend[2] ? 2 : 3;
-        const int src = __builtin_ctzll(pend[es]);
-        const int key = __shfl(es == 0 ? bk[0] : es == 1 ? bk[1] : es == 2 ? bk[2] : bk[3], src);
-        unsigned long long all = 0;
+        for (int e = 0; e < 4; ++e) v[e] = ((bk[e] >= 0 ? bk[e] : kInvalid) << 12) | (4 * t + e);
+      }
+      // stable counting passes over the 4-bit digits of the bin
+      for (int pass = 0; pass < passes; ++pass) {
+        const int sh = 12 + 4 * pass;
+        int d[4], lr[4];
+        unsigned long long cl = 0;  // this thread's digit counts, 4 bits each
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const unsigned long long me = __ballot(bk[e] == key);
-          all |= me;
-          pend[e] &= ~me;
+          d[e] = (v[e] >> sh) & 15;
+          lr[e] = (int)((cl >> (4 * d[e])) & 15ull);
+          cl += 1ull << (4 * d[e]);
         }
-        const int below_n = __popcll(all & below);
+        // counts of digits 2i (low half) and 2i + 1 (high half) in register i; 16-bit
+        // fields hold block sums (at most 4096) without carries
+        uint32_t c[8], inc[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (bk[e] == key) {
-            rank[e] = below_n;
-            uid[e] = nu;
-          }
-        if (lane == 0) {
-          ukey[wave][nu] = key;
-          ubase[wave][nu] = __popcll(all);
+        for (int i = 0; i < 8; ++i) {
+          c[i] = (uint32_t)((cl >> (8 * i)) & 15ull) | ((uint32_t)((cl >> (8 * i + 4)) & 15ull) << 16);
+          inc[i] = wave_incl_sum(c[i]);
         }
-        ++nu;
-      }
-      __syncthreads();
-      // runs of each bin claimed wavefront after wavefront (distinct keys within one)
-      for (int w = 0; w < nwaves; ++w) {
-        if (wave == w) {
-          for (int u = lane; u < nu; u += 64) {
-            const int key = ukey[w][u], b = hist[key];
-            hist[key] = b + ubase[w][u];
-            ubase[w][u] = b;
+        if (lane == 63)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) wsum[wave][i] = inc[i];
+        __syncthreads();
+        if (t < 8) {  // prefix over the wavefronts, register t
+          uint32_t run = 0;
+          for (int w = 0; w < 16; ++w) {
+            wpre[w][t] = run;
+            run += wsum[w][t];
           }
+          wtot[t] = run;
         }
         __syncthreads();
-      }
+        // comb[i]: first position of digits 2i, 2i + 1 (all smaller digits of the block)
+        // plus the entries of those digits in earlier threads
+        uint32_t comb[8];
+        {
+          uint32_t run = 0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (bk[e] >= 0)
-          a.list[ubase[wave][uid[e]] + rank[e]] =
-              make_int4(__float_as_int(qq.u), __float_as_int(qq.v), qq.lod, (int)sk);
-      __syncthreads();  // ukey and ubase are reused by the next round
+          for (int i = 0; i < 8; ++i) {
+            const uint32_t tot = wtot[i], lo = tot & 0xFFFFu;
+            comb[i] = (run | ((run + lo) << 16)) + wpre[wave][i] + inc[i] - c[i];
+            run += lo + (tot >> 16);
+          }
+        }
+        int* out = sbuf[pass & 1];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = d[e] >> 1;
+          const uint32_t a01 = (i & 1) ? comb[1] : comb[0], a23 = (i & 1) ? comb[3] : comb[2];
+          const uint32_t a45 = (i & 1) ? comb[5] : comb[4], a67 = (i & 1) ? comb[7] : comb[6];
+          const uint32_t a03 = (i & 2) ? a23 : a01, a47 = (i & 2) ? a67 : a45;
+          const uint32_t f = (i & 4) ? a47 : a03;
+          out[((d[e] & 1) ? (int)(f >> 16) : (int)(f & 0xFFFFu)) + lr[e]] = v[e];
+        }
+        __syncthreads();
+        const int4 r = reinterpret_cast<const int4*>(out)[t];
+        v[0] = r.x;
+        v[1] = r.y;
+        v[2] = r.z;
+        v[3] = r.w;
+      }
+      // sorted: position p = 4 t + e.  Runs of equal bins: a run starts where the bin
+      // changes; its start is the running maximum of the start positions.
+      const int* srt = sbuf[(passes - 1) & 1];
+      const int prev = t > 0 ? srt[4 * t - 1] >> 12 : -1;
+      const int next = t < kBinThreads - 1 ? srt[4 * t + 4] >> 12 : -1;
+      int key[4], st[4];
+      int run = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        key[e] = v[e] >> 12;
+        const int before = e == 0 ? prev : key[e - 1];
+        if (key[e] != before) run = 4 * t + e;
+        st[e] = run;
+      }
+      // the start of the run open at the end of the previous thread: the largest run start
+      // at or before it (threads without a run start of their own hold 0)
+      const int incm = wave_incl_max(run);
+      if (lane == 63) wmax[wave] = incm;
+      __syncthreads();
+      int carry = 0;
+      for (int w = 0; w < wave; ++w) carry = max(carry, wmax[w]);
+      {
+        const int x = __shfl_up(incm, 1, 64);
+        if (lane >= 1) carry = max(carry, x);
+      }
+      int lpos[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int start = max(st[e], carry);  // st[e] >= carry once this thread starts a run
+        lpos[e] = key[e] != kInvalid ? hist[key[e]] + (4 * t + e - start) : -1;
+      }
+      __syncthreads();  // every position read hist before the runs advance it
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int after = e == 3 ? next : key[e + 1];
+        if (key[e] != kInvalid && key[e] != after) {
+          const int start = max(st[e], carry);
+          hist[key[e]] += 4 * t + e - start + 1;  // the run's last entry advances its bin
+        }
+        if (lpos[e] >= 0 && lpos[e] < list_len) {
+          const int id = (v[e] & 4095) >> 2;
+          a.list[lpos[e]] = make_int4(__float_as_int(qu[id]), __float_as_int(qv[id]), ql[id], (int)(r0 + id));
+        }
+      }
+      __syncthreads();  // hist, the sort buffers and the queries are reused by the next round
     }
   }
 }
@@ -1599,9 +1675,12 @@ static hipError_t fused_t(const ntc_material& mm, const TrainPlan& p, const Trai
   return hipGetLastError();
 }
 
+// (c0, c1, channels, hidden): the configurations' shapes and Table 3's four profiles on a
+// 9-channel texture set
 #define NTC_TRAIN_SHAPES(X)                                                            \
   X(8, 8, 8, 64) X(10, 10, 10, 64) X(12, 12, 12, 64) X(16, 16, 16, 64) X(8, 8, 8, 32) \
-  X(10, 10, 10, 32) X(12, 12, 12, 32) X(16, 16, 16, 32)
+  X(10, 10, 10, 32) X(12, 12, 12, 32) X(16, 16, 16, 32)                              \
+  X(8, 12, 9, 64) X(12, 20, 9, 64) X(12, 10, 9, 64) X(16, 12, 9, 64)
 
 bool train_shape_supported(int c0, int c1, int c, int hd) {
 #define NTC_X(a, b, cc, h) \

@@ -202,3 +202,23 @@ def test_noalloc_step_rejects_steps_beyond_its_scratch(ntc):
         assert r == ntc.E_INVALID
         r = ntc._lib.ntc_train_step_noalloc(C.byref(m), C.byref(st), fake, 0, fake, C.byref(hp), None)
         assert r == ntc.E_INVALID
+
+
+def test_table3_profiles_supported_with_table6_level0_bytes(ntc):
+    """Table 3's four profiles on the table's 4096^2 x 9 reference set: decode and training
+    kernels exist (with the paper's network: hardGELU, LOD input), and the library's
+    packed level-0 grids take exactly the 4k column of Table 6 (tests/golden)."""
+    import json
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "table6_storage.json")))
+    for name, p in gold["profiles"].items():
+        m = ntc.material_init(4096, 4096, 9, p["c0"], p["c1"], p["b0"], p["b1"], 64, grid_shift=p["shift"],
+                              activation=ntc.ACT_HARDGELU, lod_input=1)
+        assert ntc.shape_supported(m, True) and ntc.shape_supported(m, False), name
+        level0 = (m.g0_packed[1] if m.num_levels > 1 else m.packed_bytes) - m.g0_packed[0]
+        assert level0 == gold["grids_mb"][name]["4096"] * 2 ** 20, (name, level0)
+        assert ntc.train_workspace_bytes(m, 262144, ntc.F16) > 0, name
+        # FP32 training sums latent gradients in 8-byte fixed point: with G0 at 2048^2 (NTC
+        # 2.25 at 4k) its 8 x 8 tiles outnumber the binning capacity; at 2k every profile fits
+        m2 = ntc.material_init(2048, 2048, 9, p["c0"], p["c1"], p["b0"], p["b1"], 64, grid_shift=p["shift"],
+                               activation=ntc.ACT_HARDGELU, lod_input=1)
+        assert ntc.train_workspace_bytes(m2, 262144, ntc.F32) > 0, name

@@ -33,8 +33,9 @@ template <typename T, int C0, int C1, int C, int HD, int B0, int B1, bool PACKED
 static hipError_t decode_t1(const ntc_material& mm, const void* src, const void* wpack, const float* mlp,
                            const ntc_query* q, long long n, const TexelRect& rect, void* out, bool out_f16,
                            hipStream_t s) {
-  constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>::WB;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
+  using DL = DecodeLayout<T, C0, C1, HD, B0, B1, PACKED>;
+  constexpr int WB = DL::WB;
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes) + DL::SLAB;
   const float *b1, *b2, *b3;
   if (mlp) {
     const long long K = mm.input_width;

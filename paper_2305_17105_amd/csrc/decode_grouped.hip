@@ -57,8 +57,9 @@ template <typename T, int C0, int C1, int C, int HD, int B0, int B1, int ACT>
 hipError_t grouped_t(const ntc_material* mats, const char* tab, unsigned long long hash,
                      const std::vector<GroupItem>& items,
                      const ntc_query* q, char* out, bool out_f16, hipStream_t s) {
-  constexpr int WB = DecodeLayout<T, C0, C1, HD, B0, B1, true>::WB;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
+  using DL = DecodeLayout<T, C0, C1, HD, B0, B1, true>;
+  constexpr int WB = DL::WB;
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes) + DL::SLAB;
   auto kern = decode_grouped_kernel<T, C0, C1, C, HD, B0, B1, ACT>;
   static const int per_cu = blocks_per_cu(kern, 256, lds);
   const PeTable pe = pe_table(mats[items[0].mat]);

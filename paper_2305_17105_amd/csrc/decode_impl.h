@@ -29,6 +29,15 @@ struct DecodeLayout {
   static constexpr PackGeom pg = PACKED ? pack_geom_decode(C0, C1, B0, B1, HD, sizeof(T) == 2)
                                         : pack_geom(C0, C1, HD, sizeof(T) == 2);
   static constexpr int WB = ((int)pg.fwd_end * (int)sizeof(T) + 15) / 16 * 16;
+  // Point decode of the paired layout locates each texel once: every lane of a wavefront
+  // takes one texel of a 64-texel group, gathers its four G0 neighbour windows and four
+  // G1 taps, forms the G1 pairs of all four lane groups and leaves them in a per-wavefront
+  // slab of LDS, SW words per texel (odd: consecutive texels fall in different banks).
+  static constexpr int NW0 = (C0 * B0 + 31) / 32, NW1 = (C1 * B1 + 31) / 32;
+  static constexpr int NP = paired ? NW1 * (4 / B1) : 0;  // G1 pairs of one lane group
+  static constexpr int GW = NW0 + NP;                     // words of one lane group
+  static constexpr int SW = (4 * GW + 1) | 1;             // + the texel's PE / LOD word
+  static constexpr int SLAB = paired ? 4 * 64 * SW * 4 : 0;  // bytes, 4 wavefronts
 };
 
 // Two codes of one 32-bit word (bit offsets s and s + 16) as FP16 values 1024 + code:
@@ -122,11 +131,11 @@ struct CodeWindow {
 // d*32/B1 + g + 4kk and that + 16/B1.  Separable, in centred code units: the row steps
 // are exact, the column step rounds once, the power-of-two scale is exact, so the
 // result equals the FP16 rounding of the exact bilinear value.
-template <int C0, int C1, int B0, int B1>
-__device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
-                                f16x2 (&out)[CodeWindow<C0, C1, B0, B1>::NW1 * (4 / B1)]) {
-  constexpr int NW1 = CodeWindow<C0, C1, B0, B1>::NW1, KP = 4 / B1, N1 = 1 << B1;
-  const f16x2 fx = {(_Float16)R.fx, (_Float16)R.fx}, fy = {(_Float16)R.fy, (_Float16)R.fy};
+template <int NW1, int B1>
+__device__ inline void g1_pairs_words(const uint32_t (&w1)[4][NW1], float gfx, float gfy, int g,
+                                      f16x2 (&out)[NW1 * (4 / B1)]) {
+  constexpr int KP = 4 / B1, N1 = 1 << B1;
+  const f16x2 fx = {(_Float16)gfx, (_Float16)gfx}, fy = {(_Float16)gfy, (_Float16)gfy};
   const _Float16 o = (_Float16)(-(1024.f + N1 / 2 - 1));
   const f16x2 of = {o, o};
   const f16x2 sc = {(_Float16)(1.f / N1), (_Float16)(1.f / N1)};
@@ -135,31 +144,71 @@ __device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
 #pragma unroll
     for (int kk = 0; kk < KP; ++kk) {
       const int sh = B1 * (g + 4 * kk);
-      const f16x2 x0 = code_pair<B1>(R.g1[0][d], sh), x1 = code_pair<B1>(R.g1[1][d], sh);
-      const f16x2 x2 = code_pair<B1>(R.g1[2][d], sh), x3 = code_pair<B1>(R.g1[3][d], sh);
+      const f16x2 x0 = code_pair<B1>(w1[0][d], sh), x1 = code_pair<B1>(w1[1][d], sh);
+      const f16x2 x2 = code_pair<B1>(w1[2][d], sh), x3 = code_pair<B1>(w1[3][d], sh);
       const f16x2 r0 = __builtin_elementwise_fma(fx, x1 - x0, x0 + of);
       const f16x2 r1 = __builtin_elementwise_fma(fx, x3 - x2, x2 + of);
       out[d * KP + kk] = __builtin_elementwise_fma(fy, r1 - r0, r0) * sc;
     }
 }
+template <int C0, int C1, int B0, int B1>
+__device__ inline void g1_pairs(const CodeWindow<C0, C1, B0, B1>& R, int g,
+                                f16x2 (&out)[CodeWindow<C0, C1, B0, B1>::NW1 * (4 / B1)]) {
+  g1_pairs_words<CodeWindow<C0, C1, B0, B1>::NW1, B1>(R.g1, R.fx, R.fy, g, out);
+}
+
+// The code words of one texel for the grouped gather: the four G0 neighbour windows
+// (order (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1)) and the four G1 taps, plus what the
+// input assembly needs from the footprint.
+template <int C0, int C1, int B0, int B1>
+struct TexelCodes {
+  static constexpr int NB0 = C0 * B0, NW0 = (NB0 + 31) / 32, NB1 = C1 * B1, NW1 = (NB1 + 31) / 32;
+  int ix, iy, l;
+  float fx, fy;
+  uint32_t g0[4][NW0];
+  uint32_t g1[4][NW1];
+  __device__ inline void fetch(const DevMat& m, const LevelBytes* __restrict__ lb, const uint32_t* __restrict__ packed,
+                               float u, float v, int lod) {
+    const Footprint f = locate(m, u, v, lod, 0);
+    ix = f.ix;
+    iy = f.iy;
+    l = f.l;
+    fx = f.fx;
+    fy = f.fy;
+    const int w0 = m.W >> (m.shift + 2 * f.j);
+    const LevelBytes b = lb[f.j];
+    gbyte* pk = (gbyte*)reinterpret_cast<const char*>(packed);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int cell = ((g >> 1) ? f.by : f.ay) * w0 + ((g & 1) ? f.bx : f.ax);
+      load_window<NW0, NB0>(pk, b.g0, (uint32_t)cell, b.g0_last, g0[g]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) load_window<NW1, NB1>(pk, b.g1, (uint32_t)f.g1_cell[k], b.g1_last, g1[k]);
+  }
+};
 
 // Latent slots of the paired FP16 layout from a code window: G0 two channels per
 // instruction ((1024 + code) / N - (N/2 - 1 + 1024) / N is exact), then the G1 pairs.
-template <int C0, int C1, int B0, int B1, int S1>
-__device__ inline void paired_inputs(const CodeWindow<C0, C1, B0, B1>& R, int g, _Float16 (&xs)[S1]) {
-  using Raw = CodeWindow<C0, C1, B0, B1>;
+template <int NW0, int B0, int S1>
+__device__ inline void paired_g0(const uint32_t (&w0)[NW0], _Float16 (&xs)[S1]) {
   constexpr int HALF = 16 / B0, N0 = 1 << B0;
   const f16x2 sc = {(_Float16)(1.f / N0), (_Float16)(1.f / N0)};
   const _Float16 o = (_Float16)(-(1024.f + N0 / 2 - 1) / N0);
   const f16x2 of = {o, o};
 #pragma unroll
-  for (int d = 0; d < Raw::NW0; ++d)
+  for (int d = 0; d < NW0; ++d)
 #pragma unroll
     for (int c = 0; c < HALF; ++c) {
-      const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(R.g0[d], B0 * c), sc, of);
+      const f16x2 x = __builtin_elementwise_fma(code_pair<B0>(w0[d], B0 * c), sc, of);
       xs[2 * (d * HALF + c)] = x[0];
       xs[2 * (d * HALF + c) + 1] = x[1];
     }
+}
+template <int C0, int C1, int B0, int B1, int S1>
+__device__ inline void paired_inputs(const CodeWindow<C0, C1, B0, B1>& R, int g, _Float16 (&xs)[S1]) {
+  using Raw = CodeWindow<C0, C1, B0, B1>;
+  paired_g0<Raw::NW0, B0>(R.g0, xs);
   f16x2 v[Raw::NW1 * (4 / B1)];
   g1_pairs(R, g, v);
   constexpr int G0S = paired_g0_slots(C0, B0);
@@ -246,6 +295,42 @@ __device__ inline void filter_tap(const DevMat& m, const ntc_filter_query& fq, l
     wt = 1.f;
   }
 }
+
+// FP16 weight A-fragments of one layer (MTN M-tiles of S slots) held in registers, in
+// the pack's operand order: S/8 fragments of 8 slots per M-tile and a 4-slot tail.
+template <int S, int MTN>
+struct RegLayer {
+  static constexpr int S8 = S / 8, NF = S8 > 0 ? S8 : 1;
+  static constexpr bool TAIL = S % 8 != 0;
+  f16x8 a[MTN][NF];
+  f16x4 t[MTN];
+  __device__ inline void load(const _Float16* __restrict__ w, int lane) {
+#pragma unroll
+    for (int mo = 0; mo < MTN; ++mo) {
+#pragma unroll
+      for (int k = 0; k < S8; ++k) a[mo][k] = *reinterpret_cast<const f16x8*>(w + mo * S * 64 + k * 512 + lane * 8);
+      if constexpr (TAIL) t[mo] = *reinterpret_cast<const f16x4*>(w + mo * S * 64 + S8 * 512 + lane * 4);
+    }
+  }
+  // acc += A(mo) * B over the S slots of b (as mma_slots, including its separate tail)
+  __device__ inline f32x4 mma(f32x4 acc, int mo, const _Float16 (&b)[S]) const {
+#pragma unroll
+    for (int k = 0; k < S8; ++k) {
+      f16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bv[j] = b[8 * k + j];
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mo][k], bv, acc, 0, 0, 0);
+    }
+    if constexpr (TAIL) {
+      f16x4 bv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = b[8 * S8 + j];
+      const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+      acc += __builtin_amdgcn_mfma_f32_16x16x16f16(t[mo], bv, zero, 0, 0, 0);
+    }
+    return acc;
+  }
+};
 
 // PACKED: latents come as bit-packed codes (ntc_decode); otherwise as FP32 values
 // in the canonical latent layout (ntc_forward, the differentiation path).
@@ -354,7 +439,121 @@ __device__ __forceinline__ void decode_body(const DevMat& m, const PeTable& pe, 
     }
   };
 
-  if constexpr (PACKED) {
+  if constexpr (PACKED && FILT == 0 && DL::paired) {
+    // Point decode, one texel per lane: a wavefront takes 64 consecutive texels (four
+    // 16-texel tiles) at a time.  Each lane locates its texel once and gathers its code
+    // words (the next group's while the current group runs through the matrix cores),
+    // then leaves the G0 windows and the G1 pairs of all four lane groups in the
+    // wavefront's slab; lane (g, r) of tile k reads back texel 16k + r's group-g words.
+    using TC = TexelCodes<C0, C1, B0, B1>;
+    constexpr int NW0 = DL::NW0, NP = DL::NP, GW = DL::GW, SW = DL::SW;
+    constexpr int G0S = paired_g0_slots(C0, B0);
+    uint32_t* slab = reinterpret_cast<uint32_t*>(lb + kMaxLevels) + wave * 64 * SW;
+    const long long groups = (n + 63) / 64;
+    auto load_texel = [&](long long grp, float& u, float& v, int& lod) {
+      u = v = 0.f;
+      lod = 0;
+      const long long s = grp * 64 + lane;
+      if (grp < groups && s < n) {
+        if (rect.w > 0) {
+          rect_query(rect, s, u, v, lod);
+        } else {
+          u = q[s].u;
+          v = q[s].v;
+          lod = q[s].lod;
+        }
+      }
+    };
+    // the three layers' weights in registers for the whole kernel (the slab's stores
+    // would otherwise keep the compiler from hoisting their LDS loads out of the loop);
+    // measured faster than layer 1 only (3 wavefronts per SIMD either way) and than
+    // weights read from LDS per tile (5 wavefronts per SIMD, 22 KiB of LDS reads a tile)
+    RegLayer<S1, MT> r1;
+    RegLayer<SH, MT> r2;
+    RegLayer<SH, 1> r3;
+    r1.load(w_lds + pg.L1, lane);
+    r2.load(w_lds + pg.L2, lane);
+    r3.load(w_lds + pg.L3, lane);
+    auto mlp_store_reg = [&](T (&xs)[S1], long long tile) {
+      const long long s = tile * 16 + r;
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + 16 * mo + 4 * g);
+        acc[mo] = r1.mma(acc[mo], mo, xs);
+      }
+      T h[SH];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        acc[mo] = *reinterpret_cast<const f32x4*>(b_lds + HD + 16 * mo + 4 * g);
+        acc[mo] = r2.mma(acc[mo], mo, h);
+      }
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) act4<ACT>(acc[mo], h + 4 * mo);
+      f32x4 y = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
+      y = r3.mma(y, 0, h);
+      store_out<C>(out, out_f16, s, n, g, y);
+    };
+    long long grp = (long long)bi * 4 + wave;
+    if (grp >= groups) return;
+    float u, v;
+    int lod;
+    load_texel(grp, u, v, lod);
+    TC cur;
+    cur.fetch(m, lb, packed, u, v, lod);
+    load_texel(grp + stride, u, v, lod);
+    for (; grp < groups; grp += stride) {
+      {
+        uint32_t* my = slab + lane * SW;
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+          f16x2 pr[NP];
+          g1_pairs_words<DL::NW1, B1>(cur.g1, cur.fx, cur.fy, gg, pr);
+#pragma unroll
+          for (int w = 0; w < NW0; ++w) my[gg * GW + w] = cur.g0[gg][w];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) my[gg * GW + NW0 + p] = __builtin_bit_cast(uint32_t, pr[p]);
+        }
+        my[4 * GW] = (uint32_t)(cur.ix & 7) | ((uint32_t)(cur.iy & 7) << 3) | ((uint32_t)cur.l << 6);
+      }
+      // LDS operations of a wavefront complete in order: the reads below see the writes
+      // above; the barrier keeps the compiler from moving memory operations across it
+      __builtin_amdgcn_wave_barrier();
+      TC nxt;
+      if (grp + stride < groups) nxt.fetch(m, lb, packed, u, v, lod);
+      if (grp + 2 * stride < groups) load_texel(grp + 2 * stride, u, v, lod);
+      // the inputs of tile k: lane (g, r) reads texel 16k + r's group-g words
+      auto assemble_tile = [&](int k, T (&xs)[S1]) {
+        const uint32_t* rd = slab + (16 * k + r) * SW;
+        uint32_t w0[NW0];
+#pragma unroll
+        for (int w = 0; w < NW0; ++w) w0[w] = rd[g * GW + w];
+        paired_g0<NW0, B0>(w0, xs);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const f16x2 pv = __builtin_bit_cast(f16x2, rd[g * GW + NW0 + p]);
+          xs[G0S + 2 * p] = pv[0];
+          xs[G0S + 2 * p + 1] = pv[1];
+        }
+        const uint32_t meta = rd[4 * GW];
+        pe_slots(xs, (int)(meta & 7u), (int)((meta >> 3) & 7u), (int)(meta >> 6));
+      };
+      {
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          const long long tile = grp * 4 + k;
+          if (tile * 16 >= n) break;  // wavefront-uniform
+          T xs[S1];
+          assemble_tile(k, xs);
+          mlp_store_reg(xs, tile);
+        }
+      }
+      cur = nxt;
+      __builtin_amdgcn_wave_barrier();  // this group's slab reads precede the next group's writes
+    }
+  } else if constexpr (PACKED) {
     // Software pipeline over the wave's tiles: queries two tiles ahead, latent words
     // one tile ahead, so both gathers are in flight while the matrix cores run.
     using Raw = CodeWindow<C0, C1, B0, B1>;

@@ -294,11 +294,6 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     if constexpr (WIDE) atomicAdd(reinterpret_cast<unsigned long long*>(ireg + k), (unsigned long long)v);
     else atomicAdd(ireg + k, v);
   };
-  // One contribution x to owned latent k of the region.
-  auto acc_lat = [&](int k, float x, bool refine) {
-    if (refine) atomicAdd(freg + k, x);
-    else add_fixed(k, quant(x));
-  };
   const int nitems = item1 >= 0 ? item1 : binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
   for (int item = item0; item < nitems; item += istride) {
     // ---------------- work item -> (tile, sample range)
@@ -490,77 +485,100 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
         // Gradients of the latents this tile owns, accumulated in LDS.  On levels whose
         // samples are sorted by anchor cell, a row (16 samples of one lane group) that
         // targets a single cell is summed across lanes first (one atomic per channel).
+        // The fixed-point pass decides once per footprint cell which lanes add (the row
+        // leader its row sum, or every owning lane its own value); every channel's add
+        // then runs under that one condition.
         const int rr = lane & 15;
         const bool own0 = valid && (f.g0x >> ts) == tx && (f.g0y >> ts) == ty;
         const int key0 = own0 ? ((f.g0y - ty * T_) * T_ + (f.g0x - tx * T_)) : -1;
         const int dst0 = (key0 < 0 ? 0 : key0) * C0;
-        if (sorted) {
-          const int rk = __shfl(key0, lane & ~15);
-          const unsigned long long bal = __ballot(key0 == rk || !valid);
-          const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
+        if (!refine) {  // block-uniform
+          if (sorted) {
+            const int rk = __shfl(key0, lane & ~15);
+            const unsigned long long bal = __ballot(key0 == rk || !valid);
+            const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
+            const bool add = uni ? (rr == 0 && rk >= 0) : own0;
 #pragma unroll
-          for (int t = 0; t < C0; ++t) {
-            if (!refine) {
+            for (int t = 0; t < C0; ++t) {
               const AccI qv = own0 ? quant(dx[t]) : (AccI)0;
               const AccI sq = row_sum16i(qv);
-              if (uni) {
-                if (rr == 0 && rk >= 0) add_fixed(dst0 + t, sq);
-              } else if (own0) {
-                add_fixed(dst0 + t, qv);
-              }
-              continue;
+              if (add) add_fixed(dst0 + t, uni ? sq : qv);
             }
-            const float sv = row_sum16(own0 ? dx[t] : 0.f);
-            if (uni) {
-              if (rr == 0 && rk >= 0) acc_lat(dst0 + t, sv, refine);
-            } else if (own0) {
-              acc_lat(dst0 + t, dx[t], refine);
+          } else if (own0) {
+#pragma unroll
+            for (int t = 0; t < C0; ++t) add_fixed(dst0 + t, quant(dx[t]));
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
+            const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
+            const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
+            const int dst1 = R0 + (key1 < 0 ? 0 : key1) * C1;
+            if (sorted) {
+              const int rk = __shfl(key1, lane & ~15);
+              const unsigned long long bal = __ballot(key1 == rk || !valid);
+              const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
+              const bool add = uni ? (rr == 0 && rk >= 0) : own1;
+#pragma unroll
+              for (int i = 0; i < IS::n1max; ++i) {
+                const AccI qv = own1 ? quant(f.g1_w[k] * dx[C0 + i]) : (AccI)0;
+                const AccI sq = row_sum16i(qv);
+                if (add && (4 * i + 3 < C1 || g + 4 * i < C1)) add_fixed(dst1 + g + 4 * i, uni ? sq : qv);
+              }
+            } else if (own1) {
+#pragma unroll
+              for (int i = 0; i < IS::n1max; ++i)
+                if (4 * i + 3 < C1 || g + 4 * i < C1) add_fixed(dst1 + g + 4 * i, quant(f.g1_w[k] * dx[C0 + i]));
             }
           }
-        } else if (own0) {
-#pragma unroll
-          for (int t = 0; t < C0; ++t) acc_lat(dst0 + t, dx[t], refine);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
-          const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
-          const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
-          const int dst1 = R0 + (key1 < 0 ? 0 : key1) * C1;
+        } else {
+          // the FP32 pass of an item whose contributions left the fixed-point range
           if (sorted) {
-            const int rk = __shfl(key1, lane & ~15);
-            const unsigned long long bal = __ballot(key1 == rk || !valid);
+            const int rk = __shfl(key0, lane & ~15);
+            const unsigned long long bal = __ballot(key0 == rk || !valid);
             const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
 #pragma unroll
-            for (int i = 0; i < IS::n1max; ++i) {
-              const int ch = g + 4 * i;
-              const float v1 = own1 ? f.g1_w[k] * dx[C0 + i] : 0.f;
-              if (!refine) {
-                const AccI qv = own1 ? quant(v1) : (AccI)0;
-                const AccI sq = row_sum16i(qv);
-                if (ch < C1) {
-                  if (uni) {
-                    if (rr == 0 && rk >= 0) add_fixed(dst1 + ch, sq);
-                  } else if (own1) {
-                    add_fixed(dst1 + ch, qv);
-                  }
-                }
-                continue;
-              }
-              const float sv = row_sum16(v1);
-              if (ch < C1) {
-                if (uni) {
-                  if (rr == 0 && rk >= 0) acc_lat(dst1 + ch, sv, refine);
-                } else if (own1) {
-                  acc_lat(dst1 + ch, v1, refine);
-                }
+            for (int t = 0; t < C0; ++t) {
+              const float sv = row_sum16(own0 ? dx[t] : 0.f);
+              if (uni) {
+                if (rr == 0 && rk >= 0) atomicAdd(freg + dst0 + t, sv);
+              } else if (own0) {
+                atomicAdd(freg + dst0 + t, dx[t]);
               }
             }
-          } else if (own1) {
+          } else if (own0) {
 #pragma unroll
-            for (int i = 0; i < IS::n1max; ++i) {
-              const int ch = g + 4 * i;
-              if (ch < C1) acc_lat(dst1 + ch, f.g1_w[k] * dx[C0 + i], refine);
+            for (int t = 0; t < C0; ++t) atomicAdd(freg + dst0 + t, dx[t]);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x1 = f.g1x[k & 1], y1 = f.g1y[k >> 1];
+            const bool own1 = valid && (x1 >> t1s) == tx && (y1 >> t1s) == ty && f.g1_w[k] != 0.f;
+            const int key1 = own1 ? ((y1 - ty * T1) * T1 + (x1 - tx * T1)) : -1;
+            const int dst1 = R0 + (key1 < 0 ? 0 : key1) * C1;
+            if (sorted) {
+              const int rk = __shfl(key1, lane & ~15);
+              const unsigned long long bal = __ballot(key1 == rk || !valid);
+              const bool uni = ((bal >> (lane & ~15)) & 0xFFFFull) == 0xFFFFull;
+#pragma unroll
+              for (int i = 0; i < IS::n1max; ++i) {
+                const int ch = g + 4 * i;
+                const float v1 = own1 ? f.g1_w[k] * dx[C0 + i] : 0.f;
+                const float sv = row_sum16(v1);
+                if (ch < C1) {
+                  if (uni) {
+                    if (rr == 0 && rk >= 0) atomicAdd(freg + dst1 + ch, sv);
+                  } else if (own1) {
+                    atomicAdd(freg + dst1 + ch, v1);
+                  }
+                }
+              }
+            } else if (own1) {
+#pragma unroll
+              for (int i = 0; i < IS::n1max; ++i) {
+                const int ch = g + 4 * i;
+                if (ch < C1) atomicAdd(freg + dst1 + ch, f.g1_w[k] * dx[C0 + i]);
+              }
             }
           }
         }
@@ -711,21 +729,48 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
       float* dst = single ? a.lat_grad : a.part_lat + (long long)item * a.region_max;
       const float osc = single ? out_scale : 1.f;
-      // where latent k of the region goes (tile sides are powers of two)
-      auto dst_index = [&](int k) -> long long {
-        if (!single) return k;
-        if (k < R0) {
-          const int c = k % C0, cell = k / C0, cx = cell & (T_ - 1), cy = cell >> ts;
-          return tab[j] + ((long long)(ty * T_ + cy) * w0 + tx * T_ + cx) * C0 + c;
-        }
-        const int k1 = k - R0, c = k1 % C1, cell = k1 / C1, cx = cell & (T1 - 1), cy = cell >> t1s;
-        return tab[8 + j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
+      // latent k of the region as a float (fixed-point sums, or the FP32 sums of a
+      // summed-again item)
+      auto reg_value = [&](int k) -> float {
+        if constexpr (WIDE) return refined ? freg[k] : (float)((double)ireg[k] * (double)fixinv);
+        else return refined ? freg[k] : (float)ireg[k] * fixinv;
       };
-      for (int k = tid; k < RG; k += NTHR) {
-        float v;
-        if constexpr (WIDE) v = refined ? freg[k] : (float)((double)ireg[k] * (double)fixinv);
-        else v = refined ? freg[k] : (float)ireg[k] * fixinv;
-        dst[dst_index(k)] = v * osc;
+      // rows of L region latents (a row of cells of the tile, all channels) go to
+      // consecutive latents: row y of the block at region offset k0 + y L lands at
+      // gbase + y gstride; 16-byte loads and stores where the rows and offsets allow
+      auto copy_rows = [&](int k0, int L, int rows, long long gbase, long long gstride) {
+        if (L % 4 == 0 && ((gbase | gstride) & 3) == 0) {
+          const int q4 = L >> 2, n4 = rows * q4;
+          for (int i = tid; i < n4; i += NTHR) {
+            const int y = i / q4, o = (i - y * q4) * 4, k = k0 + y * L + o;  // k: a multiple of 4
+            f32x4 val;
+            if (refined) {
+              val = *reinterpret_cast<const f32x4*>(freg + k);
+            } else if constexpr (WIDE) {
+              const longlong2 lo = *reinterpret_cast<const longlong2*>(ireg + k);
+              const longlong2 hi = *reinterpret_cast<const longlong2*>(ireg + k + 2);
+              const double fi = (double)fixinv;
+              val = f32x4{(float)((double)lo.x * fi), (float)((double)lo.y * fi), (float)((double)hi.x * fi),
+                          (float)((double)hi.y * fi)};
+            } else {
+              const int4 iv = *reinterpret_cast<const int4*>(ireg + k);
+              val = f32x4{(float)iv.x * fixinv, (float)iv.y * fixinv, (float)iv.z * fixinv, (float)iv.w * fixinv};
+            }
+            *reinterpret_cast<f32x4*>(dst + gbase + y * gstride + o) = val * osc;
+          }
+        } else {
+          for (int i = tid; i < rows * L; i += NTHR) {
+            const int y = i / L, o = i - y * L;
+            dst[gbase + y * gstride + o] = reg_value(k0 + y * L + o) * osc;
+          }
+        }
+      };
+      if (single) {
+        copy_rows(0, T_ * C0, T_, tab[j] + ((long long)ty * T_ * w0 + (long long)tx * T_) * C0, (long long)w0 * C0);
+        copy_rows(R0, T1 * C1, T1, tab[8 + j] + ((long long)ty * T1 * w1 + (long long)tx * T1) * C1,
+                  (long long)w1 * C1);
+      } else {
+        copy_rows(0, RG, 1, 0, 0);  // the region as it is
       }
       __syncthreads();
     }

@@ -368,6 +368,15 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       const long long g0base = tab[f.j] + (long long)f.g0_cell * C0;
       const long long g1base = tab[8 + f.j];
 
+      // targets of channels 4g .. 4g + 3, loaded with the gathers so that both arrive
+      // while the forward waits for the latents
+      float tgt[4] = {0.f, 0.f, 0.f, 0.f};
+      if (!a.dout) {
+        const long long tb = tab[16 + f.l] + ((long long)f.iy * max(1, m.W >> f.l) + f.ix) * C;  // mip width from m.W (no per-lane argument load)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < C) tgt[i] = a.targets[tb + 4 * g + i];
+      }
       // ---------------- gather (forward latents already hold this step's noise)
       T xs[S1];
 #pragma unroll
@@ -430,8 +439,6 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       // ---------------- loss and output gradient (lane group g: channels 4g..4g+3)
       T dyT[4];
       {
-        const int l = f.l;
-        const long long tb = tab[16 + l] + ((long long)f.iy * m.mip_w[l] + f.ix) * C;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = 4 * g + i;
@@ -440,7 +447,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
             if (a.dout) {
               d = a.dout[s * C + c] * dout_scale;
             } else {
-              const float e = y[i] - a.targets[tb + c];
+              const float e = y[i] - tgt[i];
               if (primary && !refine) loss += e * e;
               d = 2.f * e * a.inv_nc * scale;
             }

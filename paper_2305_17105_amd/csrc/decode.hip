@@ -11,7 +11,8 @@ static hipError_t decode_fp8_t1(const ntc_material& mm, const uint8_t* packed, c
                                 long long n, const TexelRect& rect, void* out, bool out_f16, hipStream_t s) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes) +
+                     DecodeLayout<_Float16, C0, C1, HD, B0, B1, true>::SLAB;
   const float* scales = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wpack) + WB);
   auto kern = decode_fp8_kernel<C0, C1, C, HD, B0, B1, ACT>;
   static const int per_cu = blocks_per_cu(kern, 256, lds);

@@ -74,7 +74,8 @@ hipError_t grouped_fp8_t(const ntc_material* mats, const char* tab, unsigned lon
                          const ntc_query* q, char* out, bool out_f16, hipStream_t s) {
   constexpr PackGeom pg = pack_geom_fp8(C0, C1, B0, B1, HD);
   constexpr int WB = ((int)pg.fwd_end + 15) / 16 * 16;
-  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes);
+  const size_t lds = WB + (48 + 2 * HD + 16) * 4 + kMaxLevels * sizeof(LevelBytes) +
+                     DecodeLayout<_Float16, C0, C1, HD, B0, B1, true>::SLAB;
   auto kern = decode_fp8_grouped_kernel<C0, C1, C, HD, B0, B1, ACT>;
   static const int per_cu = blocks_per_cu(kern, 256, lds);
   const PeTable pe = pe_table(mats[items[0].mat]);

@@ -821,22 +821,8 @@ __device__ __forceinline__ void decode_fp8_body(const DevMat& m, const PeTable& 
   const float lod_norm = m.lod_in && m.M > 1 ? 1.f / (float)(m.M - 1) : 0.f;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const long long tiles = (n + 15) / 16, stride = (long long)nb * 4;
+  const long long stride = (long long)nb * 4;
 
-  auto load_query = [&](long long tile, float& u, float& v, int& lod) {
-    const long long s = tile * 16 + r;
-    u = v = 0.f;
-    lod = 0;
-    if (tile < tiles && s < n) {
-      if (rect.w > 0) {
-        rect_query(rect, s, u, v, lod);
-      } else {
-        u = q[s].u;
-        v = q[s].v;
-        lod = q[s].lod;
-      }
-    }
-  };
   // A operand of MFMA kk of M-tile mo of a layer pack with S slots
   auto a_op = [&](long long base, int S, int mo, int kk) -> long {
     return *reinterpret_cast<const long*>(w_lds + base + (long long)mo * S * 64 + kk * 512 + lane * 8);
@@ -853,80 +839,136 @@ __device__ __forceinline__ void decode_fp8_body(const DevMat& m, const PeTable& 
     return cvt_e4m3x2(h[2], h[3], cvt_e4m3x2(h[0], h[1], 0u, false), true);
   };
 
-  long long tile = (long long)bi * 4 + wave;
-  if (tile >= tiles) return;
+  // As the FP16 point decode: a wavefront takes 64 texels at a time, each lane locates
+  // and gathers one texel, and the code words go through the wavefront's slab (same
+  // layout as FP16's: G0 windows, G1 pairs of every lane group, PE / LOD word); the
+  // weight operands stay in registers (8 bytes per lane and MFMA).
+  using DL = DecodeLayout<_Float16, C0, C1, HD, B0, B1, true>;
+  static_assert(DL::paired, "the FP8 layout extends the paired one");
+  using TC = TexelCodes<C0, C1, B0, B1>;
+  constexpr int NW0 = DL::NW0, GW = DL::GW, SW = DL::SW;
+  uint32_t* slab = reinterpret_cast<uint32_t*>(lb + kMaxLevels) + wave * 64 * SW;
+  long w1r[MT][S1 / 8], w2r[MT][SH / 8], w3r[SH / 8];
+#pragma unroll
+  for (int mo = 0; mo < MT; ++mo) {
+#pragma unroll
+    for (int kk = 0; kk < S1 / 8; ++kk) w1r[mo][kk] = a_op(pg.L1, S1, mo, kk);
+#pragma unroll
+    for (int kk = 0; kk < SH / 8; ++kk) w2r[mo][kk] = a_op(pg.L2, SH, mo, kk);
+  }
+#pragma unroll
+  for (int kk = 0; kk < SH / 8; ++kk) w3r[kk] = a_op(pg.L3, SH, 0, kk);
+  const long long groups = (n + 63) / 64;
+  auto load_texel = [&](long long grp, float& u, float& v, int& lod) {
+    u = v = 0.f;
+    lod = 0;
+    const long long s = grp * 64 + lane;
+    if (grp < groups && s < n) {
+      if (rect.w > 0) {
+        rect_query(rect, s, u, v, lod);
+      } else {
+        u = q[s].u;
+        v = q[s].v;
+        lod = q[s].lod;
+      }
+    }
+  };
+  long long grp = (long long)bi * 4 + wave;
+  if (grp >= groups) return;
   float u, v;
   int lod;
-  load_query(tile, u, v, lod);
-  Raw cur;
-  cur.fetch(m, lb, packed, u, v, lod, g);
-  load_query(tile + stride, u, v, lod);
-  for (; tile < tiles; tile += stride) {
-    Raw nxt;
-    if (tile + stride < tiles) nxt.fetch(m, lb, packed, u, v, lod, g);
-    if (tile + 2 * stride < tiles) load_query(tile + 2 * stride, u, v, lod);
-
-    // ---- inputs: S1/4 words of e4m3 bytes
-    uint32_t xw[S1 / 4];
-#pragma unroll
-    for (int i = 0; i < S1 / 4; ++i) xw[i] = 0u;
-    constexpr uint32_t BM = ((1u << B0) - 1u) * 0x01010101u;
-#pragma unroll
-    for (int d = 0; d < Raw::NW0; ++d)
-#pragma unroll
-      for (int k = 0; k < 8 / B0; ++k) xw[(8 / B0) * d + k] = codes_to_e4m3<B0>((cur.g0[d] >> (B0 * k)) & BM);
+  load_texel(grp, u, v, lod);
+  TC cur;
+  cur.fetch(m, lb, packed, u, v, lod);
+  load_texel(grp + stride, u, v, lod);
+  for (; grp < groups; grp += stride) {
     {
-      f16x2 pv2[NP];
-      g1_pairs(cur, g, pv2);
+      uint32_t* my = slab + lane * SW;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int t = C0 + 2 * p;
-        xw[t / 4] = cvt_e4m3x2((float)pv2[p][0], (float)pv2[p][1], xw[t / 4], (t % 4) != 0);
+      for (int gg = 0; gg < 4; ++gg) {
+        f16x2 pr[NP];
+        g1_pairs_words<Raw::NW1, B1>(cur.g1, cur.fx, cur.fy, gg, pr);
+#pragma unroll
+        for (int w = 0; w < NW0; ++w) my[gg * GW + w] = cur.g0[gg][w];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) my[gg * GW + NW0 + p] = __builtin_bit_cast(uint32_t, pr[p]);
       }
-      float pv[3];
-      pe_values(pe_lds, cur.ix, cur.iy, g, pv);
-      constexpr int t0 = pg.T_lat;  // even
-      const float lodv = g == 0 ? (float)cur.l * lod_norm : 0.f;  // LOD input (section 4.4)
-      xw[t0 / 4] = cvt_e4m3x2(pv[0], pv[1], xw[t0 / 4], (t0 % 4) != 0);
-      xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], lodv, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
+      my[4 * GW] = (uint32_t)(cur.ix & 7) | ((uint32_t)(cur.iy & 7) << 3) | ((uint32_t)cur.l << 6);
     }
-    // ---- layer 1
-    uint32_t hw[SH / 4];
+    __builtin_amdgcn_wave_barrier();  // LDS operations of a wavefront complete in order
+    TC nxt;
+    if (grp + stride < groups) nxt.fetch(m, lb, packed, u, v, lod);
+    if (grp + 2 * stride < groups) load_texel(grp + 2 * stride, u, v, lod);
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      const long long tile = grp * 4 + k;
+      if (tile * 16 >= n) break;  // wavefront-uniform
+      const uint32_t* rd = slab + (16 * k + r) * SW + g * GW;
+      const uint32_t meta = slab[(16 * k + r) * SW + 4 * GW];
+      // ---- inputs: S1/4 words of e4m3 bytes
+      uint32_t xw[S1 / 4];
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < S1 / 4; ++i) xw[i] = 0u;
+      constexpr uint32_t BM = ((1u << B0) - 1u) * 0x01010101u;
 #pragma unroll
-      for (int kk = 0; kk < S1 / 8; ++kk) {
-        const long b = (long)((uint64_t)xw[2 * kk] | (uint64_t)xw[2 * kk + 1] << 32);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L1, S1, mo, kk), b, acc, 0, 0, 0);
+      for (int d = 0; d < NW0; ++d) {
+        const uint32_t w0 = rd[d];
+#pragma unroll
+        for (int kb = 0; kb < 8 / B0; ++kb) xw[(8 / B0) * d + kb] = codes_to_e4m3<B0>((w0 >> (B0 * kb)) & BM);
       }
-      hw[mo] = hidden_word(acc, sc1, b_lds, mo);
-    }
-    // ---- layer 2
-    uint32_t hw2[SH / 4];
+      {
 #pragma unroll
-    for (int mo = 0; mo < MT; ++mo) {
+        for (int p = 0; p < NP; ++p) {
+          const f16x2 pv2 = __builtin_bit_cast(f16x2, rd[NW0 + p]);
+          const int t = C0 + 2 * p;
+          xw[t / 4] = cvt_e4m3x2((float)pv2[0], (float)pv2[1], xw[t / 4], (t % 4) != 0);
+        }
+        float pv[3];
+        pe_values(pe_lds, (int)(meta & 7u), (int)((meta >> 3) & 7u), g, pv);
+        constexpr int t0 = pg.T_lat;  // even
+        const float lodv = g == 0 ? (float)(meta >> 6) * lod_norm : 0.f;  // LOD input (section 4.4)
+        xw[t0 / 4] = cvt_e4m3x2(pv[0], pv[1], xw[t0 / 4], (t0 % 4) != 0);
+        xw[(t0 + 2) / 4] = cvt_e4m3x2(pv[2], lodv, xw[(t0 + 2) / 4], ((t0 + 2) % 4) != 0);
+      }
+      // ---- layer 1
+      uint32_t hw[SH / 4];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < S1 / 8; ++kk) {
+          const long b = (long)((uint64_t)xw[2 * kk] | (uint64_t)xw[2 * kk + 1] << 32);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(w1r[mo][kk], b, acc, 0, 0, 0);
+        }
+        hw[mo] = hidden_word(acc, sc1, b_lds, mo);
+      }
+      // ---- layer 2
+      uint32_t hw2[SH / 4];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < SH / 8; ++kk) {
+          const long b = (long)((uint64_t)hw[2 * kk] | (uint64_t)hw[2 * kk + 1] << 32);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(w2r[mo][kk], b, acc, 0, 0, 0);
+        }
+        hw2[mo] = hidden_word(acc, sc2, b_lds + HD, mo);
+      }
+      // ---- layer 3 (no activation)
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < SH / 8; ++kk) {
-        const long b = (long)((uint64_t)hw[2 * kk] | (uint64_t)hw[2 * kk + 1] << 32);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L2, SH, mo, kk), b, acc, 0, 0, 0);
+        const long b = (long)((uint64_t)hw2[2 * kk] | (uint64_t)hw2[2 * kk + 1] << 32);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(w3r[kk], b, acc, 0, 0, 0);
       }
-      hw2[mo] = hidden_word(acc, sc2, b_lds + HD, mo);
-    }
-    // ---- layer 3 (no activation)
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const f32x4 b3 = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
+      f32x4 y;
 #pragma unroll
-    for (int kk = 0; kk < SH / 8; ++kk) {
-      const long b = (long)((uint64_t)hw2[2 * kk] | (uint64_t)hw2[2 * kk + 1] << 32);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a_op(pg.L3, SH, 0, kk), b, acc, 0, 0, 0);
+      for (int i = 0; i < 4; ++i) y[i] = __builtin_fmaf(acc[i], sc3, b3[i]);
+      store_out<C>(out, out_f16, tile * 16 + r, n, g, y);
     }
-    const f32x4 b3 = *reinterpret_cast<const f32x4*>(b_lds + 2 * HD + 4 * g);
-    f32x4 y;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) y[i] = __builtin_fmaf(acc[i], sc3, b3[i]);
-    store_out<C>(out, out_f16, tile * 16 + r, n, g, y);
     cur = nxt;
+    __builtin_amdgcn_wave_barrier();  // this group's slab reads precede the next group's writes
   }
 }
 

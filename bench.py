@@ -41,35 +41,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("train.hip", "ntc_device.h", "ntc_internal.h")
+TRAIN_SOURCES = ("train.hip", "ntc_device.h", "ntc_internal.h")
+DECODE_SOURCES = ("decode.hip", "decode_impl.h", "ntc_device.h", "ntc_internal.h")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "train_fused_kernel_2048x12_counters.md")
+DECODE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_kernel_4096x16_counters.md")
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=TRAIN_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_2305_17105_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per launch of the FP16 fused training kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, each scaled by what the counter reads
-    for a plain copy of known size; None when the kernel sources changed since."""
+def counter_summary(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
+    """Figures of a committed rocprofv3 counter summary (key: value lines), or None when
+    the kernel sources changed since it was taken."""
     try:
         kv = {}
-        for line in open(COUNTERS_FILE):
-            if ":" in line and not line.startswith("#"):
+        for line in open(path):
+            if ":" in line and not line.startswith("#") and line.startswith("- "):
                 k, v = line.split(":", 1)
                 kv[k.strip().lstrip("- ").strip("`")] = v.strip().strip("`")
-        if kv.get("source_sha256") != kernel_source_hash():
+        if kv.get("source_sha256") != kernel_source_hash(sources):
             return None
+        return kv
+    except OSError:
+        return None
+
+
+def counter_traffic(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
+    """HBM bytes per launch of the profiled kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, each scaled by what the counter reads for a plain
+    copy of known size; None when the kernel sources changed since."""
+    kv = counter_summary(path, sources)
+    try:
         f = float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_scale"])
         w = float(kv["write_kib_per_launch"]) * float(kv["copy_write_scale"])
         return int(round((f + w) * 1024))
-    except (OSError, KeyError, ValueError):
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def counter_limiter(path, sources, launch_ms):
+    """Measured busy fractions of the profiled kernel from its committed SQ counters:
+    VALU issue (4 clocks per wave instruction) and matrix cores (16 clocks per 16x16x32
+    MFMA) over the launch's SIMD-cycles (256 CUs x 4 SIMDs x 2.4 GHz), and HBM bytes over
+    8 TB/s; None without a current summary."""
+    kv = counter_summary(path, sources)
+    try:
+        simd_cycles = 256 * 4 * 2.4e9 * launch_ms * 1e-3
+        out = dict(valu_busy=round(float(kv["valu_insts_per_launch"]) * 4 / simd_cycles, 3),
+                   mfma_busy=round(float(kv["mfma_insts_per_launch"]) * 16 / simd_cycles, 3))
+        tr = counter_traffic(path, sources)
+        if tr is not None:
+            out["hbm_frac"] = round(tr / (launch_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 3)
+        return out
+    except (TypeError, KeyError, ValueError):
         return None
 
 
@@ -279,6 +309,25 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
         res[f"psnr_mip0_{name}"] = round(-10.0 * math.log10(mse), 3)
     log(f"[bench] decode PSNR of mip 0: f32 {res['psnr_mip0_f32']} dB, f16 {res['psnr_mip0_f16']} dB, "
         f"fp8 {res['psnr_mip0_fp8']} dB")
+    # a seeded sample of mip-0 texels decoded by every path, kept for the comparison with
+    # the FP64 oracle (made in the CPU-baseline leg)
+    ns = ORACLE_SAMPLE
+    rs = np.random.default_rng(seed + 9)
+    idx = np.sort(rs.choice(n_tile, ns, replace=False))
+    qs = np.zeros(ns, dtype=[("u", "<f4"), ("v", "<f4"), ("lod", "<i4")])
+    qs["u"] = ((idx % d["W"]) + 0.5) / d["W"]
+    qs["v"] = ((idx // d["W"]) + 0.5) / d["W"]
+    qs_dev = torch.from_numpy(qs.view(np.uint8).copy()).cuda()
+    outs = {}
+    for name, prec in (("f32", ntc.F32), ("f16", ntc.F16), ("fp8", ntc.FP8_E4M3)):
+        wp = torch.zeros(ntc.mlp_packed_bytes(m, prec), dtype=torch.uint8, device="cuda")
+        ntc.pack_mlp(m, mlp, prec, wp)
+        o = torch.empty(ns * d["C"], dtype=torch.float32, device="cuda")
+        ntc.decode(m, packed, wp, prec, qs_dev, ns, o, ntc.F32)
+        outs[name] = o.cpu().numpy().astype(np.float64)
+    res["_oracle_sample"] = dict(queries=qs, packed=packed.cpu().numpy(), mlp=mlp.cpu().numpy().astype(np.float64),
+                                 targets=targets[:n_tile * d["C"]].view(n_tile, d["C"])[torch.from_numpy(idx).cuda()]
+                                 .cpu().numpy().astype(np.float64), outputs=outs)
     # filtered decode (FP16): the same random positions with a continuous LOD
     r = np.random.default_rng(seed + 6)
     fq = np.zeros(nq, dtype=[("u", "<f4"), ("v", "<f4"), ("lod", "<f4")])
@@ -307,6 +356,117 @@ def run_decode(ntc, synth, torch, nq, reps, seed=0):
                                           cost_vs_point_decode=round(ms / res["random_f16"]["ms"], 3))
         log(f"[bench] decode filtered {name} f16: {ms:.3f} ms for {nq} outputs ({taps} texels each) -> "
             f"{nq / (ms * 1e-3):.3e} outputs/s, {ms / res['random_f16']['ms']:.2f}x a point decode")
+    return res
+
+
+ORACLE_SAMPLE = 16384  # mip-0 texels decoded by the FP64 oracle beside each GPU decode path
+
+
+def _timed_ms(torch, call, reps):
+    for _ in range(2):
+        call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_small_configs(ntc, synth, torch, reps=20):
+    """The two small configurations on their own shapes: a 256^2 x 8 material (G0 64^2 x 8,
+    G1 32^2 x 8, 4-bit; MLP 52-64-64-8), 65,536 uniform queries at LOD 0.  Plain FP32
+    method: one training step (forward, loss, backward, Adam at lr 1e-2).  Differentiation
+    path: FP16 forward + backward through the torch.autograd.Function (L2 loss)."""
+    from paper_2305_17105_amd.autograd import ntc_decode_fn
+    W, C, n = 256, 8, 65536
+    m = ntc.material_init(W, W, C, C, C, 4, 4, 64, num_mips=1)
+    raw = torch.from_numpy(synth.uniform_latents(0, int(m.latent_count))).cuda()
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    ntc.quantize_latents(m, raw, packed)
+    lat = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+    ntc.dequantize_latents(m, packed, lat)
+    mlp = torch.from_numpy(synth.xavier_mlp(0, m.input_width, 64, C)).cuda()
+    _, tflat = synth.target_chain(0, 0, W, W, C, 1)
+    targets = torch.from_numpy(tflat).cuda()
+    q = torch.from_numpy(synth.random_queries(0, n, 1, 0).view(np.uint8).copy()).cuda()
+    st = ntc.TrainState(m, lat, mlp, ntc.F32)
+    ws = torch.zeros(ntc.train_workspace_bytes(m, n, ntc.F32), dtype=torch.uint8, device="cuda")
+    hp = ntc.hparams(lr_latent=1e-2, lr_mlp=1e-2, step=0, precision=ntc.F32, noise=False)
+    ntc.train_prepare(m, st, hp)
+    ms1 = _timed_ms(torch, lambda: ntc.train_step(m, st, q, n, targets, hp, ws), reps)
+    tq = targets.view(W * W, C)  # n = W * W: one target row per query
+
+    lat_p = lat.clone().requires_grad_(True)
+    mlp_p = mlp.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        y = ntc_decode_fn(m, lat_p, mlp_p, q, ntc.F16)
+        loss = ((y - tq) ** 2).mean()
+        loss.backward()
+    ms3 = _timed_ms(torch, fwd_bwd, reps)
+    out = {"config1_fp32_train_step": dict(material="256x256x8, G0 64^2x8 / G1 32^2x8 4-bit, MLP 52-64-64-8",
+                                           samples=n, ms=round(ms1, 4), samples_per_s=n / (ms1 * 1e-3)),
+           "config3_fp16_autograd_fwd_bwd": dict(material="as config 1", samples=n, ms=round(ms3, 4),
+                                                 samples_per_s=n / (ms3 * 1e-3))}
+    log(f"[bench] config 1 FP32 step: {ms1:.3f} ms ({n / (ms1 * 1e-3):.3e} samples/s); config 3 FP16 autograd "
+        f"forward+backward: {ms3:.3f} ms ({n / (ms3 * 1e-3):.3e} samples/s)")
+    return out
+
+
+def run_profile(ntc, synth, torch, steps, warmup, nq, reps, seed=21):
+    """Table 3's NTC 1.0 profile on the table's 4096^2 x 9 reference size with the paper's
+    network (hardGELU, LOD input, triangle-wave encoding): G0 2048^2 x 12 at 2 bits, G1
+    1024^2 x 10 at 4 bits.  FP16 training steps of 262,144 random samples, then FP16
+    decode of 16M random queries and of the full coherent mip 0."""
+    W, C = 4096, 9
+    m = ntc.material_init(W, W, C, 12, 10, 2, 4, 64, grid_shift=1, activation=ntc.ACT_HARDGELU, lod_input=1,
+                          posenc=ntc.PE_TRIANGLE)
+    targets = synth.target_chain_torch(seed, 2, W, W, C, int(m.num_mips), "cuda")
+    raw = torch.from_numpy(synth.uniform_latents(seed, int(m.latent_count))).cuda()
+    packed = torch.zeros(int(m.packed_bytes), dtype=torch.uint8, device="cuda")
+    ntc.quantize_latents(m, raw, packed)
+    lat = torch.zeros(int(m.latent_count), dtype=torch.float32, device="cuda")
+    ntc.dequantize_latents(m, packed, lat)
+    del raw
+    mlp = torch.from_numpy(synth.xavier_mlp(seed, m.input_width, 64, C)).cuda()
+    n = TRAIN["n"]
+    st = ntc.TrainState(m, lat, mlp, ntc.F16)
+    ws = torch.zeros(ntc.train_workspace_bytes(m, n, ntc.F16), dtype=torch.uint8, device="cuda")
+    pool = [torch.from_numpy(synth.random_queries(seed + 13 * i, n, m.num_mips).view(np.uint8).copy()).cuda()
+            for i in range(4)]
+    hps = [ntc.hparams(lr_latent=TRAIN["lr_lat"], lr_mlp=TRAIN["lr_mlp"], step=s, precision=ntc.F16, noise=True,
+                       seed=4) for s in range(warmup + steps)]
+    ntc.train_prepare(m, st, hps[0])
+    for s in range(warmup):
+        ntc.train_step(m, st, pool[s % 4], n, targets, hps[s], ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ntc.train_step(m, st, pool[(warmup + i) % 4], n, targets, hps[warmup + i], ws)
+    torch.cuda.synchronize()
+    tms = (time.perf_counter() - t0) / steps * 1e3
+    ntc.quantize_latents(m, st.latents, packed)
+    wp = torch.zeros(ntc.mlp_packed_bytes(m, ntc.F16), dtype=torch.uint8, device="cuda")
+    ntc.pack_mlp(m, st.mlp, ntc.F16, wp)
+    q = torch.from_numpy(synth.random_queries(seed + 5, nq, m.num_mips).view(np.uint8).copy()).cuda()
+    out = torch.empty(max(nq, W * W) * C, dtype=torch.float16, device="cuda")
+    ms_r = _timed_ms(torch, lambda: ntc.decode(m, packed, wp, ntc.F16, q, nq, out, ntc.F16), reps)
+    ms_c = _timed_ms(torch, lambda: ntc.decode_tile(m, packed, wp, ntc.F16, 0, 0, 0, W, W, out, ntc.F16), reps)
+    fq = decode_flops_per_query(m.input_width, 64, C)
+    res = dict(profile="NTC 1.0 (Table 3): 4096x4096x9, G0 2048^2 x 12 at 2 bits, G1 1024^2 x 10 at 4 bits, "
+                       "MLP 71-64-64-9 (hardGELU, LOD input, triangle waves)",
+               packed_mib=round(int(m.packed_bytes) / 2 ** 20, 3),
+               train_f16=dict(samples=n, ms_per_step=round(tms, 4), samples_per_s=n / (tms * 1e-3),
+                              steps=steps, loss=float(st.loss.cpu()[0])),
+               decode_random_f16=dict(queries=nq, ms=round(ms_r, 4), texels_per_s=nq / (ms_r * 1e-3),
+                                      tflops=fq * nq / (ms_r * 1e-3) / 1e12),
+               decode_coherent_f16=dict(queries=W * W, ms=round(ms_c, 4), texels_per_s=W * W / (ms_c * 1e-3),
+                                        tflops=fq * W * W / (ms_c * 1e-3) / 1e12))
+    log(f"[bench] NTC 1.0 profile 4096^2 x 9: train f16 {tms:.3f} ms/step ({n / (tms * 1e-3):.3e} samples/s); "
+        f"decode random f16 {ms_r:.3f} ms ({nq / (ms_r * 1e-3):.3e} texels/s), coherent mip 0 {ms_c:.3f} ms")
     return res
 
 
@@ -583,6 +743,33 @@ def cpu_baseline():
                 cpu=_cpu_model())
 
 
+def oracle_psnr(sample):
+    """PSNR (Eq. 1, peak 1) of a seeded sample of mip-0 texels of the decode material
+    against its targets: the FP64 oracle's decode of the same packed latents and weights,
+    and every GPU decode path's, with the delta and max-abs difference to the oracle."""
+    from oracle import ntc_oracle as O
+    d = DECODE
+    g = O.make_geometry(d["W"], d["W"], d["C"], d["c0"], d["c1"], d["b0"], d["b1"], Hd=d["hidden"])
+    lat = O.dequantize_packed(g, sample["packed"])
+    t0 = time.perf_counter()
+    ref = O.decode(g, lat, sample["mlp"], sample["queries"])
+    dt = time.perf_counter() - t0
+    t = sample["targets"]
+
+    def psnr(y):
+        return -10.0 * math.log10(float(np.mean((y.reshape(t.shape) - t) ** 2)))
+    p_or = psnr(ref)
+    out = dict(texels=len(sample["queries"]), oracle_psnr_db=round(p_or, 4), oracle_seconds=round(dt, 2))
+    for name, y in sample["outputs"].items():
+        p = psnr(y)
+        out[name] = dict(psnr_db=round(p, 4), delta_db=round(p - p_or, 4),
+                         max_abs_vs_oracle=float(np.max(np.abs(y.reshape(ref.shape) - ref))))
+    log(f"[bench] PSNR vs FP64 oracle on {len(t)} mip-0 texels: oracle {p_or:.3f} dB; " +
+        ", ".join(f"{k} {v['delta_db']:+.4f} dB (max-abs {v['max_abs_vs_oracle']:.2e})"
+                  for k, v in out.items() if isinstance(v, dict)))
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -605,6 +792,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-schedule", action="store_true")
     ap.add_argument("--paper-steps", type=int, default=1000)
+    ap.add_argument("--no-small", action="store_true", help="skip the two small configurations")
+    ap.add_argument("--no-profile", action="store_true", help="skip Table 3's NTC 1.0 profile at 4096^2 x 9")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -638,15 +827,42 @@ def main():
     m = tb.m
     fps = train_flops_per_sample(m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1)
     ach = fps * tb.n / (r16["fused_ms"] * 1e-3) / 1e12
+    # The roof of the kernel's algorithmic work is the FP16 matrix peak (its HBM bytes are
+    # far below the HBM roof); `limiter` gives the measured busy fractions of the VALU, the
+    # matrix cores and HBM from the committed counters of the same source.
     roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
                 unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4), traffic=counter_traffic(),
-                flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4))
+                flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4),
+                limiter=counter_limiter(COUNTERS_FILE, TRAIN_SOURCES, r16["fused_ms"]))
     ach32 = fps * tb.n / (r32["fused_ms"] * 1e-3) / 1e12
 
     decode = None
+    decode_roof = None
+    oracle_sample = None
     if not args.no_decode:
         decode = run_decode(ntc, synth, torch, args.decode_queries, args.decode_reps)
+        oracle_sample = decode.pop("_oracle_sample")
         decode["mixed_material"] = run_mixed(ntc, synth, torch)
+        d = DECODE
+        fq = decode_flops_per_query(d["c0"] * 4 + d["c1"] + 12, d["hidden"], d["C"])
+        kms = decode["random_f16"]["kernel_ms"]
+        achd = fq * args.decode_queries / (kms * 1e-3) / 1e12
+        decode_roof = dict(bound="mfma", kernel="decode_kernel (FP16, 4096^2 x 16, G0 2-bit / G1 4-bit, random)",
+                           achieved=round(achd, 2), peak=PEAK_F16_TFLOPS, unit="TFLOP/s",
+                           frac=round(achd / PEAK_F16_TFLOPS, 4),
+                           traffic=counter_traffic(DECODE_COUNTERS_FILE, DECODE_SOURCES), flops_per_query=fq,
+                           queries_per_launch=args.decode_queries, avg_launch_ms=kms,
+                           limiter=counter_limiter(DECODE_COUNTERS_FILE, DECODE_SOURCES, kms))
+        log(f"[bench] decode roofline (FP16 random): {achd:.1f} TFLOP/s = {achd / PEAK_F16_TFLOPS:.3f} of peak")
+
+    small = None
+    if not args.no_small:
+        small = run_small_configs(ntc, synth, torch)
+
+    profile = None
+    if not args.no_profile:
+        profile = run_profile(ntc, synth, torch, max(5, min(args.steps, 20)), 3, args.decode_queries,
+                              max(3, min(args.decode_reps, 10)))
 
     batched = None
     if not args.no_batched:
@@ -656,6 +872,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
         cpu = cpu_baseline()
+        if oracle_sample is not None:
+            cpu["decode_psnr_vs_oracle"] = oracle_psnr(oracle_sample)
 
     out = {
         "metric": "decoded texels/s + train samples/s (fwd+bwd), FP16 MFMA vs FP32 at stated PSNR",
@@ -675,6 +893,9 @@ def main():
         "fused_ms_f16": round(r16["fused_ms"], 4),
         "paper_schedule_f16": paper,
         "decode": decode,
+        "decode_roofline": decode_roof,
+        "small_configs": small,
+        "table3_profile": profile,
         "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -183,9 +183,12 @@ struct TrainCfg {
   // Owned-latent accumulators: fixed point, so a work item's sums do not depend on the
   // order of its adds (integer LDS adds also run 3x faster than FP64 ones and 25x faster
   // than FP32 ones on this GPU).  FP16 kernels: 32-bit (at 4 bytes a latent a 32 x 32 tile
-  // fits); FP32 kernels: 64-bit with a finer quantum.  A work item with a contribution
+  // fits); FP32 kernels: 64-bit with a finer quantum where a 16 x 16 tile of them fits,
+  // else 32-bit (8 x 8 tiles leave sparse level-0 tiles with a few samples per work item:
+  // 2.4x slower on the 16-channel hidden-64 shape).  A work item with a contribution
   // beyond the fixed-point range is summed again in FP32.
-  using AccI = typename std::conditional<sizeof(T) == 2, int, long long>::type;
+  static constexpr bool WIDE_FITS = OFF_REG + region(16) * 8 <= kLdsCap;
+  using AccI = typename std::conditional<sizeof(T) == 2 || !WIDE_FITS, int, long long>::type;
   static constexpr int RB = (int)sizeof(AccI);
   // largest tile side whose owned-latent gradient fits next to the rest
   static constexpr int TMAX = OFF_REG + region(32) * RB <= kLdsCap ? 32 : OFF_REG + region(16) * RB <= kLdsCap ? 16 : 8;

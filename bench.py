@@ -152,6 +152,10 @@ class TrainBench:
                                precision=precision, noise=True, seed=1)
 
         ntc.train_prepare(m, st, hp(0))
+        # (samples per work item, tile side) picked by timing the library's candidates on
+        # this batch; the tuner runs gradient passes only, the state is prepared afresh
+        chunk, tile, tune_us = ntc.train_autotune(m, st, self.pool[0], n, self.targets, hp(0), ws)
+        ntc.train_prepare(m, st, hp(0))
         for s in range(warmup):
             h = hp(s)
             ntc.train_step(m, st, self.pool[s % 8], n, self.targets, h, ws)
@@ -170,6 +174,7 @@ class TrainBench:
         fused_ms = ktot / kcnt
         loss = float(st.loss.cpu()[0])
         return dict(seconds=dt, ms_per_step=dt / steps * 1e3, samples_per_s=n * steps / dt, fused_ms=fused_ms,
+                    tuning=dict(chunk=chunk, tile=tile, us_per_gradient_pass=round(tune_us, 1)),
                     loss=loss, state=st)
 
     def run_paper_schedule(self, precision, steps, seed=3):
@@ -809,11 +814,13 @@ def main():
     tb = TrainBench(ntc, synth, torch)
     log("[bench] FP32 training run")
     r32 = tb.run(ntc.F32, args.steps, args.warmup)
-    log(f"[bench] f32: {r32['ms_per_step']:.3f} ms/step, fused {r32['fused_ms']:.3f} ms, loss {r32['loss']:.5f}")
+    log(f"[bench] f32: {r32['ms_per_step']:.3f} ms/step, fused {r32['fused_ms']:.3f} ms, loss {r32['loss']:.5f}, "
+        f"tuning {r32['tuning']}")
     psnr32 = tb.psnr(r32.pop("state"))
     log("[bench] FP16 training run")
     r16 = tb.run(ntc.F16, args.steps, args.warmup)
-    log(f"[bench] f16: {r16['ms_per_step']:.3f} ms/step, fused {r16['fused_ms']:.3f} ms, loss {r16['loss']:.5f}")
+    log(f"[bench] f16: {r16['ms_per_step']:.3f} ms/step, fused {r16['fused_ms']:.3f} ms, loss {r16['loss']:.5f}, "
+        f"tuning {r16['tuning']}")
     psnr16 = tb.psnr(r16.pop("state"))
     log(f"[bench] PSNR after {args.warmup + args.steps} steps: f16 {psnr16:.2f} dB, f32 {psnr32:.2f} dB")
 
@@ -889,8 +896,10 @@ def main():
         "psnr_db": {"f16": round(psnr16, 3), "f32": round(psnr32, 3), "steps_trained": args.warmup + args.steps},
         "fp32": {"value": round(r32["samples_per_s"], 1), "unit": "train samples/s",
                  "ms_per_step": round(r32["ms_per_step"], 4), "fused_ms": round(r32["fused_ms"], 4),
-                 "fused_tflops": round(ach32, 2), "fused_frac_of_fp32_peak": round(ach32 / PEAK_F32_TFLOPS, 4)},
+                 "fused_tflops": round(ach32, 2), "fused_frac_of_fp32_peak": round(ach32 / PEAK_F32_TFLOPS, 4),
+                 "tuning": r32["tuning"]},
         "fused_ms_f16": round(r16["fused_ms"], 4),
+        "tuning_f16": r16["tuning"],
         "paper_schedule_f16": paper,
         "decode": decode,
         "decode_roofline": decode_roof,

@@ -1243,19 +1243,26 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
   const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
   for (int k = bx * blockDim.x + threadIdx.x; k < RG; k += gx * blockDim.x) {
-    // four running sums, many loads in flight: tiles of the small levels have many items
+    // sixteen loads in flight per round into eight running sums (a fixed order): tiles of
+    // the small levels have tens to hundreds of items
     const float* src = part + (long long)it0 * region_max + k;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int i = 0;
-#pragma unroll 4
-    for (; i + 4 <= items; i += 4) {
-      s0 += src[(long long)i * region_max];
-      s1 += src[(long long)(i + 1) * region_max];
-      s2 += src[(long long)(i + 2) * region_max];
-      s3 += src[(long long)(i + 3) * region_max];
+    for (; i + 16 <= items; i += 16) {
+      float v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = src[(long long)(i + e) * region_max];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] += v[e] + v[e + 8];
     }
-    for (; i < items; ++i) s0 += src[(long long)i * region_max];
-    const float s = (s0 + s1) + (s2 + s3);
+    if (i < items) {  // ragged tail: absent items read as zero, same slots as a full round
+      float v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = i + e < items ? src[(long long)(i + e) * region_max] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] += v[e] + v[e + 8];
+    }
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     long long gi;
     if (k < R0) {
       const int c = k % C0, cell = k / C0, cx = cell % T, cy = cell / T;
@@ -1799,7 +1806,7 @@ TrainTune get_train_tune(const ntc_material& m, bool f16) {
   const TuneKey k = tune_key(m, f16);
   for (auto& r : tb.rows)
     if (r.first == k) return r.second;
-  return TrainTune{kChunkDefault, 0};
+  return TrainTune{0, 0};  // untuned: the plan's defaults
 }
 
 const TrainTune* train_tune_candidates(int* count) {

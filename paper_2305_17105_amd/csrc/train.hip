@@ -1275,12 +1275,26 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   }
 }
 
-// dscale: device (dout scale, output scale) overriding out_scale, or nullptr
+// Block (bx, y) takes region share bx of the split tiles among y, y + G, y + 2G, ...
+// (G = gridDim.y): each lane reads one candidate's item count, a ballot lists the split
+// ones, and the block walks that list, so blocks are not launched per tile (most tiles
+// are single items).  dscale: device (dout scale, output scale) overriding out_scale, or
+// nullptr.
 __global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
                                    const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
                                    float out_scale, const float* __restrict__ dscale) {
-  lat_partial_body(m, tg, item_base, part, region_max, lat_grad, dscale ? dscale[1] : out_scale, blockIdx.y,
-                   blockIdx.x, gridDim.x);
+  const float osc = dscale ? dscale[1] : out_scale;
+  const int G = gridDim.y, lane = threadIdx.x & 63;
+  for (int b0 = blockIdx.y; b0 < tg.ntiles; b0 += 64 * G) {
+    const int t = b0 + lane * G;
+    const bool split = t < tg.ntiles && item_base[t + 1] - item_base[t] > 1;
+    unsigned long long mask = __ballot(split);  // the same in every wavefront
+    while (mask) {
+      const int i = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      lat_partial_body(m, tg, item_base, part, region_max, lat_grad, osc, b0 + i * G, blockIdx.x, gridDim.x);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ weight-gradient reduction
@@ -1935,7 +1949,7 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   if (e != hipSuccess) return e;
   if (l.scatter_latents) {
     const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
-    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, p.ntiles), dim3(256), 0, s, dm, p.tg,
+    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, std::min(p.ntiles, 64)), dim3(256), 0, s, dm, p.tg,
                        (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad,
                        l.out_scale, l.dscale);
   }

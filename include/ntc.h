@@ -432,11 +432,13 @@ ntc_status ntc_decode_batched(const ntc_material* mats, int32_t nmat, const uint
                               const int64_t* offsets, void* out, ntc_dtype out_dtype, void* stream);
 
 /*
- * Grouped training: the batched step of ntc_train_step_batched with each stage that
- * is not the fused training kernel (binning, scans, partial-tile reduction,
- * weight-gradient reduction, Adam) run as one launch for the whole group instead of
- * one per material; the fused kernel still runs per material.  Every member needs
- * samples (offsets strictly increasing).
+ * Grouped training: the batched step of ntc_train_step_batched with each stage
+ * (binning, scans, partial-tile reduction, weight-gradient reduction, Adam) run as one
+ * launch for the whole group instead of one per material, and the fused training
+ * kernel as one launch per kernel shape (c0, c1, channels, hidden, activation), each
+ * member with the blocks and work-item shares of its own launch (the same sums, bit for
+ * bit).  At most 64 materials share a launch.  Every member needs samples (offsets
+ * strictly increasing).
  *   ntc_train_table_bytes: size of the device table for nmat materials.
  *   ntc_train_table_init: validates the group and writes the table into `table`
  *     (caller device memory): per material its geometry, training plan (tile shapes

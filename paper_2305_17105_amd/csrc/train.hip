@@ -199,11 +199,13 @@ struct TrainCfg {
 // `istride`, its weight-gradient partial written to row `row` of a.part_dw (and its
 // loss to a.part_loss[row]).  q: the material's queries (samples in query order when
 // !binned); scale_slot: the loss-scale slot when the step index is not on the device;
-// zero_flag: this block clears the overflow flag.  item1 < 0: all of a.nitems.
+// zero_flag: this block clears the overflow flag.  item1 < 0: all of a.nitems.  step_dev:
+// the device step index (its parity picks the loss-scale slot), or nullptr.
 template <typename T, int C0, int C1, int C, int HD, int ACT>
 __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, const TrainArgs& a,
-                                           const ntc_query* __restrict__ qs, int binned, int scale_slot, int item0,
-                                           int item1, int istride, int row, bool zero_flag) {
+                                           const ntc_query* __restrict__ qs, int binned, int scale_slot,
+                                           const int* step_dev, int item0, int item1, int istride, int row,
+                                           bool zero_flag) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
   using IS = typename Cfg::IS;
   constexpr PackGeom pg = Cfg::pg;
@@ -244,7 +246,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   if (zero_flag && tid == 0) *a.overflow_flag = 0;
   __syncthreads();
 
-  const int slot = a.step_dev ? (*a.step_dev & 1) : scale_slot;
+  const int slot = step_dev ? (*step_dev & 1) : scale_slot;
   const float scale = a.loss_scale ? a.loss_scale[slot] : 1.f;
   const float dout_scale = a.dscale ? a.dscale[0] : a.dout_scale;
   const float out_scale = a.dscale ? a.dscale[1] : a.out_scale;
@@ -851,8 +853,8 @@ __global__ __launch_bounds__((TrainCfg<T, C0, C1, C, HD>::NTHR),
                              (TrainCfg<T, C0, C1, C, HD>::NW * TrainCfg<T, C0, C1, C, HD>::BPC / 4)) void
 train_fused_kernel(DevMat m, PeTable pe, TrainArgs a) {
   if (a.table_hash && *a.table_hash != a.hash) return;  // grouped step against another table
-  fused_body<T, C0, C1, C, HD, ACT>(m, pe, a, a.q, a.binned, a.scale_slot, blockIdx.x, -1, gridDim.x, blockIdx.x,
-                                    blockIdx.x == 0);
+  fused_body<T, C0, C1, C, HD, ACT>(m, pe, a, a.q, a.binned, a.scale_slot, a.step_dev, blockIdx.x, -1, gridDim.x,
+                                    blockIdx.x, blockIdx.x == 0);
 }
 
 // ------------------------------------------------------------------ binning (counting sort)
@@ -1574,6 +1576,8 @@ __global__ void prepare_kernel(DevMat m, const float* __restrict__ lat, float* _
 struct TrainEntry {
   DevMat m;
   TileGeom tg;
+  TrainArgs fa;       // the fused pass (queries, step slot and binning come with each launch)
+  PeTable pe;
   BinArgs bin;        // q is unused: the launch's queries + q0
   AdamArgs adam;      // pointers; step-dependent scalars come with each launch
   long long q0, P;
@@ -1617,6 +1621,38 @@ __device__ inline const TrainEntry* group_member(const char* table, const TrainS
   bi = b - sg.block0[lo];
   nb = sg.block0[lo + 1] - sg.block0[lo];
   return reinterpret_cast<const TrainEntry*>(table + kGroupHeaderBytes) + sg.first + lo;
+}
+
+// The fused pass of the members of one kernel shape (at most kTrainGroup, any table
+// entries): member i takes blocks [block0[i], block0[i + 1]), as many as its own launch
+// would have, and each block runs the single-material body with the same share of the
+// member's work items, so the sums equal the member's own launch bit for bit.
+struct FusedSegs {
+  unsigned long long hash;
+  int count;
+  int mat[kTrainGroup];         // table entries of the members
+  int block0[kTrainGroup + 1];  // first block of each member; block0[count] = all blocks
+};
+
+template <typename T, int C0, int C1, int C, int HD, int ACT>
+__global__ __launch_bounds__((TrainCfg<T, C0, C1, C, HD>::NTHR),
+                             (TrainCfg<T, C0, C1, C, HD>::NW * TrainCfg<T, C0, C1, C, HD>::BPC / 4)) void
+train_fused_grouped(const char* __restrict__ table, FusedSegs sg, const ntc_query* __restrict__ q, int scale_slot,
+                    const int* __restrict__ step_dev, int binned) {
+  if (*reinterpret_cast<const unsigned long long*>(table) != sg.hash) return;
+  const int b = blockIdx.x;
+  int lo = 0, hi = sg.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sg.block0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int bi = b - sg.block0[lo], nb = sg.block0[lo + 1] - sg.block0[lo];
+  // through the constant address space: the entry's loads are invariant, so the compiler
+  // reloads fields rather than keeping them live (as it does with kernel arguments)
+  using CEntry = const __attribute__((address_space(4))) TrainEntry;
+  const TrainEntry& e = *(const TrainEntry*)((CEntry*)(table + kGroupHeaderBytes) + sg.mat[lo]);
+  fused_body<T, C0, C1, C, HD, ACT>(e.m, e.pe, e.fa, q + e.q0, binned, scale_slot, step_dev, bi, -1, nb, bi, bi == 0);
 }
 
 template <bool SCATTER>
@@ -2073,6 +2109,10 @@ void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets
     char* ws = (char*)fused[i].workspace;
     e.m = dev_mat(m);
     e.tg = p.tg;
+    e.fa = make_train_args(m, p, fused[i]);
+    e.fa.q = nullptr;
+    e.fa.table_hash = nullptr;
+    e.pe = pe_table(m);
     e.bin.q = nullptr;
     e.bin.n = g[i].n;
     e.bin.per_block = p.per_bin_block;
@@ -2134,6 +2174,63 @@ static hipError_t group_launch(int nmat, unsigned long long hash, Blocks&& block
   return hipSuccess;
 }
 
+template <typename T, int C0, int C1, int C, int HD, int ACT>
+static void fused_grouped_t(const char* tab, const FusedSegs& sg, int blocks, const ntc_query* q, int scale_slot,
+                            const int* step_dev, int binned, hipStream_t s) {
+  using Cfg = TrainCfg<T, C0, C1, C, HD>;
+  hipLaunchKernelGGL((train_fused_grouped<T, C0, C1, C, HD, ACT>), dim3(blocks), dim3(Cfg::NTHR), Cfg::LDS, s, tab,
+                     sg, q, scale_slot, step_dev, binned);
+}
+
+// One fused launch per kernel shape (c0, c1, channels, hidden, activation) and per
+// kTrainGroup members of it.
+static hipError_t launch_fused_grouped(const ntc_material* mats, int nmat, bool f16, const char* tab,
+                                       unsigned long long hash, const std::vector<GroupMember>& g, const ntc_query* q,
+                                       int scale_slot, const int* step_dev, int binned, hipStream_t s) {
+  std::vector<bool> done(nmat, false);
+  for (int i0 = 0; i0 < nmat; ++i0) {
+    if (done[i0]) continue;
+    const ntc_material& k = mats[i0];
+    std::vector<int> members;
+    for (int i = i0; i < nmat; ++i)
+      if (!done[i] && mats[i].c0 == k.c0 && mats[i].c1 == k.c1 && mats[i].channels == k.channels &&
+          mats[i].hidden == k.hidden && mats[i].activation == k.activation) {
+        members.push_back(i);
+        done[i] = true;
+      }
+    for (size_t f = 0; f < members.size(); f += kTrainGroup) {
+      FusedSegs sg{};
+      sg.hash = hash;
+      sg.count = (int)std::min<size_t>(kTrainGroup, members.size() - f);
+      int total = 0;
+      for (int i = 0; i < sg.count; ++i) {
+        sg.mat[i] = members[f + i];
+        sg.block0[i] = total;
+        total += g[members[f + i]].p.grid;
+      }
+      sg.block0[sg.count] = total;
+      bool found = false;
+#define NTC_X(a_, b_, cc, h)                                                                                \
+  if (k.c0 == a_ && k.c1 == b_ && k.channels == cc && k.hidden == h) {                                    \
+    found = true;                                                                                         \
+    if (f16) {                                                                                            \
+      if (k.activation) fused_grouped_t<_Float16, a_, b_, cc, h, 1>(tab, sg, total, q, scale_slot, step_dev, binned, s); \
+      else fused_grouped_t<_Float16, a_, b_, cc, h, 0>(tab, sg, total, q, scale_slot, step_dev, binned, s);  \
+    } else {                                                                                              \
+      if (k.activation) fused_grouped_t<float, a_, b_, cc, h, 1>(tab, sg, total, q, scale_slot, step_dev, binned, s); \
+      else fused_grouped_t<float, a_, b_, cc, h, 0>(tab, sg, total, q, scale_slot, step_dev, binned, s);     \
+    }                                                                                                     \
+  }
+      NTC_TRAIN_SHAPES(NTC_X)
+#undef NTC_X
+      if (!found) return hipErrorInvalidValue;
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_t* offsets, bool f16,
                                 const void* table, unsigned long long hash, const ntc_query* q, bool scatter,
                                 const TrainLaunch* fused, const AdamLaunch& hot, hipStream_t s) {
@@ -2156,12 +2253,9 @@ hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_
     run([&](int i) { return g[i].p.nbb; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<true>, dim3(n), dim3(kBinThreads), lds, s, tab, sg, q); });
   }
-  for (int i = 0; i < nmat && e == hipSuccess; ++i) {
-    TrainLaunch l = fused[i];
-    l.table_hash = reinterpret_cast<const unsigned long long*>(tab);
-    l.hash = hash;
-    e = launch_train_fused(mats[i], f16, g[i].p, l, s);
-  }
+  if (e == hipSuccess)
+    e = launch_fused_grouped(mats, nmat, f16, tab, hash, g, q, fused[0].scale_slot, fused[0].step_dev,
+                             scatter ? 1 : 0, s);
   if (scatter)
     run([&](int i) { return g[i].p.ntiles; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(lat_partial_grouped, dim3(n), dim3(256), 0, s, tab, sg); });

@@ -1244,27 +1244,7 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
   const int C0 = m.C0, C1 = m.C1;
   const int R0 = T * T * C0, RG = R0 + T1 * T1 * C1;
   const int w0 = m.W >> (m.shift + 2 * j), w1 = w0 >> 1;
-  for (int k = bx * blockDim.x + threadIdx.x; k < RG; k += gx * blockDim.x) {
-    // sixteen loads in flight per round into eight running sums (a fixed order): tiles of
-    // the small levels have tens to hundreds of items
-    const float* src = part + (long long)it0 * region_max + k;
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int i = 0;
-    for (; i + 16 <= items; i += 16) {
-      float v[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) v[e] = src[(long long)(i + e) * region_max];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc[e] += v[e] + v[e + 8];
-    }
-    if (i < items) {  // ragged tail: absent items read as zero, same slots as a full round
-      float v[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) v[e] = i + e < items ? src[(long long)(i + e) * region_max] : 0.f;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc[e] += v[e] + v[e + 8];
-    }
-    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  auto store = [&](int k, float s) {
     long long gi;
     if (k < R0) {
       const int c = k % C0, cell = k / C0, cx = cell % T, cy = cell / T;
@@ -1274,29 +1254,83 @@ __device__ __forceinline__ void lat_partial_body(const DevMat& m, const TileGeom
       gi = m.g1_off[j] + ((long long)(ty * T1 + cy) * w1 + tx * T1 + cx) * C1 + c;
     }
     lat_grad[gi] = s * out_scale;
+  };
+  // Item i of an element goes to running sum i & 3, in increasing i (a fixed order,
+  // whatever the grid); absent items and elements read as zero.  Sixteen loads in flight
+  // per round: sixteen items of one element when the grid has a thread per element,
+  // else four items of four elements (tiles of two or three items are the common case).
+  const int step = gx * blockDim.x;
+  const float* src = part + (long long)it0 * region_max;
+  if (RG <= step) {
+    const int k = bx * blockDim.x + threadIdx.x;
+    if (k >= RG) return;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < items; i += 16) {
+      float v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = i + e < items ? src[(long long)(i + e) * region_max + k] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e & 3] += v[e];
+    }
+    store(k, (acc[0] + acc[1]) + (acc[2] + acc[3]));
+    return;
+  }
+  for (int k0 = bx * blockDim.x + threadIdx.x; k0 < RG; k0 += 4 * step) {
+    float acc[4][4] = {};
+    for (int i = 0; i < items; i += 4) {
+      float v[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + q * step;
+          v[q][e] = (k < RG && i + e < items) ? src[(long long)(i + e) * region_max + k] : 0.f;
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[q][e] += v[q][e];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + q * step < RG) store(k0 + q * step, (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]));
   }
 }
 
-// Block (bx, y) takes region share bx of the split tiles among y, y + G, y + 2G, ...
-// (G = gridDim.y): each lane reads one candidate's item count, a ballot lists the split
-// ones, and the block walks that list, so blocks are not launched per tile (most tiles
-// are single items).  dscale: device (dout scale, output scale) overriding out_scale, or
-// nullptr.
-__global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
-                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
-                                   float out_scale, const float* __restrict__ dscale) {
-  const float osc = dscale ? dscale[1] : out_scale;
-  const int G = gridDim.y, lane = threadIdx.x & 63;
-  for (int b0 = blockIdx.y; b0 < tg.ntiles; b0 += 64 * G) {
+// Block (bx, y) of a gx x G grid takes region share bx of the split tiles among y, y + G,
+// y + 2G, ...: each lane reads one candidate's item count, a ballot lists the split ones,
+// and the block walks that list, so blocks are not launched per tile (most tiles are
+// single items).
+__device__ __forceinline__ void lat_partial_tiles(const DevMat& m, const TileGeom& tg,
+                                                  const int* __restrict__ item_base, const float* __restrict__ part,
+                                                  int region_max, float* __restrict__ lat_grad, float osc, int bx,
+                                                  int gx, int y, int G) {
+  const int lane = threadIdx.x & 63;
+  for (int b0 = y; b0 < tg.ntiles; b0 += 64 * G) {
     const int t = b0 + lane * G;
     const bool split = t < tg.ntiles && item_base[t + 1] - item_base[t] > 1;
     unsigned long long mask = __ballot(split);  // the same in every wavefront
     while (mask) {
       const int i = __builtin_ctzll(mask);
       mask &= mask - 1;
-      lat_partial_body(m, tg, item_base, part, region_max, lat_grad, osc, b0 + i * G, blockIdx.x, gridDim.x);
+      lat_partial_body(m, tg, item_base, part, region_max, lat_grad, osc, b0 + i * G, bx, gx);
     }
   }
+}
+
+// Region shares of a split-tile reduction (at least one, at most 64) and tile strides.
+__host__ __device__ inline int lat_partial_gx(int region_max) {
+  const int g = (region_max + 255) / 256;
+  return g < 1 ? 1 : (g > 64 ? 64 : g);
+}
+__host__ __device__ inline int lat_partial_ty(int ntiles) { return ntiles < 64 ? (ntiles < 1 ? 1 : ntiles) : 64; }
+
+// dscale: device (dout scale, output scale) overriding out_scale, or nullptr
+__global__ __launch_bounds__(256) void lat_partial_reduce(DevMat m, TileGeom tg, const int* __restrict__ item_base,
+                                   const float* __restrict__ part, int region_max, float* __restrict__ lat_grad,
+                                   float out_scale, const float* __restrict__ dscale) {
+  lat_partial_tiles(m, tg, item_base, part, region_max, lat_grad, dscale ? dscale[1] : out_scale, blockIdx.x,
+                    gridDim.x, blockIdx.y, gridDim.y);
 }
 
 // ------------------------------------------------------------------ weight-gradient reduction
@@ -1510,16 +1544,27 @@ __device__ __forceinline__ void adam_body(const DevMat& m, const AdamArgs& args,
     }
     return a.noise ? p + noise_at(next_key, i, bits) : p;
   };
-  // four consecutive latents per thread and iteration (16-byte accesses), then the tail
+  // four consecutive latents per thread and iteration (16-byte accesses), the next
+  // iteration's loads issued before this one's arithmetic and stores; then the tail
   const long long base = ((long long)bx - args.mlp_blocks) * 256 + threadIdx.x;
   const long long stride = ((long long)gx - args.mlp_blocks) * 256;
   const long long nv = L / 4;
+  f32x4 np, ngr, nmm, nvv;
+  if (base < nv) {
+    np = reinterpret_cast<const f32x4*>(a.latents)[base];
+    ngr = reinterpret_cast<const f32x4*>(a.lat_grad)[base];
+    nmm = reinterpret_cast<const f32x4*>(a.lat_m)[base];
+    nvv = reinterpret_cast<const f32x4*>(a.lat_v)[base];
+  }
   for (long long v4 = base; v4 < nv; v4 += stride) {
     const long long i = 4 * v4;
-    f32x4 p = reinterpret_cast<const f32x4*>(a.latents)[v4];
-    f32x4 gr = reinterpret_cast<const f32x4*>(a.lat_grad)[v4];
-    f32x4 mm = reinterpret_cast<const f32x4*>(a.lat_m)[v4];
-    f32x4 vv = reinterpret_cast<const f32x4*>(a.lat_v)[v4];
+    f32x4 p = np, gr = ngr, mm = nmm, vv = nvv;
+    if (v4 + stride < nv) {
+      np = reinterpret_cast<const f32x4*>(a.latents)[v4 + stride];
+      ngr = reinterpret_cast<const f32x4*>(a.lat_grad)[v4 + stride];
+      nmm = reinterpret_cast<const f32x4*>(a.lat_m)[v4 + stride];
+      nvv = reinterpret_cast<const f32x4*>(a.lat_v)[v4 + stride];
+    }
     f32x4 fw;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1677,6 +1722,8 @@ __global__ __launch_bounds__(1024) void bin_scan2_grouped(const char* __restrict
   if (e) bin_scan2_body(e->tg, e->total, e->base, e->tstart, e->ttotal, e->ibase, e->itile, e->nitems, s_base, s_scan);
 }
 
+// one block per tile of each member (a grid of gx x 64 per member, as for one material,
+// would reach hundreds of thousands of blocks on a many-material step)
 __global__ __launch_bounds__(256) void lat_partial_grouped(const char* __restrict__ table, TrainSegs sg) {
   int bi, nb;
   const TrainEntry* e = group_member(table, sg, bi, nb);
@@ -1984,8 +2031,8 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
   e = launch_train_fused(m, f16, p, l, s);
   if (e != hipSuccess) return e;
   if (l.scatter_latents) {
-    const int gx = std::max(1, std::min(64, (p.region_max + 255) / 256));
-    hipLaunchKernelGGL(lat_partial_reduce, dim3(gx, std::min(p.ntiles, 64)), dim3(256), 0, s, dm, p.tg,
+    hipLaunchKernelGGL(lat_partial_reduce, dim3(lat_partial_gx(p.region_max), lat_partial_ty(p.ntiles)), dim3(256), 0,
+                       s, dm, p.tg,
                        (const int*)(ws + p.off_ibase), (const float*)(ws + p.off_part_lat), p.region_max, l.lat_grad,
                        l.out_scale, l.dscale);
   }

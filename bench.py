@@ -56,9 +56,10 @@ def kernel_source_hash(sources=TRAIN_SOURCES):
     return h.hexdigest()
 
 
-def counter_summary(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
+def counter_summary(path=COUNTERS_FILE, sources=TRAIN_SOURCES, plan=None):
     """Figures of a committed rocprofv3 counter summary (key: value lines), or None when
-    the kernel sources changed since it was taken."""
+    the kernel sources changed since it was taken, or when it was taken with another
+    training plan (samples per work item, tile side) than `plan`."""
     try:
         kv = {}
         for line in open(path):
@@ -67,16 +68,22 @@ def counter_summary(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
                 kv[k.strip().lstrip("- ").strip("`")] = v.strip().strip("`")
         if kv.get("source_sha256") != kernel_source_hash(sources):
             return None
+        if plan is not None and kv.get("plan") != plan_text(plan):
+            return None
         return kv
     except OSError:
         return None
 
 
-def counter_traffic(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
+def plan_text(plan):
+    return f"chunk {plan['chunk']}, tile {plan['tile']}"
+
+
+def counter_traffic(path=COUNTERS_FILE, sources=TRAIN_SOURCES, plan=None):
     """HBM bytes per launch of the profiled kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, each scaled by what the counter reads for a plain
-    copy of known size; None when the kernel sources changed since."""
-    kv = counter_summary(path, sources)
+    copy of known size; None when the kernel sources (or the plan) changed since."""
+    kv = counter_summary(path, sources, plan)
     try:
         f = float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_scale"])
         w = float(kv["write_kib_per_launch"]) * float(kv["copy_write_scale"])
@@ -85,17 +92,17 @@ def counter_traffic(path=COUNTERS_FILE, sources=TRAIN_SOURCES):
         return None
 
 
-def counter_limiter(path, sources, launch_ms):
+def counter_limiter(path, sources, launch_ms, plan=None):
     """Measured busy fractions of the profiled kernel from its committed SQ counters:
     VALU issue (4 clocks per wave instruction) and matrix cores (16 clocks per 16x16x32
     MFMA) over the launch's SIMD-cycles (256 CUs x 4 SIMDs x 2.4 GHz), and HBM bytes over
     8 TB/s; None without a current summary."""
-    kv = counter_summary(path, sources)
+    kv = counter_summary(path, sources, plan)
     try:
         simd_cycles = 256 * 4 * 2.4e9 * launch_ms * 1e-3
         out = dict(valu_busy=round(float(kv["valu_insts_per_launch"]) * 4 / simd_cycles, 3),
                    mfma_busy=round(float(kv["mfma_insts_per_launch"]) * 16 / simd_cycles, 3))
-        tr = counter_traffic(path, sources)
+        tr = counter_traffic(path, sources, plan)
         if tr is not None:
             out["hbm_frac"] = round(tr / (launch_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 3)
         return out
@@ -139,7 +146,7 @@ class TrainBench:
                      .cuda() for i in range(8)]
         self.n = t["n"]
 
-    def run(self, precision, steps, warmup):
+    def run(self, precision, steps, warmup, tune=True):
         ntc, torch = self.ntc, self.torch
         m, n = self.m, self.n
         st = ntc.TrainState(m, self.lat0, self.mlp0, precision)
@@ -154,8 +161,11 @@ class TrainBench:
         ntc.train_prepare(m, st, hp(0))
         # (samples per work item, tile side) picked by timing the library's candidates on
         # this batch; the tuner runs gradient passes only, the state is prepared afresh
-        chunk, tile, tune_us = ntc.train_autotune(m, st, self.pool[0], n, self.targets, hp(0), ws)
-        ntc.train_prepare(m, st, hp(0))
+        if tune:
+            chunk, tile, tune_us = ntc.train_autotune(m, st, self.pool[0], n, self.targets, hp(0), ws)
+            ntc.train_prepare(m, st, hp(0))
+        else:
+            (chunk, tile), tune_us = ntc.train_get_tuning(m, precision), 0.0
         for s in range(warmup):
             h = hp(s)
             ntc.train_step(m, st, self.pool[s % 8], n, self.targets, h, ws)
@@ -560,11 +570,19 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
     for s in range(warmup):
         ntc.train_step_grouped(table, qpool[s % 2], hp)
     torch.cuda.synchronize()
+    # the library's HIP events around the fused launches (one per kernel shape) give the
+    # fused part of the eager steps
+    ntc.timing_begin(64 * steps)
     t1 = time.perf_counter()
     for s in range(steps):
         ntc.train_step_grouped(table, qpool[s % 2], hp)
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t1) / steps * 1e3
+    fused_tot, fused_cnt = ntc.timing_read("train_fused")
+    ntc.timing_end()
+    fused_step_ms = fused_tot / steps
+    step_flop = sum(float(offsets[i + 1] - offsets[i]) * train_flops_per_sample(
+        m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1) for i, m in enumerate(mats))
     graphs = []
     stream = torch.cuda.Stream()
     for k in range(2):
@@ -583,8 +601,9 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
     graph_ms = (time.perf_counter() - t1) / steps * 1e3
     loss = float(np.mean([float(st.loss.cpu()[0]) for st in states]))
     log(f"[bench] batched train: per-material launches {per_material_ms:.3f} ms/step, grouped eager "
-        f"{eager_ms:.3f} ms/step, grouped graph replay {graph_ms:.3f} ms/step -> "
-        f"{ntot / (graph_ms * 1e-3):.3e} samples/s, mean loss {loss:.5f}, step index {int(step_dev.item())}")
+        f"{eager_ms:.3f} ms/step (fused launches {fused_step_ms:.3f} ms in {fused_cnt // steps} launches), grouped "
+        f"graph replay {graph_ms:.3f} ms/step -> {ntot / (graph_ms * 1e-3):.3e} samples/s, mean loss {loss:.5f}, "
+        f"step index {int(step_dev.item())}")
     del graphs, table, ws
 
     # decode: random queries proportional to area in one batched call; coherent mip 0
@@ -645,6 +664,10 @@ def run_batched(ntc, synth, torch, steps, warmup, seed=7):
                 train_ms_per_step_graph=round(graph_ms, 4), train_ms_per_step_eager=round(eager_ms, 4),
                 train_ms_per_step_per_material_launches=round(per_material_ms, 4),
                 train_samples_per_s=ntot / (graph_ms * 1e-3), mean_loss=loss, tuned_tiles=tuned,
+                train_fused_ms_per_step_eager=round(fused_step_ms, 4), fused_launches_per_step=fused_cnt // steps,
+                train_flop_per_step=step_flop,
+                fused_mfma_frac=round(step_flop / (fused_step_ms * 1e-3) / (PEAK_F16_TFLOPS * 1e12), 4),
+                step_mfma_frac=round(step_flop / (graph_ms * 1e-3) / (PEAK_F16_TFLOPS * 1e12), 4),
                 decode_random=dict(queries=nd, ms=round(dec_ms, 4), texels_per_s=nd / (dec_ms * 1e-3),
                                    launches=sum(1 for n in dq if n > 0)),
                 decode_random_grouped=dict(queries=nd, ms=round(grp_ms, 4), texels_per_s=nd / (grp_ms * 1e-3),
@@ -795,6 +818,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="train the benchmark material with its untuned plan (profiling runs)")
     ap.add_argument("--no-paper-schedule", action="store_true")
     ap.add_argument("--paper-steps", type=int, default=1000)
     ap.add_argument("--no-small", action="store_true", help="skip the two small configurations")
@@ -813,12 +838,12 @@ def main():
 
     tb = TrainBench(ntc, synth, torch)
     log("[bench] FP32 training run")
-    r32 = tb.run(ntc.F32, args.steps, args.warmup)
+    r32 = tb.run(ntc.F32, args.steps, args.warmup, tune=not args.no_tune)
     log(f"[bench] f32: {r32['ms_per_step']:.3f} ms/step, fused {r32['fused_ms']:.3f} ms, loss {r32['loss']:.5f}, "
         f"tuning {r32['tuning']}")
     psnr32 = tb.psnr(r32.pop("state"))
     log("[bench] FP16 training run")
-    r16 = tb.run(ntc.F16, args.steps, args.warmup)
+    r16 = tb.run(ntc.F16, args.steps, args.warmup, tune=not args.no_tune)
     log(f"[bench] f16: {r16['ms_per_step']:.3f} ms/step, fused {r16['fused_ms']:.3f} ms, loss {r16['loss']:.5f}, "
         f"tuning {r16['tuning']}")
     psnr16 = tb.psnr(r16.pop("state"))
@@ -838,9 +863,10 @@ def main():
     # far below the HBM roof); `limiter` gives the measured busy fractions of the VALU, the
     # matrix cores and HBM from the committed counters of the same source.
     roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
-                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4), traffic=counter_traffic(),
+                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4),
+                traffic=counter_traffic(COUNTERS_FILE, TRAIN_SOURCES, r16["tuning"]),
                 flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4),
-                limiter=counter_limiter(COUNTERS_FILE, TRAIN_SOURCES, r16["fused_ms"]))
+                limiter=counter_limiter(COUNTERS_FILE, TRAIN_SOURCES, r16["fused_ms"], r16["tuning"]))
     ach32 = fps * tb.n / (r32["fused_ms"] * 1e-3) / 1e12
 
     decode = None

@@ -2225,8 +2225,10 @@ template <typename T, int C0, int C1, int C, int HD, int ACT>
 static void fused_grouped_t(const char* tab, const FusedSegs& sg, int blocks, const ntc_query* q, int scale_slot,
                             const int* step_dev, int binned, hipStream_t s) {
   using Cfg = TrainCfg<T, C0, C1, C, HD>;
+  const int slot = timing_before(TK_TRAIN_FUSED, s);
   hipLaunchKernelGGL((train_fused_grouped<T, C0, C1, C, HD, ACT>), dim3(blocks), dim3(Cfg::NTHR), Cfg::LDS, s, tab,
                      sg, q, scale_slot, step_dev, binned);
+  timing_after(TK_TRAIN_FUSED, s, slot);
 }
 
 // One fused launch per kernel shape (c0, c1, channels, hidden, activation) and per

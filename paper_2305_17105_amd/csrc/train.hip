@@ -244,6 +244,10 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   }
   if (tid < 16) tab[16 + tid] = m.mip_off[tid];
   if (zero_flag && tid == 0) *a.overflow_flag = 0;
+  // the owned-latent accumulators start at zero; every work item's write-out clears what
+  // it read, so they are zero again at the next item whatever its tile size
+  for (int k = tid; k < Cfg::region(Cfg::TMAX) * (int)sizeof(AccI) / 16; k += NTHR)
+    reinterpret_cast<int4*>(ireg)[k] = int4{0, 0, 0, 0};
   __syncthreads();
 
   const int slot = step_dev ? (*step_dev & 1) : scale_slot;
@@ -354,10 +358,10 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     for (int pass = 0; pass < 2; ++pass) {
     const bool refine = pass == 1;
     refined = refine;
-    if (binned) {
+    if (refine) {  // block-uniform: the FP32 pass starts from zeros (pass 0 found them so)
       for (int k = tid; k < RG; k += NTHR) ireg[k] = (AccI)0;
+      __syncthreads();
     }
-    __syncthreads();
     float nu, nv;
     int nlod;
     long long ns;
@@ -758,22 +762,28 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
             f32x4 val;
             if (refined) {
               val = *reinterpret_cast<const f32x4*>(freg + k);
+              *reinterpret_cast<int4*>(freg + k) = int4{0, 0, 0, 0};
             } else if constexpr (WIDE) {
               const longlong2 lo = *reinterpret_cast<const longlong2*>(ireg + k);
               const longlong2 hi = *reinterpret_cast<const longlong2*>(ireg + k + 2);
+              *reinterpret_cast<longlong2*>(ireg + k) = longlong2{0, 0};
+              *reinterpret_cast<longlong2*>(ireg + k + 2) = longlong2{0, 0};
               const double fi = (double)fixinv;
               val = f32x4{(float)((double)lo.x * fi), (float)((double)lo.y * fi), (float)((double)hi.x * fi),
                           (float)((double)hi.y * fi)};
             } else {
               const int4 iv = *reinterpret_cast<const int4*>(ireg + k);
+              *reinterpret_cast<int4*>(ireg + k) = int4{0, 0, 0, 0};
               val = f32x4{(float)iv.x * fixinv, (float)iv.y * fixinv, (float)iv.z * fixinv, (float)iv.w * fixinv};
             }
             *reinterpret_cast<f32x4*>(dst + gbase + y * gstride + o) = val * osc;
           }
         } else {
           for (int i = tid; i < rows * L; i += NTHR) {
-            const int y = i / L, o = i - y * L;
-            dst[gbase + y * gstride + o] = reg_value(k0 + y * L + o) * osc;
+            const int y = i / L, o = i - y * L, k = k0 + y * L + o;
+            dst[gbase + y * gstride + o] = reg_value(k) * osc;
+            if (refined) freg[k] = 0.f;  // the bytes this thread read
+            else ireg[k] = (AccI)0;
           }
         }
       };

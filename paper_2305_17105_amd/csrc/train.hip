@@ -159,7 +159,8 @@ struct TrainCfg {
   static constexpr int OFF_BIAS = OFF_PE + 48 * 4;
   static constexpr int OFF_TAB = OFF_BIAS + (2 * HD + 16) * 4;  // g0_off[8], g1_off[8], mip_off[16]
   static constexpr int OFF_RED = OFF_TAB + 32 * 8;
-  static constexpr int OFF_BUF = (OFF_RED + 4 * NW + 15) / 16 * 16;
+  static constexpr int OFF_FLAG = OFF_RED + 4 * NW;  // two ints: the lost flags of alternate items
+  static constexpr int OFF_BUF = (OFF_FLAG + 8 + 15) / 16 * 16;
   static constexpr int region(int t) { return t * t * C0 + (t / 2) * (t / 2) * C1; }
   static constexpr int kLdsCap = 160 * 1024 / BPC;
   static constexpr int buf_bytes(int rows) { return (rows * RS * (int)sizeof(T) + 15) / 16 * 16; }
@@ -217,6 +218,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   float* b_lds = reinterpret_cast<float*>(smem + Cfg::OFF_BIAS);
   long long* tab = reinterpret_cast<long long*>(smem + Cfg::OFF_TAB);
   float* red = reinterpret_cast<float*>(smem + Cfg::OFF_RED);
+  int* lost_flag = reinterpret_cast<int*>(smem + Cfg::OFF_FLAG);
   T* buf = reinterpret_cast<T*>(smem + Cfg::OFF_BUF);
   using AccI = typename Cfg::AccI;
   constexpr bool WIDE = sizeof(AccI) == 8;
@@ -244,6 +246,7 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
   }
   if (tid < 16) tab[16 + tid] = m.mip_off[tid];
   if (zero_flag && tid == 0) *a.overflow_flag = 0;
+  if (tid < 2) lost_flag[tid] = 0;
   // the owned-latent accumulators start at zero; every work item's write-out clears what
   // it read, so they are zero again at the next item whatever its tile size
   for (int k = tid; k < Cfg::region(Cfg::TMAX) * (int)sizeof(AccI) / 16; k += NTHR)
@@ -304,7 +307,8 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
     else atomicAdd(ireg + k, v);
   };
   const int nitems = item1 >= 0 ? item1 : binned ? *a.nitems : (int)((a.n + chunk_n - 1) / chunk_n);
-  for (int item = item0; item < nitems; item += istride) {
+  int par = 0;  // parity of this block's work items: which lost flag is theirs
+  for (int item = item0; item < nitems; item += istride, par ^= 1) {
     // ---------------- work item -> (tile, sample range)
     int j = 0, tx = 0, ty = 0, T_ = 2, cnt;
     long long start;
@@ -601,6 +605,9 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       }
 
       if (refine) continue;  // block-uniform
+      // a lost contribution anywhere in the item: published by the last step's staging
+      // barriers (every staging mode has at least one after its stores)
+      if (binned && lost && t0 + NCOL >= cnt) lost_flag[par] = 1;
       // ---------------- weight gradients through LDS (texels become the K axis);
       // only a sample's primary copy contributes.  Column wave*16 + r holds texel r of
       // wave `wave`.  Bias gradients are row sums of the deltas: thread (row = tid / PARTS,
@@ -731,9 +738,15 @@ __device__ __forceinline__ void fused_body(const DevMat& m, const PeTable& pe, c
       }
     }
 
-    if (binned && !refine && __syncthreads_or(lost)) {
-      lost = false;
-      continue;
+    if (binned && !refine) {
+      const bool again = lost_flag[par] != 0;  // read after the last staging barrier
+      // the next item's flag: its last reads were before this item's barriers, its next
+      // writes come after this item's write-out barrier
+      if (tid == 0) lost_flag[par ^ 1] = 0;
+      if (again) {  // block-uniform
+        lost = false;
+        continue;
+      }
     }
     // the refine pass has no staging barriers: its adds must land before the write-out
     if (refine) __syncthreads();

@@ -889,8 +889,70 @@ struct BinArgs {
   int* counts;         // [nbins][nbb]
   const int* offsets;  // [nbins][nbb], relative to the bin base
   const int* base;     // [nbins + 1]
+  const int* total;    // scatter: the bin totals, scanned by every block (or nullptr: base)
   int4* list;
 };
+
+// Exclusive scan over the 1024 threads of a block (wavefront scans by shuffles, then
+// the 16 wavefront totals); `total` receives the sum.  sh: 33 ints of LDS.
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int t = lane < 16 ? sh[lane] : 0;
+    int ti = t;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const int o = __shfl_up(ti, d, 64);
+      if (lane >= d) ti += o;
+    }
+    if (lane < 16) sh[16 + lane] = ti - t;
+    if (lane == 15) sh[32] = ti;
+  }
+  __syncthreads();
+  const int r = sh[16 + w] + incl - v;
+  total = sh[32];
+  __syncthreads();  // sh is reused by the next scan
+  return r;
+}
+
+// Exclusive scan of the bin totals by a block of 1024 threads: s_base[b] (and base[b] when
+// base is given) = the list position of bin b's first entry, s_base[nb] = the list length.
+__device__ __forceinline__ void bin_base_scan(int nb, const int* __restrict__ total, int* __restrict__ base,
+                                              int* s_base, int* s_scan) {
+  constexpr int kPer = kMaxBins / 1024;
+  const int tid = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(nb, tid * per);
+  int tv[kPer];
+  int st = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    tv[e] = (e < per && b0 + e < nb) ? total[b0 + e] : 0;
+    st += tv[e];
+  }
+  int all;
+  int pt = block_exclusive_scan(st, s_scan, all);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    if (e < per && b0 + e < nb) {
+      s_base[b0 + e] = pt;
+      if (base) base[b0 + e] = pt;
+      pt += tv[e];
+    }
+  }
+  if (tid == 0) {
+    s_base[nb] = all;
+    if (base) base[nb] = all;
+  }
+}
 
 // Bins of one sample: the sort bins of the tiles its footprint touches (at most 4,
 // all different), -1 in the unused entries.
@@ -911,10 +973,23 @@ __device__ inline void sample_bin_list(const DevMat& m, const TileGeom& tg, cons
 template <bool SCATTER>
 __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, const BinArgs& a,
                                          const ntc_query* __restrict__ q, int bi) {
-  extern __shared__ int hist[];
+  extern __shared__ int hist[];  // nbins + 1 ints
   const int nb = tg.nbins;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    hist[b] = SCATTER ? a.base[b] + a.offsets[(long long)b * a.nbb + bi] : 0;
+  if constexpr (SCATTER) {
+    // running list position of each bin in this block: the bin's base plus the entries of
+    // earlier blocks; hist[nb] = the list length
+    if (a.total) {  // block-uniform: the bases from the totals, in this block
+      __shared__ int s_scan[1024];
+      bin_base_scan(nb, a.total, nullptr, hist, s_scan);
+      __syncthreads();
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] += a.offsets[(long long)b * a.nbb + bi];
+    } else {
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = a.base[b] + a.offsets[(long long)b * a.nbb + bi];
+      if (threadIdx.x == 0) hist[nb] = a.base[nb];
+    }
+  } else {
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+  }
   __syncthreads();
   const long long s0 = (long long)bi * a.per_block;
   const long long s1 = min(a.n, s0 + a.per_block);
@@ -958,7 +1033,7 @@ __device__ __forceinline__ void bin_body(const DevMat& m, const TileGeom& tg, co
     __shared__ uint32_t wsum[16][8], wpre[16][8], wtot[8];
     __shared__ int wmax[16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int list_len = a.base[nb];
+    const int list_len = hist[nb];
     for (long long r0 = s0; r0 < s1; r0 += kBinThreads) {
       const long long sk = r0 + t;
       int v[4];
@@ -1130,36 +1205,6 @@ __global__ __launch_bounds__(256) void bin_scan1_kernel(int nbins, int nbb, cons
 // positions), then per tile its start, total and work items (at most tg.chunk samples
 // per item, at least one), the exclusive scan of the items over the tiles, and the tile
 // of every item.
-// Exclusive scan over the 1024 threads of a block (wavefront scans by shuffles, then
-// the 16 wavefront totals); `total` receives the sum.  sh: 33 ints of LDS.
-__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int o = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += o;
-  }
-  if (lane == 63) sh[w] = incl;
-  __syncthreads();
-  if (w == 0) {
-    const int t = lane < 16 ? sh[lane] : 0;
-    int ti = t;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-      const int o = __shfl_up(ti, d, 64);
-      if (lane >= d) ti += o;
-    }
-    if (lane < 16) sh[16 + lane] = ti - t;
-    if (lane == 15) sh[32] = ti;
-  }
-  __syncthreads();
-  const int r = sh[16 + w] + incl - v;
-  total = sh[32];
-  __syncthreads();  // sh is reused by the next scan
-  return r;
-}
-
 __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __restrict__ total,
                                                int* __restrict__ base, int* __restrict__ tile_start,
                                                int* __restrict__ tile_total, int* __restrict__ item_base,
@@ -1168,31 +1213,7 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
   constexpr int kPer = kMaxBins / 1024;
   const int tid = threadIdx.x;
   const int nb = tg.nbins, nt = tg.ntiles;
-  {
-    const int per = (nb + 1023) / 1024;
-    const int b0 = min(nb, tid * per);
-    int tv[kPer];
-    int st = 0;
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      tv[e] = (e < per && b0 + e < nb) ? total[b0 + e] : 0;
-      st += tv[e];
-    }
-    int all;
-    int pt = block_exclusive_scan(st, s_scan, all);
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      if (e < per && b0 + e < nb) {
-        s_base[b0 + e] = pt;
-        base[b0 + e] = pt;
-        pt += tv[e];
-      }
-    }
-    if (tid == 0) {
-      s_base[nb] = all;
-      base[nb] = all;
-    }
-  }
+  bin_base_scan(nb, total, base, s_base, s_scan);
   __syncthreads();
   {
     const int per = (nt + 1023) / 1024;
@@ -1243,13 +1264,26 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
   }
 }
 
-__global__ __launch_bounds__(1024) void bin_scan2_kernel(TileGeom tg, const int* __restrict__ total,
-                                                         int* __restrict__ base, int* __restrict__ tile_start,
-                                                         int* __restrict__ tile_total, int* __restrict__ item_base,
-                                                         int* __restrict__ item_tile, int* __restrict__ nitems) {
-  __shared__ int s_base[kMaxBins + 1];
-  __shared__ int s_scan[1024];
-  bin_scan2_body(tg, total, base, tile_start, tile_total, item_base, item_tile, nitems, s_base, s_scan);
+// The scatter pass with the tile tables beside it: blocks 0 .. nbb-1 scatter (each scans
+// the bin totals itself), block nbb writes the per-tile starts, totals and work items
+// (the one-block scan), so neither waits for the other.
+struct TileTables {
+  int* base;
+  int* tile_start;
+  int* tile_total;
+  int* item_base;
+  int* item_tile;
+  int* nitems;
+};
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(DevMat m, TileGeom tg, BinArgs a, TileTables o) {
+  if ((int)blockIdx.x == a.nbb) {
+    extern __shared__ int s_base[];  // nbins + 1 ints
+    __shared__ int s_scan[1024];
+    bin_scan2_body(tg, a.total, o.base, o.tile_start, o.tile_total, o.item_base, o.item_tile, o.nitems, s_base,
+                   s_scan);
+    return;
+  }
+  bin_body<true>(m, tg, a, a.q, blockIdx.x);
 }
 
 // Latent gradients of tiles split over several work items: partials summed in a fixed order.
@@ -2040,14 +2074,20 @@ hipError_t launch_train_gradients(const ntc_material& m, bool f16, const TrainPl
     b.offsets = (const int*)(ws + p.off_offsets);
     b.base = (const int*)(ws + p.off_base);
     b.list = (int4*)(ws + p.off_list);
-    const size_t lds = (size_t)p.nbins * 4;
+    b.total = nullptr;
+    const size_t lds = (size_t)(p.nbins + 1) * 4;
     hipLaunchKernelGGL(bin_kernel<false>, dim3(p.nbb), dim3(kBinThreads), lds, s, dm, p.tg, b);
     hipLaunchKernelGGL(bin_scan1_kernel, dim3((p.nbins + 3) / 4), dim3(256), 0, s, p.nbins, p.nbb,
                        (const int*)(ws + p.off_counts), (int*)(ws + p.off_offsets), (int*)(ws + p.off_total));
-    hipLaunchKernelGGL(bin_scan2_kernel, dim3(1), dim3(1024), 0, s, p.tg, (const int*)(ws + p.off_total),
-                       (int*)(ws + p.off_base), (int*)(ws + p.off_tstart), (int*)(ws + p.off_ttotal),
-                       (int*)(ws + p.off_ibase), (int*)(ws + p.off_itile), (int*)(ws + p.off_misc));
-    hipLaunchKernelGGL(bin_kernel<true>, dim3(p.nbb), dim3(kBinThreads), lds, s, dm, p.tg, b);
+    b.total = (const int*)(ws + p.off_total);
+    TileTables o;
+    o.base = (int*)(ws + p.off_base);
+    o.tile_start = (int*)(ws + p.off_tstart);
+    o.tile_total = (int*)(ws + p.off_ttotal);
+    o.item_base = (int*)(ws + p.off_ibase);
+    o.item_tile = (int*)(ws + p.off_itile);
+    o.nitems = (int*)(ws + p.off_misc);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(p.nbb + 1), dim3(kBinThreads), lds, s, dm, p.tg, b, o);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -2191,6 +2231,7 @@ void fill_train_table(const ntc_material* mats, int nmat, const int64_t* offsets
     e.bin.offsets = (const int*)(ws + p.off_offsets);
     e.bin.base = (const int*)(ws + p.off_base);
     e.bin.list = (int4*)(ws + p.off_list);
+    e.bin.total = nullptr;  // the grouped step scans the bases in its own launch
     e.adam.a = adam[i];
     e.adam.a.mlp_grad = (const float*)(ws + p.off_grad);
     e.adam.pg = pack_geom(m.c0, m.c1, m.hidden, f16);
@@ -2315,7 +2356,7 @@ hipError_t launch_train_grouped(const ntc_material* mats, int nmat, const int64_
     if (e == hipSuccess) e = group_launch(nmat, hash, blocks, launch);
   };
   if (scatter) {
-    const size_t lds = (size_t)max_bins * 4;
+    const size_t lds = (size_t)(max_bins + 1) * 4;
     run([&](int i) { return g[i].p.nbb; },
         [&](const TrainSegs& sg, int n) { hipLaunchKernelGGL(bin_grouped<false>, dim3(n), dim3(kBinThreads), lds, s, tab, sg, q); });
     run([&](int i) { return (g[i].p.nbins + 3) / 4; },

@@ -859,13 +859,26 @@ def main():
     m = tb.m
     fps = train_flops_per_sample(m.input_width, m.hidden, m.channels, 4 * m.c0 + m.c1)
     ach = fps * tb.n / (r16["fused_ms"] * 1e-3) / 1e12
-    # The roof of the kernel's algorithmic work is the FP16 matrix peak (its HBM bytes are
-    # far below the HBM roof); `limiter` gives the measured busy fractions of the VALU, the
-    # matrix cores and HBM from the committed counters of the same source.
-    roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
-                unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4),
-                traffic=counter_traffic(COUNTERS_FILE, TRAIN_SOURCES, r16["tuning"]),
-                flops_per_sample=fps, samples_per_launch=tb.n, avg_launch_ms=round(r16["fused_ms"], 4),
+    # Algorithmic HBM bytes of a launch: the queries (12 B), FP32 targets, one read of the
+    # FP32 forward latents and one write of the FP32 latent gradient.  The bound is the roof
+    # whose floor is the longer (matrix work at the FP16 peak, or these bytes at 8 TB/s: the
+    # two are within 10% here); `limiter` gives the measured busy fractions of the VALU,
+    # the matrix cores and HBM from the committed counters of the same source.
+    abytes = tb.n * (12 + 4 * m.channels) + 2 * 4 * int(m.latent_count)
+    t_mfma = fps * tb.n / (PEAK_F16_TFLOPS * 1e12)
+    t_hbm = abytes / (PEAK_HBM_GBS * 1e9)
+    hbm_ach = abytes / (r16["fused_ms"] * 1e-3) / 1e9
+    if t_hbm > t_mfma:
+        roof = dict(bound="hbm", kernel="train_fused_kernel (FP16)", achieved=round(hbm_ach, 1), peak=PEAK_HBM_GBS,
+                    unit="GB/s", frac=round(hbm_ach / PEAK_HBM_GBS, 4))
+    else:
+        roof = dict(bound="mfma", kernel="train_fused_kernel (FP16)", achieved=round(ach, 2), peak=PEAK_F16_TFLOPS,
+                    unit="TFLOP/s", frac=round(ach / PEAK_F16_TFLOPS, 4))
+    roof.update(traffic=counter_traffic(COUNTERS_FILE, TRAIN_SOURCES, r16["tuning"]),
+                algorithmic_bytes=abytes, flops_per_sample=fps, samples_per_launch=tb.n,
+                avg_launch_ms=round(r16["fused_ms"], 4), mfma_tflops=round(ach, 2),
+                mfma_frac=round(ach / PEAK_F16_TFLOPS, 4), hbm_frac_algorithmic=round(hbm_ach / PEAK_HBM_GBS, 4),
+                floor_us=dict(mfma=round(t_mfma * 1e6, 2), hbm=round(t_hbm * 1e6, 2)),
                 limiter=counter_limiter(COUNTERS_FILE, TRAIN_SOURCES, r16["fused_ms"], r16["tuning"]))
     ach32 = fps * tb.n / (r32["fused_ms"] * 1e-3) / 1e12
 

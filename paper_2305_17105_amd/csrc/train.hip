@@ -927,26 +927,17 @@ __device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
 // base is given) = the list position of bin b's first entry, s_base[nb] = the list length.
 __device__ __forceinline__ void bin_base_scan(int nb, const int* __restrict__ total, int* __restrict__ base,
                                               int* s_base, int* s_scan) {
-  constexpr int kPer = kMaxBins / 1024;
   const int tid = threadIdx.x;
   const int per = (nb + 1023) / 1024;
-  const int b0 = min(nb, tid * per);
-  int tv[kPer];
+  const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
   int st = 0;
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    tv[e] = (e < per && b0 + e < nb) ? total[b0 + e] : 0;
-    st += tv[e];
-  }
+  for (int b = b0; b < b1; ++b) st += total[b];
   int all;
   int pt = block_exclusive_scan(st, s_scan, all);
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    if (e < per && b0 + e < nb) {
-      s_base[b0 + e] = pt;
-      if (base) base[b0 + e] = pt;
-      pt += tv[e];
-    }
+  for (int b = b0; b < b1; ++b) {  // the totals again (cached): no register array per thread
+    s_base[b] = pt;
+    if (base) base[b] = pt;
+    pt += total[b];
   }
   if (tid == 0) {
     s_base[nb] = all;
@@ -1210,41 +1201,31 @@ __device__ __forceinline__ void bin_scan2_body(const TileGeom& tg, const int* __
                                                int* __restrict__ tile_total, int* __restrict__ item_base,
                                                int* __restrict__ item_tile, int* __restrict__ nitems, int* s_base,
                                                int* s_scan) {
-  constexpr int kPer = kMaxBins / 1024;
   const int tid = threadIdx.x;
   const int nb = tg.nbins, nt = tg.ntiles;
   bin_base_scan(nb, total, base, s_base, s_scan);
   __syncthreads();
   {
     const int per = (nt + 1023) / 1024;
-    const int t0 = min(nt, tid * per);
+    const int t0 = min(nt, tid * per), t1 = min(nt, t0 + per);
+    auto tile_items = [&](int tot) { return max(1, (tot + tg.chunk - 1) / tg.chunk); };
     int items = 0;
-    int tk[kPer];
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      tk[e] = 0;
-      const int t = t0 + e;
-      if (e < per && t < nt) {
-        int j = 0;
-        while (j + 1 < kMaxLevels && t >= tg.tile_base[j + 1]) ++j;
-        const int first = tg.bin_base[j] + (t - tg.tile_base[j]) * tg.sb[j] * tg.sb[j];
-        const int st = s_base[first];
-        const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
-        tile_start[t] = st;
-        tile_total[t] = tot;
-        tk[e] = max(1, (tot + tg.chunk - 1) / tg.chunk);
-        items += tk[e];
-      }
+    for (int t = t0; t < t1; ++t) {
+      int j = 0;
+      while (j + 1 < kMaxLevels && t >= tg.tile_base[j + 1]) ++j;
+      const int first = tg.bin_base[j] + (t - tg.tile_base[j]) * tg.sb[j] * tg.sb[j];
+      const int st = s_base[first];
+      const int tot = s_base[first + tg.sb[j] * tg.sb[j]] - st;
+      tile_start[t] = st;
+      tile_total[t] = tot;
+      items += tile_items(tot);
     }
     int all;
     int pi = block_exclusive_scan(items, s_scan, all);  // every s_base read above precedes its barriers
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      if (e < per && t0 + e < nt) {
-        item_base[t0 + e] = pi;
-        s_base[t0 + e] = pi;  // first item of each tile, for the item -> tile search
-        pi += tk[e];
-      }
+    for (int t = t0; t < t1; ++t) {  // this thread's own totals, read back: no register array
+      item_base[t] = pi;
+      s_base[t] = pi;  // first item of each tile, for the item -> tile search
+      pi += tile_items(tile_total[t]);
     }
     if (tid == 0) {
       item_base[nt] = all;
@@ -1275,7 +1256,7 @@ struct TileTables {
   int* item_tile;
   int* nitems;
 };
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(DevMat m, TileGeom tg, BinArgs a, TileTables o) {
+__global__ __launch_bounds__(kBinThreads, 8) void bin_scatter_kernel(DevMat m, TileGeom tg, BinArgs a, TileTables o) {
   if ((int)blockIdx.x == a.nbb) {
     extern __shared__ int s_base[];  // nbins + 1 ints
     __shared__ int s_scan[1024];

@@ -1739,7 +1739,7 @@ train_fused_grouped(const char* __restrict__ table, FusedSegs sg, const ntc_quer
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(kBinThreads) void bin_grouped(const char* __restrict__ table, TrainSegs sg,
+__global__ __launch_bounds__(kBinThreads, 8) void bin_grouped(const char* __restrict__ table, TrainSegs sg,
                                                    const ntc_query* __restrict__ q) {
   int bi, nb;
   const TrainEntry* e = group_member(table, sg, bi, nb);

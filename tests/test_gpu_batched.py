@@ -328,6 +328,16 @@ def test_grouped_train_more_members_than_one_launch(lib):
     _assert_states_equal(sb, sg)
 
 
+def test_grouped_train_more_members_of_one_shape_than_one_fused_launch(lib):
+    """65 materials of one kernel shape, interleaved with 5 of another: the fused pass of
+    the first shape needs two launches (64 members each at most), the stage launches two
+    as well; grouped equals batched."""
+    mats = [_material(lib, 64, 8, 32 if i % 17 else 64, 600 + i) for i in range(70)]
+    ns = [150 + 29 * (i % 7) for i in range(70)]
+    sb, sg = _grouped_vs_batched(lib, lib.F16, mats, ns, 610)
+    _assert_states_equal(sb, sg)
+
+
 def test_grouped_train_table_of_other_group_does_nothing(lib):
     """A table built for other sample groups: the step leaves every state as it was."""
     import torch
